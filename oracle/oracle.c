@@ -1,0 +1,419 @@
+/*
+ * oracle.c — TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU reference for the top-k weighted triangle problem
+ * of Kumar, Liu, Charikar and Benson, "Retrieving Top Weighted Triangles in Graphs"
+ * (WSDM 2020).  Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code with the GPU library.
+ *
+ * What it computes
+ *   - Problem statement (Sec. 1): G = (V, E, w) simple, undirected, positive weights; the
+ *     weight of triangle (i,j,l) is the generalized p-mean of its three edge weights
+ *     (Eq. 1), with the limits p = 0 (geometric mean), p = +inf (max), p = -inf (min)
+ *     named in Sec. 1.  The answer is the k heaviest triangles.
+ *   - Ties (the paper gives no rule): order by score descending, then by the original
+ *     vertex IDs (i, j, l) ascending, with i < j < l.
+ *   - Fewer than k triangles: all of them are returned (Sec. 3.2 assumes at least k).
+ *   - Enumeration: every triangle exactly once, as (i<j<l) in original IDs, by walking each
+ *     edge (i,j) with i<j and intersecting the sorted neighbour lists of i and j above j.
+ *   - Selection: one bounded heap of the k best per thread, then a full sort of the union
+ *     of the heaps, the brute-force-with-a-heap scheme of Sec. 3 ("maintain a heap of the
+ *     top-weighted triangles").  The result is by construction the first k of the total
+ *     order above.
+ *   - Weighted edge sampling (Alg. 3, Prop. 1): t independent draws of an edge with
+ *     probability w_e^q / Z, by inverse CDF over the edges in input order; the result
+ *     set is the union over the draws of every triangle on the drawn edge, i.e. every
+ *     triangle that has at least one drawn edge.  The uniform draws come from SplitMix64
+ *     (Steele, Lea, Flood, OOPSLA 2014) so the GPU can replay the same sequence.
+ *
+ * Scoring.  For p in {-inf, 0, 1, 2, +inf} the order is decided by an exact integer key
+ * (min, product, sum, sum of squares, max), a monotone transform of m_p.  For any other p
+ * the key is the FP64 value of m_p, evaluated in long double as
+ *     m = s * exp( log1p( (1/3) sum_x expm1(p * log(x/s)) ) / p ),
+ * s = max weight for p > 0 and min weight for p < 0, which is Eq. 1 rewritten so that no
+ * power overflows and small |p| loses no digits.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#include <omp.h>
+
+typedef unsigned __int128 u128;
+
+enum {
+    O_OK = 0, O_E_ARG = -1, O_E_SELF_LOOP = -2, O_E_DUP_EDGE = -3, O_E_ZERO_WEIGHT = -4,
+    O_E_VERTEX_RANGE = -5, O_E_NOMEM = -6
+};
+enum { MODE_MAX = 0, MODE_MIN = 1, MODE_SUM = 2, MODE_SUMSQ = 3, MODE_PROD = 4, MODE_GEN = 5 };
+enum { FILTER_NONE = 0, FILTER_EDGE_MARK = 1, FILTER_VERTEX_MARK = 2 };
+
+/* ------------------------------------------------------------------ scoring (Eq. 1) */
+
+int orc_mode(double p) {
+    if (isinf(p)) return p > 0 ? MODE_MAX : MODE_MIN;
+    if (p == 1.0) return MODE_SUM;
+    if (p == 2.0) return MODE_SUMSQ;
+    if (p == 0.0) return MODE_PROD;
+    return MODE_GEN;
+}
+
+static long double gen_mean(long double p, uint32_t a, uint32_t b, uint32_t c) {
+    long double x[3] = {(long double)a, (long double)b, (long double)c};
+    long double mx = x[0], mn = x[0];
+    for (int t = 1; t < 3; t++) { if (x[t] > mx) mx = x[t]; if (x[t] < mn) mn = x[t]; }
+    long double s = p > 0 ? mx : mn;
+    long double acc = 0.0L;
+    for (int t = 0; t < 3; t++) acc += expm1l(p * logl(x[t] / s));
+    return s * expl(log1pl(acc / 3.0L) / p);
+}
+
+/* Exact order key (or FP64 bits for a generic p) and FP64 score of one triangle. */
+static void score3(int mode, double p, uint32_t a, uint32_t b, uint32_t c, u128 *key, double *score) {
+    switch (mode) {
+    case MODE_MAX: { uint32_t v = a > b ? a : b; v = v > c ? v : c; *key = v; *score = (double)v; break; }
+    case MODE_MIN: { uint32_t v = a < b ? a : b; v = v < c ? v : c; *key = v; *score = (double)v; break; }
+    case MODE_SUM: { uint64_t s = (uint64_t)a + b + c; *key = s; *score = (double)s / 3.0; break; }
+    case MODE_SUMSQ: {
+        u128 s = (u128)a * a + (u128)b * b + (u128)c * c;
+        *key = s;
+        *score = (double)sqrtl((long double)s / 3.0L);
+        break;
+    }
+    case MODE_PROD: {
+        u128 s = (u128)a * b * c;
+        *key = s;
+        *score = (double)cbrtl((long double)s);
+        break;
+    }
+    default: {
+        double d = (double)gen_mean((long double)p, a, b, c);
+        uint64_t bits;
+        memcpy(&bits, &d, 8);
+        *key = bits; /* positive doubles order like their bit patterns */
+        *score = d;
+        break;
+    }
+    }
+}
+
+double orc_score(double p, uint32_t a, uint32_t b, uint32_t c, uint64_t *key_hi, uint64_t *key_lo) {
+    u128 k; double s;
+    score3(orc_mode(p), p, a, b, c, &k, &s);
+    if (key_hi) *key_hi = (uint64_t)(k >> 64);
+    if (key_lo) *key_lo = (uint64_t)k;
+    return s;
+}
+
+/* ------------------------------------------------------------------ graph */
+
+typedef struct { uint32_t nbr, w; uint64_t eid; } ent_t;
+typedef struct { uint64_t n, m; uint64_t *rp; ent_t *e; } adj_t;
+
+static int cmp_ent(const void *x, const void *y) {
+    const ent_t *a = (const ent_t *)x, *b = (const ent_t *)y;
+    return a->nbr < b->nbr ? -1 : a->nbr > b->nbr ? 1 : 0;
+}
+
+/* Validation order: vertex range, self-loop, zero weight, duplicate pair. */
+static int check_edges(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w) {
+    int range = 0, loop = 0, zero = 0;
+    for (uint64_t e = 0; e < m; e++) {
+        if (src[e] >= n || dst[e] >= n) range = 1;
+        else if (src[e] == dst[e]) loop = 1;
+        if (w[e] == 0) zero = 1;
+    }
+    if (range) return O_E_VERTEX_RANGE;
+    if (loop) return O_E_SELF_LOOP;
+    if (zero) return O_E_ZERO_WEIGHT;
+    return O_OK;
+}
+
+static void adj_free(adj_t *g) { free(g->rp); free(g->e); g->rp = NULL; g->e = NULL; }
+
+/* Symmetric adjacency with rows sorted by neighbour ID; detects duplicate pairs. */
+static int adj_build(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w, adj_t *g) {
+    int rc = check_edges(n, m, src, dst, w);
+    if (rc) return rc;
+    g->n = n; g->m = m;
+    g->rp = (uint64_t *)calloc(n + 1, sizeof(uint64_t));
+    g->e = (ent_t *)malloc((2 * m + 1) * sizeof(ent_t));
+    if (!g->rp || !g->e) { adj_free(g); return O_E_NOMEM; }
+    for (uint64_t e = 0; e < m; e++) { g->rp[src[e] + 1]++; g->rp[dst[e] + 1]++; }
+    for (uint64_t v = 0; v < n; v++) g->rp[v + 1] += g->rp[v];
+    uint64_t *cur = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
+    if (!cur) { adj_free(g); return O_E_NOMEM; }
+    memcpy(cur, g->rp, (n + 1) * sizeof(uint64_t));
+    for (uint64_t e = 0; e < m; e++) {
+        ent_t a = {dst[e], w[e], e}, b = {src[e], w[e], e};
+        g->e[cur[src[e]]++] = a;
+        g->e[cur[dst[e]]++] = b;
+    }
+    free(cur);
+    int dup = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(| : dup)
+    for (uint64_t v = 0; v < n; v++) {
+        uint64_t lo = g->rp[v], hi = g->rp[v + 1];
+        qsort(g->e + lo, hi - lo, sizeof(ent_t), cmp_ent);
+        for (uint64_t t = lo + 1; t < hi; t++)
+            if (g->e[t].nbr == g->e[t - 1].nbr) dup = 1;
+    }
+    if (dup) { adj_free(g); return O_E_DUP_EDGE; }
+    return O_OK;
+}
+
+int orc_validate(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w) {
+    if (m && (!src || !dst || !w)) return O_E_ARG;
+    adj_t g = {0};
+    int rc = adj_build(n, m, src, dst, w, &g);
+    adj_free(&g);
+    return rc;
+}
+
+/* First index in row [lo, hi) whose neighbour is > x. */
+static uint64_t first_above(const ent_t *e, uint64_t lo, uint64_t hi, uint32_t x) {
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (e[mid].nbr > x) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+/*
+ * Calls visit(ctx, tid, i, j, l, w_ij, w_il, w_jl, e_ij, e_il, e_jl) once per triangle
+ * i < j < l, in parallel over i.
+ */
+typedef void (*visit_fn)(void *, int, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
+                         uint64_t, uint64_t, uint64_t);
+
+static void enumerate(const adj_t *g, visit_fn visit, void *ctx) {
+    const ent_t *E = g->e;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (uint64_t i = 0; i < g->n; i++) {
+        const int tid = omp_get_thread_num();
+        const uint64_t ilo = g->rp[i], ihi = g->rp[i + 1];
+        for (uint64_t a = first_above(E, ilo, ihi, (uint32_t)i); a < ihi; a++) {
+            const uint32_t j = E[a].nbr;
+            /* N(i) above j, N(j) above j */
+            uint64_t x = a + 1, y = first_above(E, g->rp[j], g->rp[j + 1], j);
+            const uint64_t yhi = g->rp[j + 1];
+            while (x < ihi && y < yhi) {
+                if (E[x].nbr < E[y].nbr) x++;
+                else if (E[x].nbr > E[y].nbr) y++;
+                else {
+                    visit(ctx, tid, (uint32_t)i, j, E[x].nbr, E[a].w, E[x].w, E[y].w, E[a].eid, E[x].eid, E[y].eid);
+                    x++; y++;
+                }
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ top-k with heaps */
+
+typedef struct { u128 key; uint32_t i, j, l; double score; } rec_t;
+
+/* 1 if a ranks before b: larger key first, then smaller (i, j, l). */
+static inline int better(const rec_t *a, const rec_t *b) {
+    if (a->key != b->key) return a->key > b->key;
+    if (a->i != b->i) return a->i < b->i;
+    if (a->j != b->j) return a->j < b->j;
+    return a->l < b->l;
+}
+static int cmp_rec(const void *x, const void *y) {
+    const rec_t *a = (const rec_t *)x, *b = (const rec_t *)y;
+    return better(a, b) ? -1 : better(b, a) ? 1 : 0;
+}
+
+typedef struct { rec_t *h; uint64_t size; uint64_t count; char pad[40]; } heap_t;
+
+/* heap root = the worst record kept */
+static void heap_push(heap_t *H, uint64_t k, const rec_t *r) {
+    rec_t *h = H->h;
+    if (H->size < k) {
+        uint64_t c = H->size++;
+        h[c] = *r;
+        while (c > 0) {
+            uint64_t p = (c - 1) / 2;
+            if (better(&h[p], &h[c])) { rec_t t = h[p]; h[p] = h[c]; h[c] = t; c = p; } else break;
+        }
+    } else if (better(r, &h[0])) {
+        h[0] = *r;
+        uint64_t c = 0;
+        for (;;) {
+            uint64_t l = 2 * c + 1, rr = l + 1, worst = c;
+            if (l < k && better(&h[worst], &h[l])) worst = l;
+            if (rr < k && better(&h[worst], &h[rr])) worst = rr;
+            if (worst == c) break;
+            rec_t t = h[c]; h[c] = h[worst]; h[worst] = t; c = worst;
+        }
+    }
+}
+
+typedef struct {
+    int mode; double p; uint64_t k;
+    heap_t *heaps;
+    int filter; const uint8_t *mark;
+} topk_ctx;
+
+static void visit_topk(void *vctx, int tid, uint32_t i, uint32_t j, uint32_t l, uint32_t wij, uint32_t wil,
+                       uint32_t wjl, uint64_t eij, uint64_t eil, uint64_t ejl) {
+    topk_ctx *c = (topk_ctx *)vctx;
+    if (c->filter == FILTER_EDGE_MARK && !(c->mark[eij] | c->mark[eil] | c->mark[ejl])) return;
+    if (c->filter == FILTER_VERTEX_MARK && !(c->mark[i] | c->mark[j] | c->mark[l])) return;
+    rec_t r;
+    score3(c->mode, c->p, wij, wil, wjl, &r.key, &r.score);
+    r.i = i; r.j = j; r.l = l;
+    heap_t *H = &c->heaps[tid];
+    H->count++;
+    if (c->k) heap_push(H, c->k, &r);
+}
+
+/*
+ * Top-k triangles by (score desc, i, j, l).  Writes min(k, T) records; *t_total = T (the
+ * number of triangles admitted by the filter).  filter: 0 none; 1 mark[] over input edge
+ * IDs (a triangle is admitted if one of its edges is marked); 2 mark[] over vertices.
+ */
+int orc_topk(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w, uint64_t k,
+             double p, int nthreads, int filter, const uint8_t *mark, uint32_t *oi, uint32_t *oj, uint32_t *ol,
+             double *oscore, uint64_t *okey_hi, uint64_t *okey_lo, uint64_t *n_out, uint64_t *t_total) {
+    if (n_out) *n_out = 0;
+    if (isnan(p) || (m && (!src || !dst || !w)) || (filter && !mark) || !n_out) return O_E_ARG;
+    if (k && (!oi || !oj || !ol || !oscore)) return O_E_ARG;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    adj_t g = {0};
+    int rc = adj_build(n, m, src, dst, w, &g);
+    if (rc) return rc;
+    const int T = omp_get_max_threads();
+    heap_t *heaps = (heap_t *)calloc(T, sizeof(heap_t));
+    if (!heaps) { adj_free(&g); return O_E_NOMEM; }
+    for (int t = 0; t < T; t++) {
+        heaps[t].h = (rec_t *)malloc((k ? k : 1) * sizeof(rec_t));
+        if (!heaps[t].h) { for (int u = 0; u < T; u++) free(heaps[u].h); free(heaps); adj_free(&g); return O_E_NOMEM; }
+    }
+    topk_ctx ctx = {orc_mode(p), p, k, heaps, filter, mark};
+    enumerate(&g, visit_topk, &ctx);
+    uint64_t total = 0, kept = 0;
+    for (int t = 0; t < T; t++) { total += heaps[t].count; kept += heaps[t].size; }
+    rec_t *all = (rec_t *)malloc((kept ? kept : 1) * sizeof(rec_t));
+    if (!all) { for (int u = 0; u < T; u++) free(heaps[u].h); free(heaps); adj_free(&g); return O_E_NOMEM; }
+    uint64_t pos = 0;
+    for (int t = 0; t < T; t++) { memcpy(all + pos, heaps[t].h, heaps[t].size * sizeof(rec_t)); pos += heaps[t].size; }
+    qsort(all, kept, sizeof(rec_t), cmp_rec);
+    uint64_t out = kept < k ? kept : k;
+    for (uint64_t r = 0; r < out; r++) {
+        oi[r] = all[r].i; oj[r] = all[r].j; ol[r] = all[r].l; oscore[r] = all[r].score;
+        if (okey_hi) okey_hi[r] = (uint64_t)(all[r].key >> 64);
+        if (okey_lo) okey_lo[r] = (uint64_t)all[r].key;
+    }
+    *n_out = out;
+    if (t_total) *t_total = total;
+    free(all);
+    for (int t = 0; t < T; t++) free(heaps[t].h);
+    free(heaps);
+    adj_free(&g);
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ listing (small graphs) */
+
+typedef struct { uint32_t *i, *j, *l, *w3; uint64_t cap, cnt; } list_ctx;
+
+static void visit_list(void *vctx, int tid, uint32_t i, uint32_t j, uint32_t l, uint32_t wij, uint32_t wil,
+                       uint32_t wjl, uint64_t eij, uint64_t eil, uint64_t ejl) {
+    (void)tid; (void)eij; (void)eil; (void)ejl;
+    list_ctx *c = (list_ctx *)vctx;
+    uint64_t pos;
+#pragma omp atomic capture
+    pos = c->cnt++;
+    if (pos < c->cap) {
+        c->i[pos] = i; c->j[pos] = j; c->l[pos] = l;
+        c->w3[3 * pos] = wij; c->w3[3 * pos + 1] = wil; c->w3[3 * pos + 2] = wjl;
+    }
+}
+
+/* Every triangle (unordered), with its weights (w_ij, w_il, w_jl).  *cnt = T. */
+int orc_list(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w, uint64_t cap,
+             uint32_t *oi, uint32_t *oj, uint32_t *ol, uint32_t *ow3, uint64_t *cnt) {
+    if (!cnt || (m && (!src || !dst || !w)) || (cap && (!oi || !oj || !ol || !ow3))) return O_E_ARG;
+    adj_t g = {0};
+    int rc = adj_build(n, m, src, dst, w, &g);
+    if (rc) return rc;
+    list_ctx c = {oi, oj, ol, ow3, cap, 0};
+    enumerate(&g, visit_list, &c);
+    *cnt = c.cnt;
+    adj_free(&g);
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ weighted edge sampling */
+
+/* i-th output (0-based) of SplitMix64 started from state `seed`. */
+static inline uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Sampling exponent: q = p for finite p > 0, else 1. */
+double orc_sample_exponent(double p) { return (isfinite(p) && p > 0.0) ? p : 1.0; }
+
+/*
+ * Alg. 3's draws: `budget` iid edges with P(e) = w_e^q / Z, by inverse CDF over the input
+ * order.  Integer q in {1, 2, 3}: exact 128-bit prefix sums and r = floor(x * Z / 2^64) for
+ * the 64-bit uniform x, so e = first index with prefix > r.  Other q: FP64 prefix sums in
+ * input order and r = (x >> 11) * 2^-53 * Z.  Sets mark[e] = 1 for every drawn edge and,
+ * if out_eids is not NULL, writes the draws in order.
+ */
+int orc_es_draw(uint64_t m, const uint32_t *w, double p, uint64_t budget, uint64_t seed, uint8_t *mark,
+                uint64_t *out_eids) {
+    if (!mark || (m && !w) || isnan(p)) return O_E_ARG;
+    if (m == 0 || budget == 0) return O_OK;
+    const double q = orc_sample_exponent(p);
+    const int exact = (q == 1.0 || q == 2.0 || q == 3.0);
+    if (exact) {
+        const int qi = (int)q;
+        u128 *P = (u128 *)malloc(m * sizeof(u128));
+        if (!P) return O_E_NOMEM;
+        u128 acc = 0;
+        for (uint64_t e = 0; e < m; e++) {
+            u128 t = w[e];
+            if (qi >= 2) t *= w[e];
+            if (qi >= 3) t *= w[e];
+            acc += t;
+            P[e] = acc;
+        }
+        const u128 Z = acc;
+        const uint64_t Zh = (uint64_t)(Z >> 64), Zl = (uint64_t)Z;
+#pragma omp parallel for schedule(static)
+        for (uint64_t s = 0; s < budget; s++) {
+            const uint64_t x = splitmix64_at(seed, s);
+            const u128 r = (u128)x * Zh + (uint64_t)(((u128)x * Zl) >> 64);
+            uint64_t lo = 0, hi = m - 1;
+            while (lo < hi) { uint64_t mid = lo + (hi - lo) / 2; if (P[mid] > r) hi = mid; else lo = mid + 1; }
+            mark[lo] = 1;
+            if (out_eids) out_eids[s] = lo;
+        }
+        free(P);
+    } else {
+        double *P = (double *)malloc(m * sizeof(double));
+        if (!P) return O_E_NOMEM;
+        double acc = 0.0;
+        for (uint64_t e = 0; e < m; e++) { acc += pow((double)w[e], q); P[e] = acc; }
+        const double Z = acc;
+#pragma omp parallel for schedule(static)
+        for (uint64_t s = 0; s < budget; s++) {
+            const uint64_t x = splitmix64_at(seed, s);
+            const double r = (double)(x >> 11) * (1.0 / 9007199254740992.0) * Z;
+            uint64_t lo = 0, hi = m - 1;
+            while (lo < hi) { uint64_t mid = lo + (hi - lo) / 2; if (P[mid] > r) hi = mid; else lo = mid + 1; }
+            mark[lo] = 1;
+            if (out_eids) out_eids[s] = lo;
+        }
+        free(P);
+    }
+    return O_OK;
+}
+
+uint64_t orc_splitmix64_at(uint64_t seed, uint64_t i) { return splitmix64_at(seed, i); }
