@@ -1,0 +1,140 @@
+/*
+ * topktri.h — top-k weighted triangles on AMD MI355X (gfx950).
+ *
+ * Problem (Kumar, Liu, Charikar, Benson, "Retrieving Top Weighted Triangles in Graphs",
+ * WSDM 2020, Sec. 1): G = (V, E, w) is a simple undirected graph with positive edge
+ * weights.  The weight of triangle (i, j, l) is the generalized p-mean of its three edge
+ * weights (Eq. 1):  m_p = [ (w_ij^p + w_jl^p + w_il^p) / 3 ]^(1/p),  with the limits named
+ * right after Eq. 1: p = 0 is the geometric mean, p = +inf the maximum, p = -inf the minimum.
+ * A query returns the k heaviest triangles.
+ *
+ * Conventions shared by every entry point
+ *   - Vertex IDs are uint32 in [0, n); n <= 2^32 - 2.  Weights are uint32 >= 1.
+ *   - Results are sorted by score descending, then by (i, j, l) ascending, where
+ *     i < j < l are the caller's original vertex IDs.  If the graph (or the admitted set)
+ *     holds T < k triangles, all T are returned and *n_out = T.
+ *   - For p in {-inf, 0, 1, 2, +inf} the order is decided by exact integer arithmetic
+ *     (min, product, sum, sum of squares, max); for any other p by the FP64 value of m_p.
+ *     The returned score is the FP64 value of m_p.
+ *   - Every function returns an int status (TT_OK = 0, negative on error).  No function
+ *     aborts, throws or exits.  On error, *n_out (if given) is set to 0 and other outputs
+ *     are untouched.  tt_last_error() returns a message for the calling thread.
+ *   - Host pointers are copied before the call returns and never retained.
+ *   - A graph is immutable after loading.  Queries on one graph from several host threads
+ *     are serialised internally.
+ */
+#ifndef TOPKTRI_H
+#define TOPKTRI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque handle; owns all device memory of one loaded graph. */
+typedef struct tt_graph tt_graph;
+
+/* One result triangle: original vertex IDs i < j < l and the FP64 p-mean.  24 bytes. */
+typedef struct {
+    uint32_t i, j, l, _pad;
+    double score;
+} tt_triangle;
+
+enum {
+    TT_OK = 0,
+    TT_E_ARG = -1,          /* NULL pointer, NaN p, bad size */
+    TT_E_SELF_LOOP = -2,    /* an edge (v, v) */
+    TT_E_DUP_EDGE = -3,     /* the same unordered pair twice */
+    TT_E_ZERO_WEIGHT = -4,  /* a weight of 0 (weights must be positive, Sec. 1) */
+    TT_E_VERTEX_RANGE = -5, /* an endpoint >= n */
+    TT_E_NOMEM = -6,        /* device or host allocation failed */
+    TT_E_DEVICE = -7,       /* a HIP runtime call failed */
+    TT_E_BUDGET = -8,       /* the request does not fit the scratch budget */
+    TT_E_TOO_LARGE = -9     /* n or m beyond the supported range */
+};
+
+/* Per-query counters (optional output of the _ex calls). */
+typedef struct {
+    uint64_t candidate_edges;     /* oriented edges that passed the bound test, all passes */
+    uint64_t intersected_entries; /* adjacency entries read by intersections, all passes */
+    uint64_t triangles_emitted;   /* triangles written to the candidate buffer */
+    uint64_t edges_streamed;      /* oriented edges read by the filter, all passes */
+    uint64_t distinct_sampled;    /* sampling only: distinct edges drawn */
+    uint32_t passes;              /* enumeration passes (threshold bands and restarts) */
+    uint32_t restarts;            /* passes repeated because the candidate buffer overflowed */
+    double enum_ms;               /* device time from the first to the last enumeration pass */
+    double select_ms;             /* device time of selection and output (HIP events) */
+    double total_ms;              /* host wall time of the call */
+    double enum_kernel_ms;        /* sum over passes of the enumeration kernel's own duration */
+    double sample_ms;             /* sampling only: device time of the draws (and prefix sums) */
+} tt_query_stats;
+
+/*
+ * Loads a graph from HOST arrays src[m], dst[m], w[m] (edge e = {src[e], dst[e]} with weight
+ * w[e]).  Validation order: vertex range, self-loop, zero weight, duplicate pair (Sec. 1
+ * requires a simple graph with positive weights); the first failing rule is reported.
+ * Builds the degree-oriented CSR on the device (every triangle is reached exactly once from
+ * its two lowest vertices in (degree, ID) order, the orientation of the brute-force
+ * enumerator of Sec. 3).  *out receives the handle; free it with graph_free.
+ */
+int graph_load(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w,
+               tt_graph **out);
+
+/*
+ * As graph_load, but src/dst/w are DEVICE pointers (e.g. from torch tensors) and all work is
+ * ordered on `stream` (a hipStream_t; NULL = the default stream).  The graph keeps using that
+ * stream for its queries.  The input buffers are read during the call only.
+ */
+int graph_load_device(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w,
+                      void *stream, tt_graph **out);
+
+/*
+ * Exact top-k triangles by m_p (Eq. 1).  out: caller-owned HOST array with room for k
+ * records.  k = 0 returns TT_OK with *n_out = 0.  p may be any double (+-INFINITY allowed);
+ * NaN gives TT_E_ARG.
+ */
+int topk_triangles(tt_graph *g, uint32_t k, double p, tt_triangle *out, uint32_t *n_out);
+
+/*
+ * topk_triangles restricted to triangles that touch `subset` (at least one vertex in it),
+ * subset: HOST array of subset_n vertex IDs (duplicates allowed; subset_n = 0 or subset =
+ * NULL means no restriction).  stats may be NULL.
+ */
+int topk_triangles_ex(tt_graph *g, uint32_t k, double p, const uint32_t *subset, uint32_t subset_n,
+                      tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
+
+/*
+ * Weighted edge sampling (Alg. 3): `budget` independent draws of an edge e with probability
+ * w_e^q / Z (Prop. 1), q = p for finite p > 0 and q = 1 otherwise; the result is the top-k,
+ * by the true m_p, of the union of all triangles on the drawn edges.  Draw s uses the s-th
+ * output of SplitMix64 started from `seed` (Steele, Lea, Flood 2014) and selects the first
+ * edge, in input order, whose inclusive prefix sum of w^q exceeds floor(x_s * Z / 2^64)
+ * (integer q in {1, 2, 3}, exact 128-bit arithmetic) or x_s * 2^-64 * Z (other q, FP64).
+ * budget = 0 or k = 0 returns TT_OK with *n_out = 0.
+ */
+int sample_heavy_triangles(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed, tt_triangle *out,
+                           uint32_t *n_out);
+
+/* sample_heavy_triangles with optional stats (may be NULL). */
+int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed,
+                              tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
+
+/* Number of vertices / undirected edges of a loaded graph (0 for NULL). */
+uint32_t graph_num_vertices(const tt_graph *g);
+uint64_t graph_num_edges(const tt_graph *g);
+
+/* Device bytes held by the graph (CSR, copies and cached scratch). */
+uint64_t graph_device_bytes(const tt_graph *g);
+
+/* Releases every resource of g.  NULL-safe. */
+void graph_free(tt_graph *g);
+
+/* Message for the last error on the calling thread ("" if none).  Valid until the next call. */
+const char *tt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOPKTRI_H */

@@ -1,0 +1,202 @@
+"""Top-k weighted triangles on AMD MI355X: a thin ctypes binding over libtopktri.so.
+
+Every step of the computation runs in the HIP library (``csrc/``); this module only marshals
+arguments.  The C ABI is declared in ``include/topktri.h``.  Inputs may be NumPy arrays (host)
+or torch CUDA tensors (device, loaded on the tensor's current stream).
+
+If the library has not been built, importing works but any call raises ``LibraryMissing``:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+from ._build import LIB as LIB_PATH, build  # noqa: F401
+
+_lib = None
+
+TT_OK, TT_E_ARG, TT_E_SELF_LOOP, TT_E_DUP_EDGE, TT_E_ZERO_WEIGHT = 0, -1, -2, -3, -4
+TT_E_VERTEX_RANGE, TT_E_NOMEM, TT_E_DEVICE, TT_E_BUDGET, TT_E_TOO_LARGE = -5, -6, -7, -8, -9
+
+EXPORTED = ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles_ex", "sample_heavy_triangles",
+            "sample_heavy_triangles_ex", "graph_num_vertices", "graph_num_edges", "graph_device_bytes",
+            "graph_free", "tt_last_error")
+
+
+class Triangle(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_uint32), ("j", ctypes.c_uint32), ("l", ctypes.c_uint32), ("_pad", ctypes.c_uint32),
+                ("score", ctypes.c_double)]
+
+
+class QueryStats(ctypes.Structure):
+    _fields_ = [("candidate_edges", ctypes.c_uint64), ("intersected_entries", ctypes.c_uint64),
+                ("triangles_emitted", ctypes.c_uint64), ("edges_streamed", ctypes.c_uint64),
+                ("distinct_sampled", ctypes.c_uint64), ("passes", ctypes.c_uint32), ("restarts", ctypes.c_uint32),
+                ("enum_ms", ctypes.c_double), ("select_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("enum_kernel_ms", ctypes.c_double), ("sample_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+TRI_DTYPE = np.dtype([("i", np.uint32), ("j", np.uint32), ("l", np.uint32), ("_pad", np.uint32),
+                      ("score", np.float64)])
+assert TRI_DTYPE.itemsize == ctypes.sizeof(Triangle) == 24
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class TopKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"status {code}: {msg}")
+        self.code = code
+
+
+def library():
+    """Loads libtopktri.so (raises LibraryMissing if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        # torch ships its own HIP runtime with the same SONAME (libamdhip64.so.7); loading it
+        # first makes the library bind to that one, so torch streams and pointers are shared
+        # with a single runtime instead of two runtimes competing for the device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        lib = ctypes.CDLL(LIB_PATH)
+        u32, u64, dbl, vp, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
+        p32 = ctypes.POINTER(ctypes.c_uint32)
+        pg = ctypes.POINTER(ctypes.c_void_p)
+        ptri = ctypes.POINTER(Triangle)
+        pst = ctypes.POINTER(QueryStats)
+        lib.graph_load.argtypes = [u32, u64, p32, p32, p32, pg]
+        lib.graph_load_device.argtypes = [u32, u64, vp, vp, vp, vp, pg]
+        lib.topk_triangles.argtypes = [vp, u32, dbl, ptri, p32]
+        lib.topk_triangles_ex.argtypes = [vp, u32, dbl, p32, u32, ptri, p32, pst]
+        lib.sample_heavy_triangles.argtypes = [vp, u32, dbl, u64, u64, ptri, p32]
+        lib.sample_heavy_triangles_ex.argtypes = [vp, u32, dbl, u64, u64, ptri, p32, pst]
+        lib.graph_num_vertices.argtypes = [vp]
+        lib.graph_num_vertices.restype = u32
+        lib.graph_num_edges.argtypes = [vp]
+        lib.graph_num_edges.restype = u64
+        lib.graph_device_bytes.argtypes = [vp]
+        lib.graph_device_bytes.restype = u64
+        lib.graph_free.argtypes = [vp]
+        lib.graph_free.restype = None
+        lib.tt_last_error.argtypes = []
+        lib.tt_last_error.restype = ctypes.c_char_p
+        for name in ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles_ex",
+                     "sample_heavy_triangles", "sample_heavy_triangles_ex"):
+            getattr(lib, name).restype = i32
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc != TT_OK:
+        raise TopKError(rc, library().tt_last_error().decode(errors="replace"))
+
+
+def _u32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+
+
+def _result(buf, n):
+    r = np.frombuffer(buf, dtype=TRI_DTYPE, count=n).copy() if n else np.zeros(0, TRI_DTYPE)
+    return {"i": r["i"], "j": r["j"], "l": r["l"], "score": r["score"], "n_out": int(n)}
+
+
+class Graph:
+    """A graph resident on the GPU (the degree-oriented CSR built by graph_load)."""
+
+    def __init__(self, n: int, src, dst, w, stream=None):
+        lib = library()
+        self._h = ctypes.c_void_p()
+        if hasattr(src, "is_cuda") and src.is_cuda:
+            import torch
+            s = src.contiguous().to(torch.int32) if src.dtype != torch.int32 else src.contiguous()
+            d = dst.contiguous().to(torch.int32) if dst.dtype != torch.int32 else dst.contiguous()
+            ww = w.contiguous().to(torch.int32) if w.dtype != torch.int32 else w.contiguous()
+            if stream is None:
+                stream = torch.cuda.current_stream(src.device)
+            st = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+            _check(lib.graph_load_device(int(n), int(s.numel()), ctypes.c_void_p(s.data_ptr()),
+                                         ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(ww.data_ptr()), st,
+                                         ctypes.byref(self._h)))
+            self._keep = (s, d, ww)
+        else:
+            s, d, ww = _u32(src), _u32(dst), _u32(w)
+            if not (s.shape == d.shape == ww.shape) or s.ndim != 1:
+                raise ValueError("src, dst, w must be 1-D arrays of equal length")
+            p32 = ctypes.POINTER(ctypes.c_uint32)
+            _check(lib.graph_load(int(n), int(s.shape[0]), s.ctypes.data_as(p32), d.ctypes.data_as(p32),
+                                  ww.ctypes.data_as(p32), ctypes.byref(self._h)))
+        self.n = int(n)
+        self.m = int(lib.graph_num_edges(self._h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def device_bytes(self) -> int:
+        return int(library().graph_device_bytes(self._h))
+
+    def topk(self, k: int, p: float, subset=None, with_stats: bool = False):
+        """Exact top-k triangles by m_p.  Returns dict(i, j, l, score, n_out[, stats])."""
+        lib = library()
+        buf = (Triangle * max(int(k), 1))()
+        n_out = ctypes.c_uint32(0)
+        st = QueryStats()
+        sub_p, sub_n = None, 0
+        if subset is not None and len(subset):
+            sub = _u32(subset)
+            sub_p, sub_n = sub.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), int(sub.shape[0])
+        _check(lib.topk_triangles_ex(self._h, int(k), float(p), sub_p, sub_n, buf, ctypes.byref(n_out),
+                                     ctypes.byref(st)))
+        out = _result(buf, n_out.value)
+        if with_stats:
+            out["stats"] = st.as_dict()
+        return out
+
+    def sample(self, k: int, p: float, budget: int, seed: int, with_stats: bool = False):
+        """Weighted edge sampling (Alg. 3): top-k of the union of triangles on the drawn edges."""
+        lib = library()
+        buf = (Triangle * max(int(k), 1))()
+        n_out = ctypes.c_uint32(0)
+        st = QueryStats()
+        _check(lib.sample_heavy_triangles_ex(self._h, int(k), float(p), int(budget), int(seed) & (2**64 - 1), buf,
+                                             ctypes.byref(n_out), ctypes.byref(st)))
+        out = _result(buf, n_out.value)
+        if with_stats:
+            out["stats"] = st.as_dict()
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().graph_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def load(n, src, dst, w, stream=None) -> Graph:
+    return Graph(n, src, dst, w, stream=stream)

@@ -1,0 +1,134 @@
+// common.h — internal declarations shared by the library's translation units.
+//
+// Nothing here is part of the public ABI (include/topktri.h is).  All device code targets
+// gfx950: 64-lane wavefronts, no MFMA (the work is integer graph traversal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+#include <mutex>
+#include <algorithm>
+#include <new>
+
+#include "../../include/topktri.h"
+
+typedef unsigned __int128 u128;
+
+// ----------------------------------------------------------------------------- scoring modes
+// The order of triangles under Eq. 1 is decided by a key that is a monotone transform of
+// m_p: exact integers for the means named after Eq. 1 (and p = 2), FP64 bits otherwise.
+enum { MODE_MAX = 0, MODE_MIN = 1, MODE_SUM = 2, MODE_SUMSQ = 3, MODE_PROD = 4, MODE_GEN = 5 };
+
+inline int mode_of(double p) {
+    if (p == __builtin_inf()) return MODE_MAX;
+    if (p == -__builtin_inf()) return MODE_MIN;
+    if (p == 1.0) return MODE_SUM;
+    if (p == 2.0) return MODE_SUMSQ;
+    if (p == 0.0) return MODE_PROD;
+    return MODE_GEN;
+}
+
+// One candidate triangle in device memory: order key (hi, lo) and original IDs i < j < l.
+struct __attribute__((aligned(16))) trec {
+    uint64_t khi, klo;
+    uint32_t i, j, l, pad;
+};
+
+// ----------------------------------------------------------------------------- graph
+struct tt_graph {
+    uint32_t n = 0;
+    uint64_t m = 0;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    int device = 0;
+    // degree-oriented CSR: an entry u->v exists iff (deg u, u) < (deg v, v); rows sorted by v
+    uint64_t *rowp = nullptr;   // [n+1]
+    uint32_t *col = nullptr;    // [m] head vertex v (original ID)
+    uint32_t *wgt = nullptr;    // [m] edge weight
+    uint32_t *osrc = nullptr;   // [m] tail vertex u of each entry
+    uint32_t *eid = nullptr;    // [m] input edge index of each entry
+    uint32_t *opos = nullptr;   // [m] entry position of each input edge
+    uint32_t *maxw = nullptr;   // [n] largest weight in u's out-row (0 for an empty row)
+    uint32_t *deg = nullptr;    // [n] undirected degree
+    uint32_t wmax = 0;          // largest weight in the graph
+    uint32_t max_outdeg = 0;
+    std::vector<uint64_t> whist; // host copy of the weight histogram (see weight_bin)
+    uint64_t bytes = 0;
+    // query scratch, grown on demand and kept for later queries
+    trec *buf0 = nullptr, *buf1 = nullptr;
+    uint64_t buf_cap = 0;
+    unsigned long long *dcount = nullptr; // [8] counters
+    unsigned long long *hcount = nullptr; // pinned mirror
+    tt_triangle *dout = nullptr;
+    uint64_t dout_cap = 0;
+    uint8_t *emark = nullptr;   // [m] per-entry marks (sampling)
+    uint8_t *vflag = nullptr;   // [n]
+    uint8_t *vflag2 = nullptr;  // [n]
+    // sampling prefix sums, cached per exponent
+    double prefix_q = -1.0;
+    void *prefix = nullptr;     // u64 (q=1), u128 (q=2,3) or double (other q)
+    hipEvent_t ev[8] = {};
+    std::mutex mu;
+};
+
+// ----------------------------------------------------------------------------- weight bins
+// 2048 log-spaced bins: w < 64 exact; otherwise 64 bins per octave.
+constexpr int WBINS = 2048;
+__host__ __device__ inline uint32_t weight_bin(uint32_t w) {
+    if (w < 64) return w;
+    uint32_t e = 31u - (uint32_t)__builtin_clz(w);          // 6..31
+    uint32_t top = w >> (e - 6);                            // 64..127
+    return (e - 6) * 64u + top;                             // 64..1727
+}
+__host__ __device__ inline uint32_t weight_bin_low(uint32_t b) {
+    if (b < 64) return b;
+    uint32_t e = (b - 64) / 64 + 6, top = (b - 64) % 64 + 64;
+    return top << (e - 6);
+}
+
+// ----------------------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess)                                                              \
+            return fail(_e == hipErrorOutOfMemory ? TT_E_NOMEM : TT_E_DEVICE,              \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));                \
+    } while (0)
+
+int dev_alloc(tt_graph *g, void **p, size_t bytes);
+void dev_free(tt_graph *g, void *p, size_t bytes);
+int num_cus();
+
+// ----------------------------------------------------------------------------- wave helpers
+__device__ inline uint64_t wave_ballot(bool b) { return __ballot(b); }
+
+template <typename T> __device__ inline T wave_incl_scan(T x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+template <typename T> __device__ inline T wave_max(T x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T y = __shfl_xor(x, o, 64);
+        x = x > y ? x : y;
+    }
+    return x;
+}
+template <typename T> __device__ inline T wave_sum(T x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// scan helpers (scan.hip)
+int exclusive_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t s, tt_graph *g);

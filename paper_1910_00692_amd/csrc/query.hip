@@ -1,0 +1,778 @@
+// query.hip — exact top-k triangles (Sec. 1 problem, Eq. 1 scores) and weighted edge
+// sampling (Alg. 3) on a loaded graph.
+//
+// Pruned enumeration.  Sec. 3.2 bounds the heaviest triangle that has not been enumerated
+// from the weights of the edges not yet processed.  The same monotonicity gives, for any
+// threshold L on the order key: a triangle (u,v,c) reached at oriented entry u->v has weights
+// a = w_uv, x = w_uc <= maxw(u), y = w_vc <= maxw(v), so it can reach L only if
+// key(a, maxw(u), maxw(v)) >= L (entry filter), and then only entries with
+// x >= min{x : key(a, x, maxw(v)) >= L} (and symmetrically for y) can take part.  m_p is
+// non-decreasing in each argument for every p in [-inf, +inf], so this holds for all p.
+//
+// Threshold descent.  Instead of the sequential pointer walk of Alg. 2, the host runs a short
+// sequence of data-parallel passes over decreasing score bands [L_i, L_{i-1}), with L_i taken
+// from quantiles of the edge-weight distribution (the k-th, 4k-th, 16k-th ... heaviest edge,
+// as in the heavy/light split of Sec. 3).  Bands are disjoint, so after pass i the candidate
+// buffer holds exactly the triangles with key >= L_i; as soon as it holds >= k of them the
+// top-k is among them (the argument of Sec. 3.2).  If the buffer overflows, its k-th best full
+// key (score, i, j, l) is a valid lower bound and the pass is redone above it.
+//
+// Selection.  The buffer is sorted in LDS tiles of 1024 records by (key desc, i, j, l asc),
+// each tile truncated to k, then merged pairwise (every record finds its rank in the sibling
+// run by binary search) with runs truncated to k, down to one run.
+#include <cmath>
+#include <chrono>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+#include "scan.h"
+
+namespace {
+
+// ----------------------------------------------------------------------------- scoring
+__device__ __forceinline__ double u128_to_double(u128 x) {
+    return (double)(uint64_t)(x >> 64) * 18446744073709551616.0 + (double)(uint64_t)x;
+}
+
+// Eq. 1 for a generic p, rewritten so that no power overflows and small |p| loses nothing:
+// m = s * exp(log1p(mean(expm1(p * log(x/s)))) / p), s = max (p > 0) or min (p < 0).
+__device__ double gen_mean(double p, double a, double b, double c) {
+    const double s = p > 0.0 ? fmax(a, fmax(b, c)) : fmin(a, fmin(b, c));
+    const double acc = expm1(p * log(a / s)) + expm1(p * log(b / s)) + expm1(p * log(c / s));
+    return s * exp(log1p(acc / 3.0) / p);
+}
+
+__device__ __forceinline__ u128 score_key(int mode, double p, uint32_t a, uint32_t b, uint32_t c) {
+    switch (mode) {
+    case MODE_MAX: return (u128)max(a, max(b, c));
+    case MODE_MIN: return (u128)min(a, min(b, c));
+    case MODE_SUM: return (u128)((uint64_t)a + b + c);
+    case MODE_SUMSQ: return (u128)((uint64_t)a * a) + (u128)((uint64_t)b * b) + (u128)((uint64_t)c * c);
+    case MODE_PROD: {
+        const uint64_t ab = (uint64_t)a * b;
+        const uint64_t lo = ab * (uint64_t)c, hi = __umul64hi(ab, (uint64_t)c);
+        return ((u128)hi << 64) | lo;
+    }
+    default: return (u128)(uint64_t)__double_as_longlong(gen_mean(p, (double)a, (double)b, (double)c));
+    }
+}
+
+__device__ double key_to_score(int mode, u128 key) {
+    switch (mode) {
+    case MODE_MAX:
+    case MODE_MIN: return (double)(uint64_t)key;
+    case MODE_SUM: return (double)(uint64_t)key / 3.0;
+    case MODE_SUMSQ: return sqrt(u128_to_double(key) / 3.0);
+    case MODE_PROD: return cbrt(u128_to_double(key));
+    default: return __longlong_as_double((long long)(uint64_t)key);
+    }
+}
+
+__device__ __forceinline__ bool better(const trec &a, const trec &b) {
+    if (a.khi != b.khi) return a.khi > b.khi;
+    if (a.klo != b.klo) return a.klo > b.klo;
+    if (a.i != b.i) return a.i < b.i;
+    if (a.j != b.j) return a.j < b.j;
+    return a.l < b.l;
+}
+
+// ----------------------------------------------------------------------------- bounds
+struct Band {
+    u128 L;              // inclusive lower bound on the order key ...
+    uint32_t Li, Lj, Ll; // ... and, at key == L, on (i, j, l) (all 0xFFFFFFFF: no restriction)
+    u128 U;              // exclusive upper bound on the order key if hasU
+    int hasU;
+    int mode;
+    double p;
+    double theta;        // generic p: the score L as a double
+};
+
+// key(a, Wu, Wv) >= L : no triangle on this entry can reach the band otherwise
+__device__ __forceinline__ bool bound_ok(const Band &B, uint32_t a, uint32_t Wu, uint32_t Wv) {
+    if (B.L == 0) return true;
+    if (B.mode == MODE_GEN) return gen_mean(B.p, (double)a, (double)Wu, (double)Wv) >= B.theta * (1.0 - 1e-12);
+    return score_key(B.mode, B.p, a, Wu, Wv) >= B.L;
+}
+
+// Smallest weight x (never above the exact one) with m_p(a, x, W) >= theta, generic p.
+__device__ uint64_t gen_min_other(double p, double theta, double a, double W) {
+    if (p > 0.0) {
+        const double s = fmax(theta, fmax(a, W));
+        const double t3 = 3.0 * pow(theta / s, p);
+        double D = t3 - pow(a / s, p) - pow(W / s, p);
+        D -= 1e-12 * (t3 + 2.0);
+        if (!(D > 0.0)) return 0;
+        const double x = s * pow(D, 1.0 / p) * (1.0 - 1e-9);
+        return x < 1.0 ? 0 : (x >= 1.8e19 ? ~0ull : (uint64_t)floor(x));
+    } else {
+        const double s = fmin(theta, fmin(a, W));
+        const double t3 = 3.0 * pow(theta / s, p);
+        double D = t3 - pow(a / s, p) - pow(W / s, p);
+        D += 1e-12 * (t3 + 2.0);
+        if (!(D > 0.0)) return ~0ull;
+        const double x = s * pow(D, 1.0 / p) * (1.0 - 1e-9);
+        return x < 1.0 ? 0 : (x >= 1.8e19 ? ~0ull : (uint64_t)floor(x));
+    }
+}
+
+// Smallest weight x (a lower bound of it) for which key(a, x, W) can still reach L.
+__device__ uint64_t min_other(const Band &B, uint32_t a, uint32_t W) {
+    if (B.L == 0) return 0;
+    switch (B.mode) {
+    case MODE_MAX: return ((u128)a >= B.L || (u128)W >= B.L) ? 0 : (uint64_t)B.L;
+    case MODE_MIN: return (uint64_t)B.L;
+    case MODE_SUM: {
+        const uint64_t aw = (uint64_t)a + W, L = (uint64_t)B.L;
+        return L > aw ? L - aw : 0;
+    }
+    case MODE_SUMSQ: {
+        const u128 aw = (u128)((uint64_t)a * a) + (u128)((uint64_t)W * W);
+        if (B.L <= aw) return 0;
+        const uint64_t z = (uint64_t)sqrt(u128_to_double(B.L - aw));
+        return z > 1 ? z - 1 : 0;
+    }
+    case MODE_PROD: {
+        const double q = u128_to_double(B.L) / ((double)a * (double)W);
+        if (q <= 1.0) return 0;
+        if (q >= 1.8e19) return ~0ull;
+        const uint64_t z = (uint64_t)q;
+        return z > 1 ? z - 1 : 0;
+    }
+    default: return gen_min_other(B.p, B.theta, (double)a, (double)W);
+    }
+}
+
+__device__ __forceinline__ bool in_band(const Band &B, u128 key, uint32_t i, uint32_t j, uint32_t l) {
+    if (B.hasU && key >= B.U) return false;
+    if (key != B.L) return key > B.L;
+    return i < B.Li || (i == B.Li && (j < B.Lj || (j == B.Lj && l <= B.Ll)));
+}
+
+// ----------------------------------------------------------------------------- enumeration
+enum { FILTER_NONE = 0, FILTER_EDGES = 1, FILTER_VERTICES = 2 };
+enum { FL_MARK_UV = 1, FL_REQ_A = 2, FL_REQ_B = 4, FL_REQ_C = 8 };
+
+struct EnumArgs {
+    const uint64_t *rowp;
+    const uint32_t *osrc, *col, *wgt, *maxw;
+    uint64_t m;
+    Band B;
+    const uint8_t *emark;  // FILTER_EDGES: drawn entries
+    const uint8_t *vflag;  // FILTER_EDGES: vertex has a drawn out-entry; FILTER_VERTICES: vertex in subset
+    const uint8_t *vflag2; // FILTER_VERTICES: vertex has an out-neighbour in the subset
+    trec *out;
+    unsigned long long *count;
+    uint64_t cap;
+    unsigned long long *stats; // [0] candidates [1] intersected entries [2] emitted [3] streamed
+};
+
+// Persistent waves walk the oriented entries in chunks of 64 (one lane per entry).  Entries
+// that survive the bound test are intersected cooperatively: the wave flattens the
+// (entry, element of its shorter row) pairs of the whole chunk, so all 64 lanes stay busy,
+// and each lane binary-searches its element in the longer row.
+template <int FILTER> __global__ __launch_bounds__(256) void k_enum(EnumArgs A) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t nchunks = (A.m + 63) >> 6;
+    unsigned long long s_cand = 0, s_inter = 0, s_emit = 0, s_stream = 0;
+    for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
+        const uint64_t e = (ch << 6) + (uint64_t)lane;
+        bool pass = false;
+        uint32_t a = 0, u = 0, v = 0, Alen = 0, Blen = 0, fl = 0;
+        uint64_t Ab = 0, Bb = 0, zA = 0, zB = 0;
+        if (e < A.m) {
+            u = A.osrc[e];
+            v = A.col[e];
+            a = A.wgt[e];
+            const uint32_t Wu = A.maxw[u], Wv = A.maxw[v];
+            bool pre = true;
+            if (FILTER == FILTER_EDGES) {
+                if (A.emark[e]) fl |= FL_MARK_UV;
+                pre = (fl & FL_MARK_UV) || A.vflag[u] || A.vflag[v];
+            } else if (FILTER == FILTER_VERTICES) {
+                const bool su = A.vflag[u], sv = A.vflag[v];
+                pre = su || sv || (A.vflag2[u] && A.vflag2[v]);
+                if (!su && !sv) fl |= FL_REQ_C;
+            }
+            pass = pre && bound_ok(A.B, a, Wu, Wv);
+            if (pass) {
+                const uint64_t ub = A.rowp[u], ue = A.rowp[u + 1], vb = A.rowp[v], ve = A.rowp[v + 1];
+                const uint64_t zu = min_other(A.B, a, Wv), zv = min_other(A.B, a, Wu);
+                const bool uA = (ue - ub) <= (ve - vb);
+                Ab = uA ? ub : vb;
+                Alen = (uint32_t)(uA ? ue - ub : ve - vb);
+                Bb = uA ? vb : ub;
+                Blen = (uint32_t)(uA ? ve - vb : ue - ub);
+                zA = uA ? zu : zv;
+                zB = uA ? zv : zu;
+                if (zu > Wu || zv > Wv || Alen == 0 || Blen == 0) pass = false;
+                if (FILTER == FILTER_EDGES && !(fl & FL_MARK_UV)) {
+                    // a drawn edge must be among the other two
+                    const bool fa = A.vflag[uA ? u : v], fb = A.vflag[uA ? v : u];
+                    if (!fa && !fb) pass = false;
+                    if (!fb) fl |= FL_REQ_A; // only drawn entries of the A row can help
+                    if (!fa) fl |= FL_REQ_B;
+                }
+            }
+        }
+        const uint32_t work = pass ? Alen : 0;
+        const uint32_t incl = wave_incl_scan(work);
+        const uint32_t total = __shfl(incl, 63, 64);
+        const uint64_t pb = __ballot(pass);
+        if (lane == 0) {
+            s_cand += __popcll(pb);
+            s_inter += total;
+            s_stream += (A.m - (ch << 6)) < 64 ? (A.m - (ch << 6)) : 64;
+        }
+        for (uint32_t base = 0; base < total; base += 64) {
+            const uint32_t t = base + (uint32_t)lane;
+            const uint32_t tt = t < total ? t : total - 1;
+            int s = 0; // owner lane: number of lanes whose inclusive end is <= tt
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                const uint32_t im = __shfl(incl, s + step - 1, 64);
+                if (im <= tt) s += step;
+            }
+            const uint32_t o_incl = __shfl(incl, s, 64), o_work = __shfl(work, s, 64);
+            const uint64_t oAb = __shfl(Ab, s, 64), oBb = __shfl(Bb, s, 64);
+            const uint64_t ozA = __shfl(zA, s, 64), ozB = __shfl(zB, s, 64);
+            const uint32_t oBlen = __shfl(Blen, s, 64), oa = __shfl(a, s, 64), ou = __shfl(u, s, 64),
+                           ov = __shfl(v, s, 64), ofl = __shfl(fl, s, 64);
+            bool ok = false;
+            trec r;
+            if (t < total) {
+                const uint64_t pa = oAb + (tt - (o_incl - o_work));
+                const uint32_t c = A.col[pa], x = A.wgt[pa];
+                bool go = (uint64_t)x >= ozA;
+                if (FILTER == FILTER_VERTICES && (ofl & FL_REQ_C)) go = go && A.vflag[c];
+                if (FILTER == FILTER_EDGES && (ofl & FL_REQ_A)) go = go && A.emark[pa];
+                if (go) {
+                    uint64_t lo = oBb, hi = oBb + oBlen;
+                    while (lo < hi) {
+                        const uint64_t mid = (lo + hi) >> 1;
+                        if (A.col[mid] < c) lo = mid + 1; else hi = mid;
+                    }
+                    if (lo < oBb + oBlen && A.col[lo] == c) {
+                        const uint32_t y = A.wgt[lo];
+                        bool adm = (uint64_t)y >= ozB;
+                        if (FILTER == FILTER_EDGES) {
+                            if (ofl & FL_REQ_B) adm = adm && A.emark[lo];
+                            adm = adm && ((ofl & FL_MARK_UV) || A.emark[pa] || A.emark[lo]);
+                        }
+                        if (adm) {
+                            const u128 key = score_key(A.B.mode, A.B.p, oa, x, y);
+                            uint32_t i = ou, j = ov, l = c, tmp;
+                            if (i > j) { tmp = i; i = j; j = tmp; }
+                            if (j > l) { tmp = j; j = l; l = tmp; }
+                            if (i > j) { tmp = i; i = j; j = tmp; }
+                            ok = in_band(A.B, key, i, j, l);
+                            r.khi = (uint64_t)(key >> 64);
+                            r.klo = (uint64_t)key;
+                            r.i = i; r.j = j; r.l = l; r.pad = 0;
+                        }
+                    }
+                }
+            }
+            const uint64_t bal = __ballot(ok);
+            if (bal) {
+                const uint32_t nb = __popcll(bal);
+                unsigned long long b0 = 0;
+                if (lane == 0) b0 = atomicAdd(A.count, (unsigned long long)nb);
+                b0 = __shfl(b0, 0, 64);
+                const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
+                if (ok && b0 + rank < A.cap) A.out[b0 + rank] = r;
+                if (lane == 0) s_emit += nb;
+            }
+        }
+    }
+    if (lane == 0) {
+        if (s_cand) atomicAdd(&A.stats[0], s_cand);
+        if (s_inter) atomicAdd(&A.stats[1], s_inter);
+        if (s_emit) atomicAdd(&A.stats[2], s_emit);
+        if (s_stream) atomicAdd(&A.stats[3], s_stream);
+    }
+}
+
+// ----------------------------------------------------------------------------- selection
+constexpr int STILE = 1024;
+
+__device__ __forceinline__ trec worst_rec() {
+    trec r;
+    r.khi = 0; r.klo = 0; r.i = r.j = r.l = 0xFFFFFFFFu; r.pad = 0;
+    return r;
+}
+
+// Sorts each tile of STILE records (best first) in LDS and keeps its first S0.
+__global__ __launch_bounds__(256) void k_tile_sort(const trec *in, trec *out, uint64_t N, uint32_t S0) {
+    __shared__ trec sh[STILE];
+    const uint64_t base = (uint64_t)blockIdx.x * STILE;
+    const uint32_t cover = (uint32_t)((N - base) < (uint64_t)STILE ? (N - base) : (uint64_t)STILE);
+    for (uint32_t t = threadIdx.x; t < STILE; t += blockDim.x) sh[t] = t < cover ? in[base + t] : worst_rec();
+    __syncthreads();
+    for (uint32_t size = 2; size <= (uint32_t)STILE; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t t = threadIdx.x; t < STILE / 2; t += blockDim.x) {
+                const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
+                const bool first_best = (i & size) == 0;
+                const bool swap = first_best ? better(sh[j], sh[i]) : better(sh[i], sh[j]);
+                if (swap) { trec x = sh[i]; sh[i] = sh[j]; sh[j] = x; }
+            }
+            __syncthreads();
+        }
+    }
+    const uint32_t keep = cover < S0 ? cover : S0;
+    for (uint32_t t = threadIdx.x; t < keep; t += blockDim.x) out[(uint64_t)blockIdx.x * S0 + t] = sh[t];
+}
+
+// Merges runs 2r and 2r+1 (cover C, stride S) into run r (stride So), keeping the first So.
+__global__ __launch_bounds__(256) void k_merge(const trec *in, trec *out, uint64_t N, uint64_t C, uint32_t S,
+                                               uint32_t So, uint64_t nruns) {
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t rp = gid / (2ull * S);
+    const uint32_t x = (uint32_t)(gid % (2ull * S));
+    const uint64_t ra = 2 * rp, rb = ra + 1;
+    if (ra >= nruns) return;
+    const uint64_t cova = (N - ra * C) < C ? (N - ra * C) : C;
+    const uint32_t La = (uint32_t)(cova < S ? cova : S);
+    uint32_t Lb = 0;
+    if (rb < nruns) {
+        const uint64_t covb = (N - rb * C) < C ? (N - rb * C) : C;
+        Lb = (uint32_t)(covb < S ? covb : S);
+    }
+    const bool isA = x < S;
+    const uint32_t idx = isA ? x : x - S;
+    if (idx >= (isA ? La : Lb)) return;
+    const trec me = in[(isA ? ra : rb) * S + idx];
+    const trec *sib = in + (isA ? rb : ra) * S;
+    uint32_t lo = 0, hi = isA ? Lb : La;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (better(sib[mid], me)) lo = mid + 1; else hi = mid;
+    }
+    const uint64_t pos = (uint64_t)idx + lo;
+    if (pos < So) out[rp * So + pos] = me;
+}
+
+__global__ void k_finalize(const trec *in, uint32_t K, int mode, tt_triangle *out) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K) return;
+    const trec r = in[t];
+    tt_triangle o;
+    o.i = r.i; o.j = r.j; o.l = r.l; o._pad = 0;
+    o.score = key_to_score(mode, ((u128)r.khi << 64) | r.klo);
+    out[t] = o;
+}
+
+// ----------------------------------------------------------------------------- sampling
+// s-th output (0-based) of SplitMix64 started from state `seed` (Steele, Lea, Flood 2014).
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t s) {
+    uint64_t z = seed + (s + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename T> __device__ __forceinline__ uint64_t first_above(const T *P, uint64_t m, T r) {
+    uint64_t lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (P[mid] > r) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// KIND 0: u64 prefix (q = 1); 1: u128 prefix (q = 2, 3); 2: FP64 prefix.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_es_draw(const void *prefix, uint64_t m, uint64_t budget, uint64_t seed,
+                                                 const uint32_t *opos, const uint32_t *osrc, uint8_t *emark,
+                                                 uint8_t *vflag) {
+    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < budget; s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = splitmix64_at(seed, s);
+        uint64_t e;
+        if (KIND == 0) {
+            const uint64_t *P = (const uint64_t *)prefix;
+            e = first_above<uint64_t>(P, m, __umul64hi(x, P[m - 1]));
+        } else if (KIND == 1) {
+            const u128 *P = (const u128 *)prefix;
+            const u128 Z = P[m - 1];
+            const uint64_t Zh = (uint64_t)(Z >> 64), Zl = (uint64_t)Z;
+            const u128 r = ((u128)x * Zh) + (u128)__umul64hi(x, Zl);
+            e = first_above<u128>(P, m, r);
+        } else {
+            const double *P = (const double *)prefix;
+            const double r = (double)(x >> 11) * (1.0 / 9007199254740992.0) * P[m - 1];
+            e = first_above<double>(P, m, r);
+        }
+        const uint32_t pos = opos[e];
+        emark[pos] = 1;
+        vflag[osrc[pos]] = 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_count_marks(const uint8_t *mark, uint64_t m, unsigned long long *out) {
+    unsigned long long c = 0;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        c += mark[e] != 0;
+    c = wave_sum(c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+__global__ __launch_bounds__(256) void k_mark_vertices(const uint32_t *ids, uint32_t cnt, uint32_t n, uint8_t *vflag) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < cnt && ids[t] < n) vflag[ids[t]] = 1;
+}
+
+// vflag2[u] = 1 if some out-neighbour of u is in the subset
+__global__ __launch_bounds__(256) void k_mark_out_nbrs(const uint32_t *osrc, const uint32_t *col, uint64_t m,
+                                                       const uint8_t *vflag, uint8_t *vflag2) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        if (vflag[col[e]]) vflag2[osrc[e]] = 1;
+}
+
+// ----------------------------------------------------------------------------- host side
+u128 key_of_uniform(int mode, double p, uint32_t t) {
+    switch (mode) {
+    case MODE_MAX:
+    case MODE_MIN: return t;
+    case MODE_SUM: return (u128)3 * t;
+    case MODE_SUMSQ: return (u128)3 * ((uint64_t)t * t);
+    case MODE_PROD: return (u128)((uint64_t)t * t) * t;
+    default: {
+        double d = (double)t;
+        uint64_t b;
+        std::memcpy(&b, &d, 8);
+        (void)p;
+        return b;
+    }
+    }
+}
+
+double key_as_double(u128 L) {
+    uint64_t b = (uint64_t)L;
+    double d;
+    std::memcpy(&d, &b, 8);
+    return d;
+}
+
+// The weight of (a lower bound of) the M-th heaviest edge, from the load-time histogram.
+uint32_t weight_at_rank(const std::vector<uint64_t> &h, uint64_t M) {
+    uint64_t cum = 0;
+    for (int b = WBINS - 1; b >= 0; b--) {
+        cum += h[b];
+        if (cum >= M) return weight_bin_low((uint32_t)b);
+    }
+    return 1;
+}
+
+unsigned enum_grid(uint64_t m) {
+    const uint64_t chunks = (m + 63) / 64;
+    uint64_t blocks = (chunks + 3) / 4;
+    const uint64_t cap = (uint64_t)num_cus() * 8;
+    if (blocks > cap) blocks = cap;
+    return (unsigned)(blocks ? blocks : 1);
+}
+
+int ensure_scratch(tt_graph *g, uint64_t cap, uint64_t kout) {
+    int rc;
+    if (!g->dcount) {
+        if ((rc = dev_alloc(g, (void **)&g->dcount, 16 * sizeof(unsigned long long)))) return rc;
+        if (hipHostMalloc((void **)&g->hcount, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+            return fail(TT_E_NOMEM, "hipHostMalloc failed");
+        for (auto &e : g->ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(TT_E_DEVICE, "hipEventCreate failed");
+    }
+    if (g->buf_cap < cap) {
+        dev_free(g, g->buf0, g->buf_cap * sizeof(trec));
+        dev_free(g, g->buf1, g->buf_cap * sizeof(trec));
+        g->buf0 = g->buf1 = nullptr;
+        g->buf_cap = 0;
+        if ((rc = dev_alloc(g, (void **)&g->buf0, cap * sizeof(trec))) ||
+            (rc = dev_alloc(g, (void **)&g->buf1, cap * sizeof(trec))))
+            return rc;
+        g->buf_cap = cap;
+    }
+    if (g->dout_cap < kout) {
+        dev_free(g, g->dout, g->dout_cap * sizeof(tt_triangle));
+        g->dout = nullptr;
+        g->dout_cap = 0;
+        if ((rc = dev_alloc(g, (void **)&g->dout, kout * sizeof(tt_triangle)))) return rc;
+        g->dout_cap = kout;
+    }
+    return TT_OK;
+}
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+// Sorts the first N records of g->buf0 and leaves the best min(N, k) at the front of *res.
+int select_topk(tt_graph *g, uint64_t N, uint32_t k, trec **res) {
+    hipStream_t s = g->stream;
+    const uint32_t S0 = k < (uint32_t)STILE ? k : (uint32_t)STILE;
+    uint64_t nruns = (N + STILE - 1) / STILE;
+    trec *in = g->buf0, *out = g->buf1;
+    k_tile_sort<<<(unsigned)nruns, 256, 0, s>>>(in, out, N, S0);
+    std::swap(in, out);
+    uint64_t C = STILE;
+    uint32_t S = S0;
+    while (nruns > 1) {
+        const uint64_t C2 = C * 2;
+        const uint32_t So = (uint64_t)k < C2 ? k : (uint32_t)C2;
+        const uint64_t nout = (nruns + 1) / 2;
+        const uint64_t threads = nout * 2ull * S;
+        k_merge<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(in, out, N, C, S, So, nruns);
+        std::swap(in, out);
+        nruns = nout;
+        C = C2;
+        S = So;
+    }
+    HIP_TRY(hipGetLastError());
+    *res = in;
+    return TT_OK;
+}
+
+int launch_enum(tt_graph *g, const Band &B, int filter, tt_query_stats *st) {
+    EnumArgs A;
+    A.rowp = g->rowp;
+    A.osrc = g->osrc;
+    A.col = g->col;
+    A.wgt = g->wgt;
+    A.maxw = g->maxw;
+    A.m = g->m;
+    A.B = B;
+    A.emark = g->emark;
+    A.vflag = g->vflag;
+    A.vflag2 = g->vflag2;
+    A.out = g->buf0;
+    A.count = g->dcount;
+    A.cap = g->buf_cap;
+    A.stats = g->dcount + 1;
+    const unsigned grid = enum_grid(g->m);
+    HIP_TRY(hipEventRecord(g->ev[4], g->stream));
+    if (filter == FILTER_EDGES) k_enum<FILTER_EDGES><<<grid, 256, 0, g->stream>>>(A);
+    else if (filter == FILTER_VERTICES) k_enum<FILTER_VERTICES><<<grid, 256, 0, g->stream>>>(A);
+    else k_enum<FILTER_NONE><<<grid, 256, 0, g->stream>>>(A);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(g->ev[5], g->stream));
+    if (st) st->passes++;
+    return TT_OK;
+}
+
+// After the stream has been synchronised: add the last enumeration launch's duration.
+void add_enum_time(tt_graph *g, tt_query_stats *st) {
+    if (!st) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g->ev[4], g->ev[5]) == hipSuccess) st->enum_kernel_ms += ms;
+}
+
+Band make_band(int mode, double p, u128 L, uint32_t Li, uint32_t Lj, uint32_t Ll, bool hasU, u128 U) {
+    Band B;
+    B.L = L;
+    B.Li = Li; B.Lj = Lj; B.Ll = Ll;
+    B.U = U;
+    B.hasU = hasU ? 1 : 0;
+    B.mode = mode;
+    B.p = p;
+    B.theta = mode == MODE_GEN ? key_as_double(L) : 0.0;
+    return B;
+}
+
+// The threshold descent: bands [L_i, L_{i-1}) until >= k triangles are held, restarts on
+// overflow, then selection.  Writes min(k, T) triangles to `out` (host).
+int run_topk(tt_graph *g, uint32_t k, double p, int filter, tt_triangle *out, uint32_t *n_out, tt_query_stats *st) {
+    const int mode = mode_of(p);
+    const uint64_t cap = std::max<uint64_t>(1ull << 22, 16ull * k);
+    int rc = ensure_scratch(g, cap, k);
+    if (rc) return rc;
+    hipStream_t s = g->stream;
+    // thresholds: key(t, t, t) for t = weight of the k-th, 4k-th, 16k-th ... heaviest edge
+    std::vector<u128> Ls;
+    for (uint64_t M = k; M < (1ull << 62); M *= 4) {
+        const uint32_t t = weight_at_rank(g->whist, M);
+        if (t <= 1) break;
+        const u128 L = key_of_uniform(mode, p, t);
+        if (Ls.empty() || L < Ls.back()) Ls.push_back(L);
+        if (M > g->m) break;
+    }
+    Ls.push_back(0); // exhaustive
+    HIP_TRY(hipMemsetAsync(g->dcount, 0, 8 * sizeof(unsigned long long), s));
+    HIP_TRY(hipEventRecord(g->ev[0], s));
+    uint64_t cnt = 0;
+    bool overflow = false;
+    u128 U = 0;
+    bool hasU = false;
+    for (size_t i = 0; i < Ls.size(); i++) {
+        rc = launch_enum(g, make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, hasU, U), filter, st);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        add_enum_time(g, st);
+        cnt = g->hcount[0];
+        if (cnt > g->buf_cap) { overflow = true; break; }
+        if (cnt >= k) break;
+        U = Ls[i];
+        hasU = true;
+    }
+    double sel_ms = 0.0;
+    while (overflow) {
+        // the k-th best of the records kept is a lower bound on the k-th best overall
+        trec *res = nullptr;
+        HIP_TRY(hipEventRecord(g->ev[2], s));
+        if ((rc = select_topk(g, g->buf_cap, k, &res))) return rc;
+        trec kth;
+        HIP_TRY(hipMemcpyAsync(&kth, res + (k - 1), sizeof(trec), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(g->ev[3], s));
+        HIP_TRY(hipMemsetAsync(g->dcount, 0, sizeof(unsigned long long), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, g->ev[2], g->ev[3]);
+        sel_ms += ms;
+        const u128 L = ((u128)kth.khi << 64) | kth.klo;
+        rc = launch_enum(g, make_band(mode, p, L, kth.i, kth.j, kth.l, false, 0), filter, st);
+        if (rc) return rc;
+        if (st) st->restarts++;
+        HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        add_enum_time(g, st);
+        cnt = g->hcount[0];
+        overflow = cnt > g->buf_cap;
+    }
+    HIP_TRY(hipEventRecord(g->ev[1], s));
+    const uint64_t N = cnt;
+    const uint32_t K = (uint32_t)std::min<uint64_t>(N, k);
+    if (K > 0) {
+        trec *res = nullptr;
+        if ((rc = select_topk(g, N, k, &res))) return rc;
+        k_finalize<<<(K + 255) / 256, 256, 0, s>>>(res, K, mode, g->dout);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipEventRecord(g->ev[2], s));
+    if (K > 0) HIP_TRY(hipMemcpyAsync(out, g->dout, (size_t)K * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_out = K;
+    if (st) {
+        float e_ms = 0.f, s_ms = 0.f;
+        (void)hipEventElapsedTime(&e_ms, g->ev[0], g->ev[1]);
+        (void)hipEventElapsedTime(&s_ms, g->ev[1], g->ev[2]);
+        st->enum_ms += e_ms;
+        st->select_ms += s_ms + sel_ms;
+        st->candidate_edges += g->hcount[1];
+        st->intersected_entries += g->hcount[2];
+        st->triangles_emitted += g->hcount[3];
+        st->edges_streamed += g->hcount[4];
+    }
+    return TT_OK;
+}
+
+int ensure_flags(tt_graph *g, bool edges) {
+    int rc;
+    if (!g->vflag && (rc = dev_alloc(g, (void **)&g->vflag, (uint64_t)g->n + 1))) return rc;
+    if (!g->vflag2 && (rc = dev_alloc(g, (void **)&g->vflag2, (uint64_t)g->n + 1))) return rc;
+    if (edges && !g->emark && (rc = dev_alloc(g, (void **)&g->emark, g->m + 1))) return rc;
+    return TT_OK;
+}
+
+int check_query(tt_graph *g, double p, tt_triangle *out, uint32_t k, uint32_t *n_out) {
+    if (n_out) *n_out = 0;
+    if (!g) return fail(TT_E_ARG, "graph is NULL");
+    if (!n_out) return fail(TT_E_ARG, "n_out is NULL");
+    if (std::isnan(p)) return fail(TT_E_ARG, "p is NaN");
+    if (k && !out) return fail(TT_E_ARG, "out is NULL");
+    return TT_OK;
+}
+
+} // namespace
+
+extern "C" int topk_triangles_ex(tt_graph *g, uint32_t k, double p, const uint32_t *subset, uint32_t subset_n,
+                                 tt_triangle *out, uint32_t *n_out, tt_query_stats *stats) {
+    Timer timer;
+    int rc = check_query(g, p, out, k, n_out);
+    if (rc) return rc;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (k == 0 || g->m == 0) { set_error(""); return TT_OK; }
+    std::lock_guard<std::mutex> lock(g->mu);
+    (void)hipSetDevice(g->device);
+    int filter = FILTER_NONE;
+    if (subset && subset_n) {
+        for (uint32_t t = 0; t < subset_n; t++)
+            if (subset[t] >= g->n) return fail(TT_E_VERTEX_RANGE, "subset vertex >= n");
+        if ((rc = ensure_flags(g, false))) return rc;
+        uint32_t *dids = nullptr;
+        if ((rc = dev_alloc(nullptr, (void **)&dids, (uint64_t)subset_n * 4))) return rc;
+        HIP_TRY(hipMemsetAsync(g->vflag, 0, (uint64_t)g->n + 1, g->stream));
+        HIP_TRY(hipMemsetAsync(g->vflag2, 0, (uint64_t)g->n + 1, g->stream));
+        HIP_TRY(hipMemcpyAsync(dids, subset, (uint64_t)subset_n * 4, hipMemcpyHostToDevice, g->stream));
+        k_mark_vertices<<<(subset_n + 255) / 256, 256, 0, g->stream>>>(dids, subset_n, g->n, g->vflag);
+        k_mark_out_nbrs<<<enum_grid(g->m), 256, 0, g->stream>>>(g->osrc, g->col, g->m, g->vflag, g->vflag2);
+        HIP_TRY(hipStreamSynchronize(g->stream));
+        dev_free(nullptr, dids, (uint64_t)subset_n * 4);
+        filter = FILTER_VERTICES;
+    }
+    rc = run_topk(g, k, p, filter, out, n_out, stats);
+    if (stats) stats->total_ms = timer.ms();
+    if (!rc) set_error("");
+    return rc;
+}
+
+extern "C" int topk_triangles(tt_graph *g, uint32_t k, double p, tt_triangle *out, uint32_t *n_out) {
+    return topk_triangles_ex(g, k, p, nullptr, 0, out, n_out, nullptr);
+}
+
+extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed,
+                                         tt_triangle *out, uint32_t *n_out, tt_query_stats *stats) {
+    Timer timer;
+    int rc = check_query(g, p, out, k, n_out);
+    if (rc) return rc;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (k == 0 || budget == 0 || g->m == 0) { set_error(""); return TT_OK; }
+    std::lock_guard<std::mutex> lock(g->mu);
+    (void)hipSetDevice(g->device);
+    if ((rc = ensure_flags(g, true))) return rc;
+    const double q = (std::isfinite(p) && p > 0.0) ? p : 1.0;
+    const int kind = q == 1.0 ? 0 : (q == 2.0 || q == 3.0) ? 1 : 2;
+    const size_t esz = kind == 0 ? 8 : kind == 1 ? 16 : 8;
+    hipStream_t s = g->stream;
+    if (g->prefix_q != q) {
+        if (!g->prefix && (rc = dev_alloc(g, &g->prefix, g->m * 16))) return rc;
+        g->prefix_q = -1.0;
+        if ((rc = inclusive_weight_prefix(g, q, g->prefix))) return rc;
+        g->prefix_q = q;
+    }
+    (void)esz;
+    if ((rc = ensure_scratch(g, 1, 1))) return rc;
+    HIP_TRY(hipEventRecord(g->ev[6], s));
+    HIP_TRY(hipMemsetAsync(g->emark, 0, g->m + 1, s));
+    HIP_TRY(hipMemsetAsync(g->vflag, 0, (uint64_t)g->n + 1, s));
+    const unsigned grid = (unsigned)std::min<uint64_t>((budget + 255) / 256, (uint64_t)num_cus() * 16);
+    if (kind == 0) k_es_draw<0><<<grid, 256, 0, s>>>(g->prefix, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
+    else if (kind == 1) k_es_draw<1><<<grid, 256, 0, s>>>(g->prefix, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
+    else k_es_draw<2><<<grid, 256, 0, s>>>(g->prefix, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(g->ev[7], s));
+    rc = run_topk(g, k, p, FILTER_EDGES, out, n_out, stats);
+    if (!rc && stats) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g->ev[6], g->ev[7]) == hipSuccess) stats->sample_ms = ms;
+    }
+    if (!rc && stats) {
+        HIP_TRY(hipMemsetAsync(g->dcount + 8, 0, 8, s));
+        k_count_marks<<<enum_grid(g->m), 256, 0, s>>>(g->emark, g->m, g->dcount + 8);
+        HIP_TRY(hipMemcpyAsync(g->hcount + 8, g->dcount + 8, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        stats->distinct_sampled = g->hcount[8];
+        stats->total_ms = timer.ms();
+    }
+    if (!rc) set_error("");
+    return rc;
+}
+
+extern "C" int sample_heavy_triangles(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed,
+                                      tt_triangle *out, uint32_t *n_out) {
+    return sample_heavy_triangles_ex(g, k, p, budget, seed, out, n_out, nullptr);
+}

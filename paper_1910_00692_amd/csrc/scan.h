@@ -1,0 +1,7 @@
+// scan.h — prefix sums used by the CSR build and by weighted edge sampling.
+#pragma once
+#include "common.h"
+
+// Inclusive prefix sums of w_e^q over input edges e = 0..m-1 (weights read through opos).
+// q = 1: uint64_t[m]; q = 2 or 3: u128[m]; any other q: double[m].
+int inclusive_weight_prefix(tt_graph *g, double q, void *out);

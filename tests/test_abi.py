@@ -1,0 +1,69 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol include/topktri.h declares,
+and rejects bad arguments before touching the device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_1910_00692_amd as tt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "topktri.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tt.LIB_PATH):
+        tt.build()
+    return tt.library()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("graph_load", "topk_triangles", "sample_heavy_triangles", "graph_free", "tt_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(tt.EXPORTED)
+
+
+def test_struct_sizes():
+    assert ctypes.sizeof(tt.Triangle) == 24
+    text = open(HEADER).read()
+    assert "uint32_t i, j, l, _pad;" in text
+
+
+def test_argument_errors_before_device_work(lib):
+    h = ctypes.c_void_p()
+    assert lib.graph_load(3, 2, None, None, None, ctypes.byref(h)) == tt.TT_E_ARG
+    assert b"NULL" in lib.tt_last_error()
+    assert lib.graph_load(3, 0, None, None, None, None) == tt.TT_E_ARG
+    one = (ctypes.c_uint32 * 1)(0)
+    assert lib.graph_load(3, 2**32, one, one, one, ctypes.byref(h)) == tt.TT_E_TOO_LARGE
+    n_out = ctypes.c_uint32(7)
+    out = (tt.Triangle * 4)()
+    assert lib.topk_triangles(None, 4, 1.0, out, ctypes.byref(n_out)) == tt.TT_E_ARG
+    assert n_out.value == 0
+    assert lib.sample_heavy_triangles(None, 4, 1.0, 10, 1, out, ctypes.byref(n_out)) == tt.TT_E_ARG
+    lib.graph_free(None)  # NULL-safe
+    assert lib.graph_num_edges(None) == 0 and lib.graph_num_vertices(None) == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(tt, "_lib", None)
+    monkeypatch.setattr(tt, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(tt.LibraryMissing):
+        tt.library()

@@ -1,0 +1,62 @@
+"""Full-size parity on the 1M-vertex / 20M-edge workload (50 planted heavy 4-cliques), loaded
+from device-resident tensors exactly as bench.py does, at the four p of that workload and
+for edge sampling with 1e7 draws."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from paritylib import EdgeIndex, assert_parity, triples
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def medium():
+    import torch
+    import paper_1910_00692_amd as tt
+    g = graphgen.medium()
+    log(f"medium n={g.n} m={g.m}")
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(g.src.view(np.int32)).to(dev)
+    d = torch.from_numpy(g.dst.view(np.int32)).to(dev)
+    w = torch.from_numpy(g.w.view(np.int32)).to(dev)
+    G = tt.Graph(g.n, s, d, w, stream=torch.cuda.current_stream(dev))
+    yield g, G, EdgeIndex(g.src, g.dst, g.w)
+    G.close()
+
+
+@pytest.mark.parametrize("p", [-math.inf, 1.0, 2.0, math.inf])
+def test_medium_exact(medium, p):
+    g, G, ei = medium
+    log(f"medium exact p={p}")
+    got = G.topk(1000, p, with_stats=True)
+    want = oracle.topk(g.n, g.src, g.dst, g.w, 1000, p)
+    log(f"  stats {got['stats']}")
+    assert_parity(got, want, p, ei, ctx=f"medium p={p}")
+    # every planted 4-clique triangle has all weights >= 1000; at p = -inf they outrank all
+    # natural triangles whose lightest edge is below 1000
+    if p == -math.inf:
+        planted = set()
+        for c in g.planted.tolist():
+            c = sorted(c)
+            planted |= {(c[0], c[1], c[2]), (c[0], c[1], c[3]), (c[0], c[2], c[3]), (c[1], c[2], c[3])}
+        assert planted <= set(triples(got))
+
+
+@pytest.mark.parametrize("p", [1.0, -math.inf])
+def test_medium_sampling(medium, p):
+    g, G, ei = medium
+    log(f"medium sampling p={p}")
+    got = G.sample(1000, p, 10_000_000, seed=1234, with_stats=True)
+    want = oracle.sample_heavy_triangles(g.n, g.src, g.dst, g.w, 1000, p, 10_000_000, 1234)
+    log(f"  stats {got['stats']}")
+    assert got["stats"]["distinct_sampled"] == want["distinct_edges"]
+    assert_parity(got, want, p, ei, ctx=f"medium es p={p}")

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on seeded inputs.
+
+Covered: tiny random graphs at every p (many ties), the 2,000-node workload at every p and
+k from 1 to beyond the triangle count, candidate-buffer overflow and restart (K_300 with
+uniform weights: 4.45M tied triangles), planted heavy cliques, vertex-subset queries,
+validation errors, empty and degenerate graphs, device-pointer loads, determinism, and
+weighted edge sampling replayed draw for draw.
+"""
+import itertools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from paritylib import EdgeIndex, assert_parity, triples
+
+pytestmark = pytest.mark.gpu
+
+ALL_P = [-math.inf, -3.0, -1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, math.inf]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def tt():
+    import paper_1910_00692_amd as tt
+    tt.library()
+    return tt
+
+
+def rand_graph(rng, n, prob, wlo=1, whi=20):
+    iu = np.array(list(itertools.combinations(range(n), 2)), np.uint32).reshape(-1, 2)
+    keep = rng.random(len(iu)) < prob
+    e = iu[keep]
+    flip = rng.random(len(e)) < 0.5
+    src = np.where(flip, e[:, 1], e[:, 0]).astype(np.uint32)
+    dst = np.where(flip, e[:, 0], e[:, 1]).astype(np.uint32)
+    perm = rng.permutation(len(src))
+    w = rng.integers(wlo, whi + 1, len(src)).astype(np.uint32)
+    return src[perm], dst[perm], w
+
+
+def check(tt, n, s, d, w, k, p, G=None, subset=None, ctx=""):
+    own = G is None
+    if own:
+        G = tt.Graph(n, s, d, w)
+    try:
+        got = G.topk(k, p, subset=subset)
+    finally:
+        if own:
+            G.close()
+    vm = None
+    if subset is not None:
+        vm = np.zeros(n, np.uint8)
+        vm[np.asarray(subset, np.int64)] = 1
+    want = oracle.topk(n, s, d, w, k, p, vertex_mark=vm)
+    assert_parity(got, want, p, EdgeIndex(s, d, w), ctx=f"{ctx} k={k} p={p}")
+    return got, want
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tiny_random_graphs(tt, seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(3, 45))
+    s, d, w = rand_graph(rng, n, rng.uniform(0.1, 0.8), 1, int(rng.choice([3, 20, 10**6])))
+    log(f"tiny seed={seed} n={n} m={len(s)}")
+    with tt.Graph(n, s, d, w) as G:
+        for p in ALL_P:
+            for k in (1, 7, 60, 100000):
+                check(tt, n, s, d, w, k, p, G=G, ctx=f"tiny{seed}")
+
+
+@pytest.fixture(scope="module")
+def small(tt):
+    g = graphgen.small()
+    G = tt.Graph(g.n, g.src, g.dst, g.w)
+    yield g, G
+    G.close()
+
+
+@pytest.mark.parametrize("p", ALL_P)
+def test_small_workload(tt, small, p):
+    g, G = small
+    for k in (1, 100, 1000, 30000):
+        log(f"small p={p} k={k}")
+        got, want = check(tt, g.n, g.src, g.dst, g.w, k, p, G=G, ctx="small")
+    assert want["total"] == 21481 or want["total"] > 0
+
+
+def test_small_stats_and_determinism(tt, small):
+    g, G = small
+    a = G.topk(100, 1.0, with_stats=True)
+    b = G.topk(100, 1.0, with_stats=True)
+    assert triples(a) == triples(b) and np.array_equal(a["score"], b["score"])
+    st = a["stats"]
+    assert st["passes"] >= 1 and st["edges_streamed"] >= g.m and st["triangles_emitted"] >= 100
+    log(f"stats {st}")
+
+
+def test_overflow_restart_with_ties(tt):
+    """K_300 with one weight: 4,455,100 triangles tie at every p, more than the 4M-record
+    candidate buffer, so the query must restart above the k-th full key (score, i, j, l)."""
+    n = 300
+    s, d = (np.array(x, np.uint32) for x in zip(*itertools.combinations(range(n), 2)))
+    w = np.full(len(s), 5, np.uint32)
+    log("K300 uniform")
+    with tt.Graph(n, s, d, w) as G:
+        for p in (1.0, -math.inf, 0.5):
+            got = G.topk(100, p, with_stats=True)
+            want = list(itertools.islice(itertools.combinations(range(n), 3), 100))
+            assert triples(got) == want
+            assert np.all(got["score"] == 5.0)
+            assert got["stats"]["restarts"] >= 1, got["stats"]
+
+
+def test_planted_cliques(tt):
+    g = graphgen.chung_lu(20000, 200000, 2.2, 1.8, seed=3, plant=8, plant_size=4, plant_mult=1000)
+    log(f"planted m={g.m}")
+    with tt.Graph(g.n, g.src, g.dst, g.w) as G:
+        for p in (-math.inf, 0.0, 1.0, 2.0, math.inf, -1.0, 1.5):
+            check(tt, g.n, g.src, g.dst, g.w, 64, p, G=G, ctx="planted")
+
+
+def test_subset_queries(tt, small):
+    g, G = small
+    rng = np.random.default_rng(5)
+    for size in (1, 10, 300):
+        sub = rng.choice(g.n, size=size, replace=False).astype(np.uint32)
+        for p in (1.0, -math.inf, 2.0, -1.0):
+            log(f"subset size={size} p={p}")
+            check(tt, g.n, g.src, g.dst, g.w, 50, p, G=G, subset=sub, ctx=f"subset{size}")
+
+
+def test_validation_errors(tt):
+    cases = [
+        (3, [0, 1], [1, 1], [1, 1]),
+        (3, [0, 1], [1, 0], [1, 1]),
+        (3, [0, 1], [1, 2], [1, 0]),
+        (3, [0, 1], [1, 3], [1, 1]),
+        (4, [0, 1, 2, 0], [1, 2, 0, 1], [1, 1, 1, 1]),
+    ]
+    for n, s, d, w in cases:
+        want = oracle.validate(n, s, d, w)
+        with pytest.raises(tt.TopKError) as e:
+            tt.Graph(n, s, d, w)
+        assert e.value.code == want, (s, d, w, e.value.code, want)
+
+
+def test_empty_and_degenerate(tt):
+    with tt.Graph(5, [], [], []) as G:
+        assert G.topk(10, 1.0)["n_out"] == 0
+        assert G.sample(10, 1.0, 100, 1)["n_out"] == 0
+    with tt.Graph(0, [], [], []) as G:
+        assert G.topk(10, 1.0)["n_out"] == 0
+    # a tree: no triangles
+    n = 200
+    s = np.arange(1, n, dtype=np.uint32)
+    d = (np.arange(1, n) // 2).astype(np.uint32)
+    with tt.Graph(n, s, d, np.ones(n - 1, np.uint32)) as G:
+        assert G.topk(10, 1.0)["n_out"] == 0
+    # one triangle, k = 0 and k > T
+    with tt.Graph(4, [0, 1, 2, 2], [1, 2, 0, 3], [5, 6, 7, 1]) as G:
+        assert G.topk(0, 1.0)["n_out"] == 0
+        r = G.topk(10, 1.0)
+        assert r["n_out"] == 1 and triples(r) == [(0, 1, 2)] and r["score"][0] == 6.0
+    # largest weights: keys need 96 bits (product) and 66 bits (sum of squares)
+    big = 2**32 - 1
+    s, d, w = [0, 1, 2, 3, 3], [1, 2, 0, 0, 1], [big, big - 1, big, 1, 2]
+    for p in ALL_P:
+        check(tt, 4, np.array(s, np.uint32), np.array(d, np.uint32), np.array(w, np.uint32), 5, p, ctx="bigw")
+
+
+def test_device_pointer_load(tt, small):
+    import torch
+    g, G = small
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(g.src.astype(np.int32)).to(dev)
+    d = torch.from_numpy(g.dst.astype(np.int32)).to(dev)
+    w = torch.from_numpy(g.w.astype(np.int32)).to(dev)
+    with tt.Graph(g.n, s, d, w) as G2:
+        for p in (1.0, math.inf):
+            a, b = G.topk(500, p), G2.topk(500, p)
+            assert triples(a) == triples(b) and np.array_equal(a["score"], b["score"])
+
+
+# ------------------------------------------------------------------------------ sampling
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sampling_replay_tiny(tt, seed):
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(6, 40))
+    s, d, w = rand_graph(rng, n, rng.uniform(0.2, 0.7), 1, int(rng.choice([5, 1000])))
+    log(f"es tiny seed={seed} n={n} m={len(s)}")
+    ei = EdgeIndex(s, d, w)
+    with tt.Graph(n, s, d, w) as G:
+        for p in (1.0, 2.0, 3.0, -math.inf, math.inf, 0.0, -1.0):
+            for budget in (1, 5, 50, 5000):
+                got = G.sample(30, p, budget, seed=seed * 7 + 1)
+                want = oracle.sample_heavy_triangles(n, s, d, w, 30, p, budget, seed * 7 + 1)
+                assert_parity(got, want, p, ei, ctx=f"es seed={seed} p={p} budget={budget}")
+
+
+@pytest.mark.parametrize("p", [1.0, 2.0, -math.inf, math.inf])
+def test_sampling_small_workload(tt, small, p):
+    g, G = small
+    ei = EdgeIndex(g.src, g.dst, g.w)
+    for budget, seed in ((100, 1), (10000, 2), (200000, 3)):
+        log(f"es small p={p} budget={budget}")
+        got = G.sample(100, p, budget, seed, with_stats=True)
+        want = oracle.sample_heavy_triangles(g.n, g.src, g.dst, g.w, 100, p, budget, seed)
+        assert_parity(got, want, p, ei, ctx=f"es small p={p} budget={budget}")
+        assert got["stats"]["distinct_sampled"] == want["distinct_edges"]
+
+
+def test_sampling_converges_to_exact(tt, small):
+    g, G = small
+    exact = G.topk(100, 1.0)
+    es = G.sample(100, 1.0, 50_000_000, 11)
+    assert triples(es) == triples(exact)
