@@ -43,33 +43,55 @@ struct tt_graph {
     hipStream_t stream = nullptr;
     bool owns_stream = false;
     int device = 0;
-    // degree-oriented CSR: an entry u->v exists iff (deg u, u) < (deg v, v); rows sorted by v
-    uint64_t *rowp = nullptr;   // [n+1]
-    uint32_t *col = nullptr;    // [m] head vertex v (original ID)
+    // Degree-oriented CSR: an entry u->v exists iff (deg u, u) < (deg v, v).  Rows are laid out
+    // in descending order of the row bound hb (grouped by weight_bin(hb)), so that the rows
+    // that can hold a triangle of score >= t form a prefix of the entry arrays.
+    uint64_t *rstart = nullptr; // [n+1] first entry of u's row
+    uint32_t *rlen = nullptr;   // [n+1] out-degree of u
+    uint32_t *col = nullptr;    // [m] head vertex v (original ID); rows sorted by v
     uint32_t *wgt = nullptr;    // [m] edge weight
     uint32_t *osrc = nullptr;   // [m] tail vertex u of each entry
     uint32_t *eid = nullptr;    // [m] input edge index of each entry
     uint32_t *opos = nullptr;   // [m] entry position of each input edge
+    uint32_t *wcol = nullptr;   // [m] the same rows sorted by weight descending (then head ID)
+    uint32_t *wwgt = nullptr;   // [m]
+    uint32_t *wpos = nullptr;   // [m] position of each weight-sorted entry in the head-sorted row
+    // The same entries in descending weight_bin(weight) order: for a band in which every edge
+    // of a qualifying triangle must weigh >= z, the entries that can be its base are a prefix.
+    uint32_t *ws_src = nullptr, *ws_col = nullptr, *ws_wgt = nullptr;
+    uint32_t *ws_pos = nullptr; // head-sorted position of each such entry
+    std::vector<uint64_t> wbase; // host: first entry of each weight bin (bins descending)
     uint32_t *maxw = nullptr;   // [n] largest weight in u's out-row (0 for an empty row)
+    uint32_t *hb = nullptr;     // [n] max(maxw[u], maxw[v] over out-neighbours v): bounds every
+                                //     triangle based at u, for every p
     uint32_t *deg = nullptr;    // [n] undirected degree
     uint32_t wmax = 0;          // largest weight in the graph
     uint32_t max_outdeg = 0;
-    std::vector<uint64_t> whist; // host copy of the weight histogram (see weight_bin)
+    std::vector<uint64_t> whist; // host: edge count per weight_bin(w)
+    std::vector<uint64_t> ebin;  // host: entry count per weight_bin(hb[tail])
+    std::vector<uint64_t> ebase; // host: first entry of each bin (bins in descending order)
     uint64_t bytes = 0;
     // query scratch, grown on demand and kept for later queries
     trec *buf0 = nullptr, *buf1 = nullptr;
     uint64_t buf_cap = 0;
-    unsigned long long *dcount = nullptr; // [8] counters
+    unsigned long long *dcount = nullptr; // [16] counters
     unsigned long long *hcount = nullptr; // pinned mirror
     tt_triangle *dout = nullptr;
     uint64_t dout_cap = 0;
     uint8_t *emark = nullptr;   // [m] per-entry marks (sampling)
     uint8_t *vflag = nullptr;   // [n]
     uint8_t *vflag2 = nullptr;  // [n]
-    // sampling prefix sums, cached per exponent
-    double prefix_q = -1.0;
-    void *prefix = nullptr;     // u64 (q=1), u128 (q=2,3) or double (other q)
+    // sampling tables, cached for the two most recent exponents q
+    struct SampleTable {
+        double q = -1.0;
+        void *prefix = nullptr;   // u64 (q=1), u128 (q=2,3) or double (other q), [m]
+        uint32_t *guide = nullptr; // [2^bits + 1] first candidate edge per top-bits bucket
+        uint64_t last_use = 0;
+    } tables[2];
+    uint32_t guide_bits = 0;
+    uint64_t use_clock = 0;
     hipEvent_t ev[8] = {};
+    std::vector<hipEvent_t> band_ev; // start/stop pairs of the enumeration passes of a query
     std::mutex mu;
 };
 

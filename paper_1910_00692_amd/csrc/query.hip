@@ -91,12 +91,19 @@ struct Band {
 // key(a, Wu, Wv) >= L : no triangle on this entry can reach the band otherwise
 __device__ __forceinline__ bool bound_ok(const Band &B, uint32_t a, uint32_t Wu, uint32_t Wv) {
     if (B.L == 0) return true;
-    if (B.mode == MODE_GEN) return gen_mean(B.p, (double)a, (double)Wu, (double)Wv) >= B.theta * (1.0 - 1e-12);
+    if (B.mode == MODE_GEN) {
+        // cheap upper bounds first: m_p <= max for every p, m_p <= arithmetic mean for p <= 1
+        const double lim = B.theta * (1.0 - 1e-12);
+        const double da = (double)a, du = (double)Wu, dv = (double)Wv;
+        if (fmax(da, fmax(du, dv)) < lim) return false;
+        if (B.p <= 1.0 && (da + du + dv) / 3.0 < lim * (1.0 - 1e-12)) return false;
+        return gen_mean(B.p, da, du, dv) >= lim;
+    }
     return score_key(B.mode, B.p, a, Wu, Wv) >= B.L;
 }
 
 // Smallest weight x (never above the exact one) with m_p(a, x, W) >= theta, generic p.
-__device__ uint64_t gen_min_other(double p, double theta, double a, double W) {
+__host__ __device__ uint64_t gen_min_other(double p, double theta, double a, double W) {
     if (p > 0.0) {
         const double s = fmax(theta, fmax(a, W));
         const double t3 = 3.0 * pow(theta / s, p);
@@ -154,42 +161,66 @@ enum { FILTER_NONE = 0, FILTER_EDGES = 1, FILTER_VERTICES = 2 };
 enum { FL_MARK_UV = 1, FL_REQ_A = 2, FL_REQ_B = 4, FL_REQ_C = 8 };
 
 struct EnumArgs {
-    const uint64_t *rowp;
-    const uint32_t *osrc, *col, *wgt, *maxw;
-    uint64_t m;
+    const uint64_t *rstart;
+    const uint32_t *rlen, *col, *wgt, *wcol, *wwgt, *wpos, *maxw;
+    // the stream of candidate entries (tail, head, weight, head-sorted position or NULL if the
+    // stream is the head-sorted layout itself) and its length
+    const uint32_t *s_src, *s_col, *s_wgt, *s_pos;
+    uint64_t E;
+    const unsigned long long *skip; // set (between passes) once the answer is complete
     Band B;
-    const uint8_t *emark;  // FILTER_EDGES: drawn entries
+    const uint8_t *emark;  // FILTER_EDGES: drawn entries (head-sorted positions)
     const uint8_t *vflag;  // FILTER_EDGES: vertex has a drawn out-entry; FILTER_VERTICES: vertex in subset
     const uint8_t *vflag2; // FILTER_VERTICES: vertex has an out-neighbour in the subset
     trec *out;
     unsigned long long *count;
     uint64_t cap;
-    unsigned long long *stats; // [0] candidates [1] intersected entries [2] emitted [3] streamed
+    unsigned long long *stats; // [0] candidates [1] intersected entries [2] emitted [3] streamed [4] passes
 };
 
-// Persistent waves walk the oriented entries in chunks of 64 (one lane per entry).  Entries
-// that survive the bound test are intersected cooperatively: the wave flattens the
-// (entry, element of its shorter row) pairs of the whole chunk, so all 64 lanes stay busy,
-// and each lane binary-searches its element in the longer row.
+// Number of entries of a weight-sorted (descending) row with weight >= z.
+__device__ __forceinline__ uint32_t count_at_least(const uint32_t *ww, uint64_t b, uint32_t len, uint64_t z) {
+    if (z == 0) return len;
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)ww[b + mid] >= z) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Persistent waves walk the first E oriented entries in chunks of 64 (one lane per entry).
+// An entry u->v that passes the bound test gets the weight floors zu (for w_uc) and zv (for
+// w_vc); the entries of each row at or above its floor are a prefix of the weight-sorted copy
+// of the row.  The side with fewer such entries is iterated: the wave flattens the
+// (entry, qualifying element) pairs of the whole chunk across its 64 lanes, and each lane
+// binary-searches its element in the other row's head-sorted copy.
 template <int FILTER> __global__ __launch_bounds__(256) void k_enum(EnumArgs A) {
+    // a band after the one that completed the answer has nothing to do; the flag is written
+    // only between passes, never while this pass appends to the buffer
+    if (A.skip && *A.skip) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&A.stats[3], (unsigned long long)A.E);
+        atomicAdd(&A.stats[4], 1ull);
+    }
     const int lane = threadIdx.x & 63;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    const uint64_t nchunks = (A.m + 63) >> 6;
-    unsigned long long s_cand = 0, s_inter = 0, s_emit = 0, s_stream = 0;
+    const uint64_t nchunks = (A.E + 63) >> 6;
+    unsigned long long s_cand = 0, s_inter = 0, s_emit = 0;
     for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
         const uint64_t e = (ch << 6) + (uint64_t)lane;
         bool pass = false;
-        uint32_t a = 0, u = 0, v = 0, Alen = 0, Blen = 0, fl = 0;
-        uint64_t Ab = 0, Bb = 0, zA = 0, zB = 0;
-        if (e < A.m) {
-            u = A.osrc[e];
-            v = A.col[e];
-            a = A.wgt[e];
+        uint32_t a = 0, u = 0, v = 0, qA = 0, Blen = 0, fl = 0;
+        uint64_t Ab = 0, Bb = 0, zB = 0;
+        if (e < A.E) {
+            u = A.s_src[e];
+            v = A.s_col[e];
+            a = A.s_wgt[e];
             const uint32_t Wu = A.maxw[u], Wv = A.maxw[v];
             bool pre = true;
             if (FILTER == FILTER_EDGES) {
-                if (A.emark[e]) fl |= FL_MARK_UV;
+                if (A.emark[A.s_pos ? A.s_pos[e] : e]) fl |= FL_MARK_UV;
                 pre = (fl & FL_MARK_UV) || A.vflag[u] || A.vflag[v];
             } else if (FILTER == FILTER_VERTICES) {
                 const bool su = A.vflag[u], sv = A.vflag[v];
@@ -198,33 +229,34 @@ template <int FILTER> __global__ __launch_bounds__(256) void k_enum(EnumArgs A) 
             }
             pass = pre && bound_ok(A.B, a, Wu, Wv);
             if (pass) {
-                const uint64_t ub = A.rowp[u], ue = A.rowp[u + 1], vb = A.rowp[v], ve = A.rowp[v + 1];
                 const uint64_t zu = min_other(A.B, a, Wv), zv = min_other(A.B, a, Wu);
-                const bool uA = (ue - ub) <= (ve - vb);
+                const uint64_t ub = A.rstart[u], vb = A.rstart[v];
+                const uint32_t ul = A.rlen[u], vl = A.rlen[v];
+                const uint32_t qu = (zu > Wu) ? 0 : count_at_least(A.wwgt, ub, ul, zu);
+                const uint32_t qv = (qu == 0 || zv > Wv) ? 0 : count_at_least(A.wwgt, vb, vl, zv);
+                const bool uA = qu <= qv;
+                qA = uA ? qu : qv;
                 Ab = uA ? ub : vb;
-                Alen = (uint32_t)(uA ? ue - ub : ve - vb);
                 Bb = uA ? vb : ub;
-                Blen = (uint32_t)(uA ? ve - vb : ue - ub);
-                zA = uA ? zu : zv;
+                Blen = uA ? vl : ul;
                 zB = uA ? zv : zu;
-                if (zu > Wu || zv > Wv || Alen == 0 || Blen == 0) pass = false;
+                if (qu == 0 || qv == 0) pass = false;
                 if (FILTER == FILTER_EDGES && !(fl & FL_MARK_UV)) {
-                    // a drawn edge must be among the other two
+                    // a drawn edge must be one of the other two
                     const bool fa = A.vflag[uA ? u : v], fb = A.vflag[uA ? v : u];
                     if (!fa && !fb) pass = false;
-                    if (!fb) fl |= FL_REQ_A; // only drawn entries of the A row can help
+                    if (!fb) fl |= FL_REQ_A; // only drawn entries of the iterated row can help
                     if (!fa) fl |= FL_REQ_B;
                 }
             }
         }
-        const uint32_t work = pass ? Alen : 0;
+        const uint32_t work = pass ? qA : 0;
         const uint32_t incl = wave_incl_scan(work);
         const uint32_t total = __shfl(incl, 63, 64);
         const uint64_t pb = __ballot(pass);
         if (lane == 0) {
             s_cand += __popcll(pb);
             s_inter += total;
-            s_stream += (A.m - (ch << 6)) < 64 ? (A.m - (ch << 6)) : 64;
         }
         for (uint32_t base = 0; base < total; base += 64) {
             const uint32_t t = base + (uint32_t)lane;
@@ -236,18 +268,21 @@ template <int FILTER> __global__ __launch_bounds__(256) void k_enum(EnumArgs A) 
                 if (im <= tt) s += step;
             }
             const uint32_t o_incl = __shfl(incl, s, 64), o_work = __shfl(work, s, 64);
-            const uint64_t oAb = __shfl(Ab, s, 64), oBb = __shfl(Bb, s, 64);
-            const uint64_t ozA = __shfl(zA, s, 64), ozB = __shfl(zB, s, 64);
+            const uint64_t oAb = __shfl(Ab, s, 64), oBb = __shfl(Bb, s, 64), ozB = __shfl(zB, s, 64);
             const uint32_t oBlen = __shfl(Blen, s, 64), oa = __shfl(a, s, 64), ou = __shfl(u, s, 64),
                            ov = __shfl(v, s, 64), ofl = __shfl(fl, s, 64);
             bool ok = false;
             trec r;
             if (t < total) {
                 const uint64_t pa = oAb + (tt - (o_incl - o_work));
-                const uint32_t c = A.col[pa], x = A.wgt[pa];
-                bool go = (uint64_t)x >= ozA;
-                if (FILTER == FILTER_VERTICES && (ofl & FL_REQ_C)) go = go && A.vflag[c];
-                if (FILTER == FILTER_EDGES && (ofl & FL_REQ_A)) go = go && A.emark[pa];
+                const uint32_t c = A.wcol[pa], x = A.wwgt[pa];
+                bool go = true;
+                if (FILTER == FILTER_VERTICES && (ofl & FL_REQ_C)) go = A.vflag[c];
+                uint8_t markA = 0;
+                if (FILTER == FILTER_EDGES) {
+                    markA = A.emark[A.wpos[pa]];
+                    if (ofl & FL_REQ_A) go = markA;
+                }
                 if (go) {
                     uint64_t lo = oBb, hi = oBb + oBlen;
                     while (lo < hi) {
@@ -258,8 +293,9 @@ template <int FILTER> __global__ __launch_bounds__(256) void k_enum(EnumArgs A) 
                         const uint32_t y = A.wgt[lo];
                         bool adm = (uint64_t)y >= ozB;
                         if (FILTER == FILTER_EDGES) {
-                            if (ofl & FL_REQ_B) adm = adm && A.emark[lo];
-                            adm = adm && ((ofl & FL_MARK_UV) || A.emark[pa] || A.emark[lo]);
+                            const uint8_t markB = A.emark[lo];
+                            if (ofl & FL_REQ_B) adm = adm && markB;
+                            adm = adm && ((ofl & FL_MARK_UV) || markA || markB);
                         }
                         if (adm) {
                             const u128 key = score_key(A.B.mode, A.B.p, oa, x, y);
@@ -291,8 +327,13 @@ template <int FILTER> __global__ __launch_bounds__(256) void k_enum(EnumArgs A) 
         if (s_cand) atomicAdd(&A.stats[0], s_cand);
         if (s_inter) atomicAdd(&A.stats[1], s_inter);
         if (s_emit) atomicAdd(&A.stats[2], s_emit);
-        if (s_stream) atomicAdd(&A.stats[3], s_stream);
     }
+}
+
+// Between two passes: the later bands are skipped once the buffer holds >= k triangles (the
+// answer is complete) or has overflowed (the host restarts).
+__global__ void k_band_gate(const unsigned long long *count, unsigned long long k, unsigned long long *skip) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *count >= k) *skip = 1;
 }
 
 // ----------------------------------------------------------------------------- selection
@@ -374,8 +415,30 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t s) {
     return z ^ (z >> 31);
 }
 
-template <typename T> __device__ __forceinline__ uint64_t first_above(const T *P, uint64_t m, T r) {
-    uint64_t lo = 0, hi = m - 1;
+// The draw rule: the edge picked by the 64-bit uniform x is the first e with prefix[e] > r(x),
+// r(x) = floor(x * Z / 2^64) (integer prefix) or (x >> 11) * 2^-53 * Z (FP64 prefix).
+// KIND 0: u64 prefix (q = 1); 1: u128 prefix (q = 2, 3); 2: FP64 prefix.
+template <int KIND> struct Draw;
+template <> struct Draw<0> {
+    typedef uint64_t T;
+    static __device__ __forceinline__ T r(const T *P, uint64_t m, uint64_t x) { return __umul64hi(x, P[m - 1]); }
+};
+template <> struct Draw<1> {
+    typedef u128 T;
+    static __device__ __forceinline__ T r(const T *P, uint64_t m, uint64_t x) {
+        const u128 Z = P[m - 1];
+        return ((u128)x * (uint64_t)(Z >> 64)) + (u128)__umul64hi(x, (uint64_t)Z);
+    }
+};
+template <> struct Draw<2> {
+    typedef double T;
+    static __device__ __forceinline__ T r(const T *P, uint64_t m, uint64_t x) {
+        return (double)(x >> 11) * (1.0 / 9007199254740992.0) * P[m - 1];
+    }
+};
+
+// first e in [lo, hi] with P[e] > r (the answer is known to lie in that range)
+template <typename T> __device__ __forceinline__ uint64_t first_above(const T *P, uint64_t lo, uint64_t hi, T r) {
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
         if (P[mid] > r) hi = mid; else lo = mid + 1;
@@ -383,28 +446,31 @@ template <typename T> __device__ __forceinline__ uint64_t first_above(const T *P
     return lo;
 }
 
-// KIND 0: u64 prefix (q = 1); 1: u128 prefix (q = 2, 3); 2: FP64 prefix.
+// Guide table (cut points): G[j] = the edge picked by x = j * 2^(64-bits), j = 0 .. 2^bits - 1,
+// and G[2^bits] = m - 1.  The draw rule is monotone in x, so every x in bucket j picks an edge
+// in [G[j], G[j+1]]; a draw then searches only that range, with the same result.
 template <int KIND>
-__global__ __launch_bounds__(256) void k_es_draw(const void *prefix, uint64_t m, uint64_t budget, uint64_t seed,
-                                                 const uint32_t *opos, const uint32_t *osrc, uint8_t *emark,
-                                                 uint8_t *vflag) {
+__global__ __launch_bounds__(256) void k_es_guide(const void *prefix, uint64_t m, uint32_t bits, uint32_t *G) {
+    typedef typename Draw<KIND>::T T;
+    const T *P = (const T *)prefix;
+    const uint64_t nb = 1ull << bits;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= nb; j += (uint64_t)gridDim.x * blockDim.x) {
+        if (j == nb) { G[j] = (uint32_t)(m - 1); continue; }
+        const uint64_t x = j << (64 - bits);
+        G[j] = (uint32_t)first_above<T>(P, 0, m - 1, Draw<KIND>::r(P, m, x));
+    }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_es_draw(const void *prefix, const uint32_t *G, uint32_t bits, uint64_t m,
+                                                 uint64_t budget, uint64_t seed, const uint32_t *opos,
+                                                 const uint32_t *osrc, uint8_t *emark, uint8_t *vflag) {
+    typedef typename Draw<KIND>::T T;
+    const T *P = (const T *)prefix;
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < budget; s += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t x = splitmix64_at(seed, s);
-        uint64_t e;
-        if (KIND == 0) {
-            const uint64_t *P = (const uint64_t *)prefix;
-            e = first_above<uint64_t>(P, m, __umul64hi(x, P[m - 1]));
-        } else if (KIND == 1) {
-            const u128 *P = (const u128 *)prefix;
-            const u128 Z = P[m - 1];
-            const uint64_t Zh = (uint64_t)(Z >> 64), Zl = (uint64_t)Z;
-            const u128 r = ((u128)x * Zh) + (u128)__umul64hi(x, Zl);
-            e = first_above<u128>(P, m, r);
-        } else {
-            const double *P = (const double *)prefix;
-            const double r = (double)(x >> 11) * (1.0 / 9007199254740992.0) * P[m - 1];
-            e = first_above<double>(P, m, r);
-        }
+        const uint64_t j = x >> (64 - bits);
+        const uint64_t e = first_above<T>(P, G[j], G[j + 1], Draw<KIND>::r(P, m, x));
         const uint32_t pos = opos[e];
         emark[pos] = 1;
         vflag[osrc[pos]] = 1;
@@ -536,14 +602,107 @@ int select_topk(tt_graph *g, uint64_t N, uint32_t k, trec **res) {
     return TT_OK;
 }
 
-int launch_enum(tt_graph *g, const Band &B, int filter, tt_query_stats *st) {
+// An integer t <= the score of any triangle whose key is >= L (so rows with hb < t can be
+// skipped): the score of key L, rounded down, lowered once more for the inexact roots.
+uint64_t score_floor(int mode, u128 L) {
+    if (L == 0) return 0;
+    double v;
+    switch (mode) {
+    case MODE_MAX:
+    case MODE_MIN: return (uint64_t)L;
+    case MODE_SUM: return (uint64_t)(L / 3);
+    case MODE_SUMSQ: v = std::sqrt((double)L / 3.0); break;
+    case MODE_PROD: v = std::cbrt((double)L); break;
+    default: v = key_as_double(L) * (1.0 - 1e-9); break;
+    }
+    if (!(v > 1.0)) return 0;
+    const uint64_t f = (uint64_t)std::floor(v);
+    return f > 0 ? f - 1 : 0;
+}
+
+// Entries to stream for a band with lower key L: every row whose bin is >= bin(score floor).
+uint64_t entries_for(const tt_graph *g, int mode, u128 L) {
+    const uint64_t t = score_floor(mode, L);
+    if (t == 0) return g->m;
+    if (t > 0xFFFFFFFFull) return 0;
+    const uint32_t b = weight_bin((uint32_t)t);
+    return g->ebase[b] + g->ebin[b];
+}
+
+// The lightest edge of any triangle whose key is >= L weighs at least this (a lower bound):
+// with the other two edges at the graph's largest weight W, key(W, W, z) must still reach L.
+uint64_t weight_floor(int mode, double p, u128 L, uint32_t W) {
+    if (L == 0) return 0;
+    switch (mode) {
+    case MODE_MAX: return 0;
+    case MODE_MIN: return (uint64_t)L;
+    case MODE_SUM: {
+        const u128 w2 = (u128)2 * W;
+        return L > w2 ? (uint64_t)(L - w2) : 0;
+    }
+    case MODE_SUMSQ: {
+        const u128 w2 = (u128)2 * ((uint64_t)W * W);
+        if (L <= w2) return 0;
+        const uint64_t z = (uint64_t)std::sqrt((double)(L - w2));
+        return z > 1 ? z - 1 : 0;
+    }
+    case MODE_PROD: {
+        const double q = (double)L / ((double)W * (double)W);
+        if (q <= 1.0) return 0;
+        const uint64_t z = q >= 1.8e19 ? ~0ull : (uint64_t)q;
+        return z > 1 ? z - 1 : 0;
+    }
+    default: return gen_min_other(p, key_as_double(L), (double)W, (double)W);
+    }
+}
+
+struct Stream {
+    const uint32_t *src, *col, *wgt, *pos;
+    uint64_t E;
+};
+
+// The shorter of the two streams that hold every possible base entry of a band triangle:
+// rows with hb >= score floor (row order), or entries with weight >= weight floor.
+Stream pick_stream(const tt_graph *g, int mode, double p, u128 L) {
+    Stream r{g->osrc, g->col, g->wgt, nullptr, entries_for(g, mode, L)};
+    const uint64_t z = weight_floor(mode, p, L, g->wmax);
+    uint64_t E2 = g->m;
+    if (z > 0xFFFFFFFFull) E2 = 0;
+    else if (z > 0) {
+        const uint32_t b = weight_bin((uint32_t)z);
+        E2 = g->wbase[b] + g->whist[b];
+    }
+    if (E2 < r.E) r = Stream{g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, E2};
+    return r;
+}
+
+int ensure_band_events(tt_graph *g, size_t pairs) {
+    while (g->band_ev.size() < 2 * pairs) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return fail(TT_E_DEVICE, "hipEventCreate failed");
+        g->band_ev.push_back(e);
+    }
+    return TT_OK;
+}
+
+// Enqueues one enumeration pass (no host synchronisation); `slot` picks its event pair.
+int launch_enum(tt_graph *g, const Band &B, int filter, bool gated, size_t slot) {
+    const Stream S = pick_stream(g, B.mode, B.p, B.L);
     EnumArgs A;
-    A.rowp = g->rowp;
-    A.osrc = g->osrc;
+    A.rstart = g->rstart;
+    A.rlen = g->rlen;
     A.col = g->col;
     A.wgt = g->wgt;
+    A.wcol = g->wcol;
+    A.wwgt = g->wwgt;
+    A.wpos = g->wpos;
     A.maxw = g->maxw;
-    A.m = g->m;
+    A.s_src = S.src;
+    A.s_col = S.col;
+    A.s_wgt = S.wgt;
+    A.s_pos = S.pos;
+    A.E = S.E;
+    A.skip = gated ? g->dcount + 7 : nullptr;
     A.B = B;
     A.emark = g->emark;
     A.vflag = g->vflag;
@@ -552,22 +711,25 @@ int launch_enum(tt_graph *g, const Band &B, int filter, tt_query_stats *st) {
     A.count = g->dcount;
     A.cap = g->buf_cap;
     A.stats = g->dcount + 1;
-    const unsigned grid = enum_grid(g->m);
-    HIP_TRY(hipEventRecord(g->ev[4], g->stream));
-    if (filter == FILTER_EDGES) k_enum<FILTER_EDGES><<<grid, 256, 0, g->stream>>>(A);
-    else if (filter == FILTER_VERTICES) k_enum<FILTER_VERTICES><<<grid, 256, 0, g->stream>>>(A);
-    else k_enum<FILTER_NONE><<<grid, 256, 0, g->stream>>>(A);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(g->ev[5], g->stream));
-    if (st) st->passes++;
+    HIP_TRY(hipEventRecord(g->band_ev[2 * slot], g->stream));
+    if (S.E) {
+        const unsigned grid = enum_grid(S.E);
+        if (filter == FILTER_EDGES) k_enum<FILTER_EDGES><<<grid, 256, 0, g->stream>>>(A);
+        else if (filter == FILTER_VERTICES) k_enum<FILTER_VERTICES><<<grid, 256, 0, g->stream>>>(A);
+        else k_enum<FILTER_NONE><<<grid, 256, 0, g->stream>>>(A);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipEventRecord(g->band_ev[2 * slot + 1], g->stream));
     return TT_OK;
 }
 
-// After the stream has been synchronised: add the last enumeration launch's duration.
-void add_enum_time(tt_graph *g, tt_query_stats *st) {
+// After the stream has been synchronised: add the durations of passes [0, n).
+void add_enum_time(tt_graph *g, tt_query_stats *st, size_t n) {
     if (!st) return;
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, g->ev[4], g->ev[5]) == hipSuccess) st->enum_kernel_ms += ms;
+    for (size_t i = 0; i < n; i++) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g->band_ev[2 * i], g->band_ev[2 * i + 1]) == hipSuccess) st->enum_kernel_ms += ms;
+    }
 }
 
 Band make_band(int mode, double p, u128 L, uint32_t Li, uint32_t Lj, uint32_t Ll, bool hasU, u128 U) {
@@ -600,24 +762,24 @@ int run_topk(tt_graph *g, uint32_t k, double p, int filter, tt_triangle *out, ui
         if (M > g->m) break;
     }
     Ls.push_back(0); // exhaustive
+    if ((rc = ensure_band_events(g, Ls.size()))) return rc;
     HIP_TRY(hipMemsetAsync(g->dcount, 0, 8 * sizeof(unsigned long long), s));
     HIP_TRY(hipEventRecord(g->ev[0], s));
-    uint64_t cnt = 0;
-    bool overflow = false;
-    u128 U = 0;
-    bool hasU = false;
+    // all bands are enqueued at once; a band finds the buffer already holding >= k triangles
+    // (the answer is complete) or overflowed, and returns at once
     for (size_t i = 0; i < Ls.size(); i++) {
-        rc = launch_enum(g, make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, hasU, U), filter, st);
+        if (i > 0) {
+            k_band_gate<<<1, 64, 0, s>>>(g->dcount, k, g->dcount + 7);
+            HIP_TRY(hipGetLastError());
+        }
+        rc = launch_enum(g, make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, i > 0, i > 0 ? Ls[i - 1] : 0), filter, true, i);
         if (rc) return rc;
-        HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        add_enum_time(g, st);
-        cnt = g->hcount[0];
-        if (cnt > g->buf_cap) { overflow = true; break; }
-        if (cnt >= k) break;
-        U = Ls[i];
-        hasU = true;
     }
+    HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    add_enum_time(g, st, Ls.size());
+    uint64_t cnt = g->hcount[0];
+    bool overflow = cnt > g->buf_cap;
     double sel_ms = 0.0;
     while (overflow) {
         // the k-th best of the records kept is a lower bound on the k-th best overall
@@ -633,12 +795,12 @@ int run_topk(tt_graph *g, uint32_t k, double p, int filter, tt_triangle *out, ui
         (void)hipEventElapsedTime(&ms, g->ev[2], g->ev[3]);
         sel_ms += ms;
         const u128 L = ((u128)kth.khi << 64) | kth.klo;
-        rc = launch_enum(g, make_band(mode, p, L, kth.i, kth.j, kth.l, false, 0), filter, st);
+        rc = launch_enum(g, make_band(mode, p, L, kth.i, kth.j, kth.l, false, 0), filter, false, 0);
         if (rc) return rc;
         if (st) st->restarts++;
         HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        add_enum_time(g, st);
+        add_enum_time(g, st, 1);
         cnt = g->hcount[0];
         overflow = cnt > g->buf_cap;
     }
@@ -666,6 +828,7 @@ int run_topk(tt_graph *g, uint32_t k, double p, int filter, tt_triangle *out, ui
         st->intersected_entries += g->hcount[2];
         st->triangles_emitted += g->hcount[3];
         st->edges_streamed += g->hcount[4];
+        st->passes += (uint32_t)g->hcount[5];
     }
     return TT_OK;
 }
@@ -684,6 +847,35 @@ int check_query(tt_graph *g, double p, tt_triangle *out, uint32_t k, uint32_t *n
     if (!n_out) return fail(TT_E_ARG, "n_out is NULL");
     if (std::isnan(p)) return fail(TT_E_ARG, "p is NaN");
     if (k && !out) return fail(TT_E_ARG, "out is NULL");
+    return TT_OK;
+}
+
+// Prefix sums of w^q (input order) and their guide table, for the two most recent q.
+int sample_table(tt_graph *g, double q, int kind, tt_graph::SampleTable **out) {
+    g->use_clock++;
+    for (auto &t : g->tables)
+        if (t.q == q && t.prefix) { t.last_use = g->use_clock; *out = &t; return TT_OK; }
+    tt_graph::SampleTable *t = &g->tables[0];
+    if (g->tables[1].last_use < t->last_use) t = &g->tables[1];
+    int rc;
+    if (!g->guide_bits) {
+        uint32_t bits = 1;
+        while (bits < 26 && (1ull << (bits + 1)) <= g->m) bits++;
+        g->guide_bits = bits;
+    }
+    if (!t->prefix && (rc = dev_alloc(g, &t->prefix, g->m * 16))) return rc;
+    if (!t->guide && (rc = dev_alloc(g, (void **)&t->guide, ((1ull << g->guide_bits) + 1) * 4))) return rc;
+    t->q = -1.0;
+    if ((rc = inclusive_weight_prefix(g, q, t->prefix))) return rc;
+    const uint64_t nb = (1ull << g->guide_bits) + 1;
+    const unsigned grid = (unsigned)std::min<uint64_t>((nb + 255) / 256, (uint64_t)num_cus() * 16);
+    if (kind == 0) k_es_guide<0><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
+    else if (kind == 1) k_es_guide<1><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
+    else k_es_guide<2><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
+    HIP_TRY(hipGetLastError());
+    t->q = q;
+    t->last_use = g->use_clock;
+    *out = t;
     return TT_OK;
 }
 
@@ -733,34 +925,29 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
     if (k == 0 || budget == 0 || g->m == 0) { set_error(""); return TT_OK; }
     std::lock_guard<std::mutex> lock(g->mu);
     (void)hipSetDevice(g->device);
-    if ((rc = ensure_flags(g, true))) return rc;
+    if ((rc = ensure_flags(g, true)) || (rc = ensure_scratch(g, 1, 1))) return rc;
     const double q = (std::isfinite(p) && p > 0.0) ? p : 1.0;
     const int kind = q == 1.0 ? 0 : (q == 2.0 || q == 3.0) ? 1 : 2;
-    const size_t esz = kind == 0 ? 8 : kind == 1 ? 16 : 8;
     hipStream_t s = g->stream;
-    if (g->prefix_q != q) {
-        if (!g->prefix && (rc = dev_alloc(g, &g->prefix, g->m * 16))) return rc;
-        g->prefix_q = -1.0;
-        if ((rc = inclusive_weight_prefix(g, q, g->prefix))) return rc;
-        g->prefix_q = q;
-    }
-    (void)esz;
-    if ((rc = ensure_scratch(g, 1, 1))) return rc;
     HIP_TRY(hipEventRecord(g->ev[6], s));
+    tt_graph::SampleTable *tab = nullptr;
+    if ((rc = sample_table(g, q, kind, &tab))) return rc;
     HIP_TRY(hipMemsetAsync(g->emark, 0, g->m + 1, s));
     HIP_TRY(hipMemsetAsync(g->vflag, 0, (uint64_t)g->n + 1, s));
     const unsigned grid = (unsigned)std::min<uint64_t>((budget + 255) / 256, (uint64_t)num_cus() * 16);
-    if (kind == 0) k_es_draw<0><<<grid, 256, 0, s>>>(g->prefix, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
-    else if (kind == 1) k_es_draw<1><<<grid, 256, 0, s>>>(g->prefix, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
-    else k_es_draw<2><<<grid, 256, 0, s>>>(g->prefix, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
+    const uint32_t bits = g->guide_bits;
+    if (kind == 0)
+        k_es_draw<0><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
+    else if (kind == 1)
+        k_es_draw<1><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
+    else
+        k_es_draw<2><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(g->ev[7], s));
     rc = run_topk(g, k, p, FILTER_EDGES, out, n_out, stats);
     if (!rc && stats) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, g->ev[6], g->ev[7]) == hipSuccess) stats->sample_ms = ms;
-    }
-    if (!rc && stats) {
         HIP_TRY(hipMemsetAsync(g->dcount + 8, 0, 8, s));
         k_count_marks<<<enum_grid(g->m), 256, 0, s>>>(g->emark, g->m, g->dcount + 8);
         HIP_TRY(hipMemcpyAsync(g->hcount + 8, g->dcount + 8, 8, hipMemcpyDeviceToHost, s));
