@@ -36,6 +36,11 @@ struct __attribute__((aligned(16))) trec {
     uint32_t i, j, l, pad;
 };
 
+// A candidate base entry u->v of the current pass: tail, head, weight, head-sorted position.
+struct cand {
+    uint32_t u, v, a, pos;
+};
+
 // ----------------------------------------------------------------------------- graph
 struct tt_graph {
     uint32_t n = 0;
@@ -73,6 +78,9 @@ struct tt_graph {
     uint64_t bytes = 0;
     // query scratch, grown on demand and kept for later queries
     trec *buf0 = nullptr, *buf1 = nullptr;
+    struct cand *cand = nullptr;      // [m+1] candidate entries of the current pass (16 B each)
+    uint32_t *ccnt = nullptr;         // candidates per filter block
+    unsigned long long *spart = nullptr; // spread per-pass counters
     uint64_t buf_cap = 0;
     unsigned long long *dcount = nullptr; // [16] counters
     unsigned long long *hcount = nullptr; // pinned mirror

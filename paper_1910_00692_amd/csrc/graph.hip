@@ -489,7 +489,7 @@ void release(tt_graph *g) {
     if (!g) return;
     void *ptrs[] = {g->rstart, g->rlen, g->col,    g->wgt,    g->osrc,   g->eid,   g->opos,  g->wcol,
                     g->wwgt,   g->wpos, g->maxw,   g->hb,     g->deg,    g->buf0,  g->buf1,  g->dcount,
-                    g->dout,   g->emark, g->vflag, g->vflag2, g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos};
+                    g->dout,   g->emark, g->vflag, g->vflag2, g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->cand, g->ccnt, g->spart};
     for (void *p : ptrs) dev_free(g, p, 0);
     for (auto &t : g->tables) {
         dev_free(g, t.prefix, 0);

@@ -175,8 +175,21 @@ struct EnumArgs {
     trec *out;
     unsigned long long *count;
     uint64_t cap;
-    unsigned long long *stats; // [0] candidates [1] intersected entries [2] emitted [3] streamed [4] passes
+    // per-pass counters, each spread over STAT_SLOTS slots to avoid same-address atomics:
+    // [0] candidates [1] intersected entries [2] emitted [3] streamed [4] passes
+    unsigned long long *stats;
+    // candidate list: block b of the filter writes its candidates to C[b*seg ...] and their
+    // number to ccnt[b]
+    cand *C;
+    uint32_t *ccnt;
+    uint64_t seg;
+    uint32_t nseg;
 };
+
+constexpr int STAT_SLOTS = 1024;
+__device__ __forceinline__ void stat_add(unsigned long long *stats, int c, unsigned long long v) {
+    if (v) atomicAdd(&stats[c * STAT_SLOTS + (blockIdx.x & (STAT_SLOTS - 1))], v);
+}
 
 // Number of entries of a weight-sorted (descending) row with weight >= z.
 __device__ __forceinline__ uint32_t count_at_least(const uint32_t *ww, uint64_t b, uint32_t len, uint64_t z) {
@@ -189,51 +202,156 @@ __device__ __forceinline__ uint32_t count_at_least(const uint32_t *ww, uint64_t 
     return lo;
 }
 
-// Persistent waves walk the first E oriented entries in chunks of 64 (one lane per entry).
-// An entry u->v that passes the bound test gets the weight floors zu (for w_uc) and zv (for
-// w_vc); the entries of each row at or above its floor are a prefix of the weight-sorted copy
-// of the row.  The side with fewer such entries is iterated: the wave flattens the
-// (entry, qualifying element) pairs of the whole chunk across its 64 lanes, and each lane
-// binary-searches its element in the other row's head-sorted copy.
-template <int FILTER> __global__ __launch_bounds__(256) void k_enum(EnumArgs A) {
-    // a band after the one that completed the answer has nothing to do; the flag is written
-    // only between passes, never while this pass appends to the buffer
-    if (A.skip && *A.skip) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        atomicAdd(&A.stats[3], (unsigned long long)A.E);
-        atomicAdd(&A.stats[4], 1ull);
+// Number of entries of two weight-sorted rows at or above their floors; both binary searches
+// advance together so that their loads overlap.
+__device__ __forceinline__ void count_pair(const uint32_t *ww, uint64_t b1, uint32_t n1, uint64_t z1, uint64_t b2,
+                                           uint32_t n2, uint64_t z2, uint32_t &q1, uint32_t &q2) {
+    uint32_t lo1 = z1 ? 0 : n1, hi1 = n1, lo2 = z2 ? 0 : n2, hi2 = n2;
+    while (lo1 < hi1 || lo2 < hi2) {
+        if (lo1 < hi1) {
+            const uint32_t mid = (lo1 + hi1) >> 1;
+            if ((uint64_t)ww[b1 + mid] >= z1) lo1 = mid + 1; else hi1 = mid;
+        }
+        if (lo2 < hi2) {
+            const uint32_t mid = (lo2 + hi2) >> 1;
+            if ((uint64_t)ww[b2 + mid] >= z2) lo2 = mid + 1; else hi2 = mid;
+        }
     }
+    q1 = lo1;
+    q2 = lo2;
+}
+
+constexpr int FILTER_UNROLL = 4;
+
+// Phase 1: stream the first E entries of the chosen order; an entry that can be the base of a
+// triangle in the band (bound test + subset / sampling pre-test) is appended to the candidate
+// list (wave ballot, one atomic per wave).  Pure streaming: FILTER_UNROLL entries per lane
+// are in flight at once.
+template <int FILTER> __global__ __launch_bounds__(256) void k_filter(EnumArgs A) {
+    __shared__ uint32_t lcount;
+    if (A.skip && *A.skip) return; // written only between passes
+    if (threadIdx.x == 0) lcount = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        stat_add(A.stats, 3, A.E);
+        stat_add(A.stats, 4, 1);
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
+    const uint64_t lo = (uint64_t)blockIdx.x * A.seg;
+    const uint64_t hi = lo + A.seg < A.E ? lo + A.seg : A.E;
+    cand *out = A.C + lo;
+    for (uint64_t base = lo + (threadIdx.x >> 6) * 64 * FILTER_UNROLL; base < hi; base += blockDim.x * FILTER_UNROLL) {
+        uint32_t u[FILTER_UNROLL], v[FILTER_UNROLL], a[FILTER_UNROLL], pos[FILTER_UNROLL];
+        bool pass[FILTER_UNROLL];
+#pragma unroll
+        for (int k = 0; k < FILTER_UNROLL; k++) {
+            const uint64_t e = base + (uint64_t)k * 64 + lane;
+            pass[k] = e < hi;
+            u[k] = v[k] = a[k] = pos[k] = 0;
+            if (pass[k]) {
+                u[k] = A.s_src[e];
+                v[k] = A.s_col[e];
+                a[k] = A.s_wgt[e];
+                pos[k] = A.s_pos ? A.s_pos[e] : (uint32_t)e;
+            }
+        }
+        uint32_t n_pass = 0, rank[FILTER_UNROLL];
+#pragma unroll
+        for (int k = 0; k < FILTER_UNROLL; k++) {
+            if (pass[k]) {
+                bool pre = true;
+                if (FILTER == FILTER_EDGES) pre = A.emark[pos[k]] || A.vflag[u[k]] || A.vflag[v[k]];
+                else if (FILTER == FILTER_VERTICES)
+                    pre = A.vflag[u[k]] || A.vflag[v[k]] || (A.vflag2[u[k]] && A.vflag2[v[k]]);
+                pass[k] = pre && bound_ok(A.B, a[k], A.maxw[u[k]], A.maxw[v[k]]);
+            }
+            const uint64_t bal = __ballot(pass[k]);
+            rank[k] = n_pass + __popcll(bal & ((1ull << lane) - 1ull));
+            n_pass += __popcll(bal);
+        }
+        if (n_pass) {
+            uint32_t b0 = 0;
+            if (lane == 0) b0 = atomicAdd(&lcount, n_pass); // LDS atomic: block-local offset
+            b0 = __shfl(b0, 0, 64);
+#pragma unroll
+            for (int k = 0; k < FILTER_UNROLL; k++)
+                if (pass[k]) out[b0 + rank[k]] = cand{u[k], v[k], a[k], pos[k]};
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        A.ccnt[blockIdx.x] = lcount;
+        stat_add(A.stats, 0, lcount);
+    }
+}
+
+// Phase 2: persistent waves over the candidate list (its length is read on the device).  A
+// candidate u->v gets the weight floors zu (for w_uc) and zv (for w_vc); the entries of each
+// row at or above its floor are a prefix of the weight-sorted copy of the row.  The side with
+// fewer such entries is iterated: the wave flattens the (candidate, qualifying element) pairs
+// of its 64 candidates across its lanes, and each lane binary-searches its element in the
+// other row's head-sorted copy.
+constexpr int MAX_SEG = 4096;
+
+template <int FILTER> __global__ __launch_bounds__(256) void k_intersect(EnumArgs A) {
+    __shared__ uint32_t pre[MAX_SEG + 1]; // exclusive prefix of 64-candidate chunks per segment
+    __shared__ uint32_t wsum[4];
+    if (A.skip && *A.skip) return;
+    const int lane = threadIdx.x & 63;
+    {
+        // block scan of the per-segment chunk counts (each thread owns 16 consecutive segments)
+        constexpr int PER = (MAX_SEG + 255) / 256;
+        uint32_t loc[PER], sum = 0;
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            const uint32_t sg = threadIdx.x * PER + i;
+            loc[i] = sg < A.nseg ? (A.ccnt[sg] + 63) >> 6 : 0;
+            sum += loc[i];
+        }
+        const uint32_t incl = wave_incl_scan(sum);
+        if (lane == 63) wsum[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        uint32_t run = incl - sum;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); w++) run += wsum[w];
+#pragma unroll
+        for (int i = 0; i < PER; i++) {
+            pre[threadIdx.x * PER + i] = run;
+            run += loc[i];
+        }
+        if (threadIdx.x == 255) pre[MAX_SEG] = run;
+        __syncthreads();
+    }
+    const uint32_t nchunks = pre[MAX_SEG];
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    const uint64_t nchunks = (A.E + 63) >> 6;
-    unsigned long long s_cand = 0, s_inter = 0, s_emit = 0;
+    unsigned long long s_inter = 0, s_emit = 0;
     for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
-        const uint64_t e = (ch << 6) + (uint64_t)lane;
+        // segment holding chunk ch: the last sg with pre[sg] <= ch
+        uint32_t lo_s = 0, hi_s = MAX_SEG;
+        while (hi_s - lo_s > 1) {
+            const uint32_t mid = (lo_s + hi_s) >> 1;
+            if (pre[mid] <= ch) lo_s = mid; else hi_s = mid;
+        }
+        const uint32_t sg = lo_s;
+        const uint64_t j = ((uint64_t)(ch - pre[sg]) << 6) + (uint64_t)lane;
         bool pass = false;
         uint32_t a = 0, u = 0, v = 0, qA = 0, Blen = 0, fl = 0;
         uint64_t Ab = 0, Bb = 0, zB = 0;
-        if (e < A.E) {
-            u = A.s_src[e];
-            v = A.s_col[e];
-            a = A.s_wgt[e];
+        if (j < A.ccnt[sg]) {
+            const cand c = A.C[(uint64_t)sg * A.seg + j];
+            u = c.u;
+            v = c.v;
+            a = c.a;
             const uint32_t Wu = A.maxw[u], Wv = A.maxw[v];
-            bool pre = true;
-            if (FILTER == FILTER_EDGES) {
-                if (A.emark[A.s_pos ? A.s_pos[e] : e]) fl |= FL_MARK_UV;
-                pre = (fl & FL_MARK_UV) || A.vflag[u] || A.vflag[v];
-            } else if (FILTER == FILTER_VERTICES) {
-                const bool su = A.vflag[u], sv = A.vflag[v];
-                pre = su || sv || (A.vflag2[u] && A.vflag2[v]);
-                if (!su && !sv) fl |= FL_REQ_C;
-            }
-            pass = pre && bound_ok(A.B, a, Wu, Wv);
+            const uint64_t ub = A.rstart[u], vb = A.rstart[v];
+            const uint32_t ul = A.rlen[u], vl = A.rlen[v];
+            if (FILTER == FILTER_EDGES && A.emark[c.pos]) fl |= FL_MARK_UV;
+            if (FILTER == FILTER_VERTICES && !A.vflag[u] && !A.vflag[v]) fl |= FL_REQ_C;
+            const uint64_t zu = min_other(A.B, a, Wv), zv = min_other(A.B, a, Wu);
+            pass = zu <= Wu && zv <= Wv;
             if (pass) {
-                const uint64_t zu = min_other(A.B, a, Wv), zv = min_other(A.B, a, Wu);
-                const uint64_t ub = A.rstart[u], vb = A.rstart[v];
-                const uint32_t ul = A.rlen[u], vl = A.rlen[v];
-                const uint32_t qu = (zu > Wu) ? 0 : count_at_least(A.wwgt, ub, ul, zu);
-                const uint32_t qv = (qu == 0 || zv > Wv) ? 0 : count_at_least(A.wwgt, vb, vl, zv);
+                uint32_t qu, qv;
+                count_pair(A.wwgt, ub, ul, zu, vb, vl, zv, qu, qv);
                 const bool uA = qu <= qv;
                 qA = uA ? qu : qv;
                 Ab = uA ? ub : vb;
@@ -253,19 +371,15 @@ template <int FILTER> __global__ __launch_bounds__(256) void k_enum(EnumArgs A) 
         const uint32_t work = pass ? qA : 0;
         const uint32_t incl = wave_incl_scan(work);
         const uint32_t total = __shfl(incl, 63, 64);
-        const uint64_t pb = __ballot(pass);
-        if (lane == 0) {
-            s_cand += __popcll(pb);
-            s_inter += total;
-        }
+        if (lane == 0) s_inter += total;
         for (uint32_t base = 0; base < total; base += 64) {
             const uint32_t t = base + (uint32_t)lane;
             const uint32_t tt = t < total ? t : total - 1;
             int s = 0; // owner lane: number of lanes whose inclusive end is <= tt
 #pragma unroll
-            for (int step = 32; step > 0; step >>= 1) {
-                const uint32_t im = __shfl(incl, s + step - 1, 64);
-                if (im <= tt) s += step;
+            for (int st = 32; st > 0; st >>= 1) {
+                const uint32_t im = __shfl(incl, s + st - 1, 64);
+                if (im <= tt) s += st;
             }
             const uint32_t o_incl = __shfl(incl, s, 64), o_work = __shfl(work, s, 64);
             const uint64_t oAb = __shfl(Ab, s, 64), oBb = __shfl(Bb, s, 64), ozB = __shfl(zB, s, 64);
@@ -324,10 +438,24 @@ template <int FILTER> __global__ __launch_bounds__(256) void k_enum(EnumArgs A) 
         }
     }
     if (lane == 0) {
-        if (s_cand) atomicAdd(&A.stats[0], s_cand);
-        if (s_inter) atomicAdd(&A.stats[1], s_inter);
-        if (s_emit) atomicAdd(&A.stats[2], s_emit);
+        stat_add(A.stats, 1, s_inter);
+        stat_add(A.stats, 2, s_emit);
     }
+}
+
+// Sums the spread counters into out[0..5) and clears them.
+__global__ void k_reduce_stats(unsigned long long *stats, unsigned long long *out) {
+    const int c = blockIdx.x;
+    unsigned long long v = 0;
+    for (int t = threadIdx.x; t < STAT_SLOTS; t += blockDim.x) {
+        v += stats[c * STAT_SLOTS + t];
+        stats[c * STAT_SLOTS + t] = 0;
+    }
+    v = wave_sum(v);
+    __shared__ unsigned long long ws[4];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out[c] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
 // Between two passes: the later bands are skipped once the buffer holds >= k triangles (the
@@ -540,8 +668,23 @@ unsigned enum_grid(uint64_t m) {
     return (unsigned)(blocks ? blocks : 1);
 }
 
+unsigned filter_grid(uint64_t E) {
+    const uint64_t per_block = 256ull * FILTER_UNROLL;
+    uint64_t blocks = (E + per_block - 1) / per_block;
+    uint64_t cap = (uint64_t)num_cus() * 8;
+    if (cap > (uint64_t)MAX_SEG) cap = MAX_SEG;
+    if (blocks > cap) blocks = cap;
+    return (unsigned)(blocks ? blocks : 1);
+}
+
 int ensure_scratch(tt_graph *g, uint64_t cap, uint64_t kout) {
     int rc;
+    if (!g->cand && (rc = dev_alloc(g, (void **)&g->cand, (g->m + 1) * sizeof(cand)))) return rc;
+    if (!g->ccnt && (rc = dev_alloc(g, (void **)&g->ccnt, MAX_SEG * sizeof(uint32_t)))) return rc;
+    if (!g->spart) {
+        if ((rc = dev_alloc(g, (void **)&g->spart, 5 * STAT_SLOTS * sizeof(unsigned long long)))) return rc;
+        HIP_TRY(hipMemsetAsync(g->spart, 0, 5 * STAT_SLOTS * sizeof(unsigned long long), g->stream));
+    }
     if (!g->dcount) {
         if ((rc = dev_alloc(g, (void **)&g->dcount, 16 * sizeof(unsigned long long)))) return rc;
         if (hipHostMalloc((void **)&g->hcount, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
@@ -710,13 +853,25 @@ int launch_enum(tt_graph *g, const Band &B, int filter, bool gated, size_t slot)
     A.out = g->buf0;
     A.count = g->dcount;
     A.cap = g->buf_cap;
-    A.stats = g->dcount + 1;
+    A.stats = g->spart;
+    A.C = g->cand;
+    A.ccnt = g->ccnt;
+    A.nseg = filter_grid(S.E);
+    A.seg = (S.E + A.nseg - 1) / A.nseg;
     HIP_TRY(hipEventRecord(g->band_ev[2 * slot], g->stream));
     if (S.E) {
-        const unsigned grid = enum_grid(S.E);
-        if (filter == FILTER_EDGES) k_enum<FILTER_EDGES><<<grid, 256, 0, g->stream>>>(A);
-        else if (filter == FILTER_VERTICES) k_enum<FILTER_VERTICES><<<grid, 256, 0, g->stream>>>(A);
-        else k_enum<FILTER_NONE><<<grid, 256, 0, g->stream>>>(A);
+        const unsigned fgrid = A.nseg;
+        const unsigned igrid = (unsigned)num_cus() * 8;
+        if (filter == FILTER_EDGES) {
+            k_filter<FILTER_EDGES><<<fgrid, 256, 0, g->stream>>>(A);
+            k_intersect<FILTER_EDGES><<<igrid, 256, 0, g->stream>>>(A);
+        } else if (filter == FILTER_VERTICES) {
+            k_filter<FILTER_VERTICES><<<fgrid, 256, 0, g->stream>>>(A);
+            k_intersect<FILTER_VERTICES><<<igrid, 256, 0, g->stream>>>(A);
+        } else {
+            k_filter<FILTER_NONE><<<fgrid, 256, 0, g->stream>>>(A);
+            k_intersect<FILTER_NONE><<<igrid, 256, 0, g->stream>>>(A);
+        }
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipEventRecord(g->band_ev[2 * slot + 1], g->stream));
@@ -814,6 +969,7 @@ int run_topk(tt_graph *g, uint32_t k, double p, int filter, tt_triangle *out, ui
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipEventRecord(g->ev[2], s));
+    k_reduce_stats<<<5, 256, 0, s>>>(g->spart, g->dcount + 1);
     if (K > 0) HIP_TRY(hipMemcpyAsync(out, g->dout, (size_t)K * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
