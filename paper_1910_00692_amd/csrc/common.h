@@ -70,6 +70,7 @@ struct tt_graph {
     uint32_t *hb = nullptr;     // [n] max(maxw[u], maxw[v] over out-neighbours v): bounds every
                                 //     triangle based at u, for every p
     uint32_t *deg = nullptr;    // [n] undirected degree
+    uint32_t *in_w = nullptr;   // [m] weights in input order (sampling prefix sums)
     uint32_t wmax = 0;          // largest weight in the graph
     uint32_t max_outdeg = 0;
     std::vector<uint64_t> whist; // host: edge count per weight_bin(w)

@@ -127,10 +127,42 @@ __global__ __launch_bounds__(256) void k_validate(const uint32_t *src, const uin
     if ((threadIdx.x & 63) == 0 && f) atomicOr(flags, f);
 }
 
+// Wave-level merging of atomics: in grid-stride loops the valid lanes are a prefix of the wave,
+// and runs of equal keys in consecutive lanes (edge lists are often grouped by endpoint) are
+// merged so that each run issues one atomic.  Returns the run's first lane for every lane.
+struct WaveRuns {
+    uint64_t heads;   // lanes that start a run
+    int first;        // first lane of this lane's run
+    int end;          // one past the last lane of this lane's run
+};
+__device__ __forceinline__ WaveRuns wave_runs(uint32_t key, bool valid) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t vmask = __ballot(valid);
+    const uint32_t pk = __shfl_up(key, 1, 64);
+    const bool pv = lane > 0 && ((vmask >> (lane - 1)) & 1ull);
+    const bool head = valid && (!pv || pk != key);
+    WaveRuns r;
+    r.heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const uint64_t before = r.heads & upto;
+    r.first = before ? 63 - __builtin_clzll(before) : 0;
+    const uint64_t after = lane == 63 ? 0ull : (r.heads >> (lane + 1)) << (lane + 1);
+    const int nvalid = vmask ? 64 - __builtin_clzll(vmask) : 0;
+    r.end = after ? __builtin_ctzll(after) : nvalid;
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_degree(const uint32_t *src, const uint32_t *dst, uint64_t m, uint32_t *deg) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
-        atomicAdd(&deg[src[e]], 1u);
-        atomicAdd(&deg[dst[e]], 1u);
+    const int lane = threadIdx.x & 63;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
+        const uint64_t e = base + lane;
+        const bool valid = e < m;
+        const uint32_t a = valid ? src[e] : 0u, b = valid ? dst[e] : 0u;
+        WaveRuns ra = wave_runs(a, valid);
+        if (valid && ra.first == lane) atomicAdd(&deg[a], (uint32_t)(ra.end - lane));
+        WaveRuns rb = wave_runs(b, valid);
+        if (valid && rb.first == lane) atomicAdd(&deg[b], (uint32_t)(rb.end - lane));
     }
 }
 
@@ -144,59 +176,34 @@ __device__ inline void orient(uint32_t a, uint32_t b, const uint32_t *deg, uint3
 
 __global__ __launch_bounds__(256) void k_outdeg(const uint32_t *src, const uint32_t *dst, uint64_t m,
                                                 const uint32_t *deg, uint32_t *outdeg) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t t, h;
-        orient(src[e], dst[e], deg, t, h);
-        atomicAdd(&outdeg[t], 1u);
+    const int lane = threadIdx.x & 63;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
+        const uint64_t e = base + lane;
+        const bool valid = e < m;
+        uint32_t t = 0, h = 0;
+        if (valid) orient(src[e], dst[e], deg, t, h);
+        WaveRuns r = wave_runs(t, valid);
+        if (valid && r.first == lane) atomicAdd(&outdeg[t], (uint32_t)(r.end - lane));
     }
 }
 
+// Scatters every edge into its tail's row (rows unsorted) as one 16-byte record.
 __global__ __launch_bounds__(256) void k_scatter(const uint32_t *src, const uint32_t *dst, const uint32_t *w, uint64_t m,
                                                  const uint32_t *deg, const uint64_t *rowp, uint32_t *cursor,
-                                                 uint32_t *col, uint32_t *wgt, uint32_t *eid) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t t, h;
-        orient(src[e], dst[e], deg, t, h);
-        uint64_t pos = rowp[t] + atomicAdd(&cursor[t], 1u);
-        col[pos] = h;
-        wgt[pos] = w[e];
-        eid[pos] = (uint32_t)e;
-    }
-}
-
-// Segmented sort of every row by key K (ascending), carrying up to two u32 payloads.
-// Rows of at most 64 entries: one wave per row, each lane's rank found by counting.
-// Longer rows are queued for k_sort_big_rows.
-template <typename K>
-__global__ __launch_bounds__(256) void k_sort_small_rows(const uint64_t *rstart, const uint32_t *rlen, uint32_t n,
-                                                         K *key, uint32_t *p1, uint32_t *p2, uint32_t *big,
-                                                         uint32_t *nbig) {
-    const uint64_t row = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+                                                 uint4 *rec) {
     const int lane = threadIdx.x & 63;
-    if (row >= n) return;
-    const uint64_t b = rstart[row];
-    const uint32_t len = rlen[row];
-    if (len <= 1) return;
-    if (len > 64) {
-        if (lane == 0) big[atomicAdd(nbig, 1u)] = (uint32_t)row;
-        return;
-    }
-    K c = ~K(0);
-    uint32_t x = 0, y = 0;
-    if (lane < (int)len) {
-        c = key[b + lane];
-        x = p1[b + lane];
-        if (p2) y = p2[b + lane];
-    }
-    uint32_t rank = 0;
-    for (uint32_t j = 0; j < len; j++) {
-        K cj = __shfl(c, (int)j, 64);
-        rank += (cj < c) || (cj == c && (int)j < lane);
-    }
-    if (lane < (int)len) {
-        key[b + rank] = c;
-        p1[b + rank] = x;
-        if (p2) p2[b + rank] = y;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
+        const uint64_t e = base + lane;
+        const bool valid = e < m;
+        uint32_t t = 0, h = 0;
+        if (valid) orient(src[e], dst[e], deg, t, h);
+        WaveRuns r = wave_runs(t, valid);
+        uint32_t slot = 0;
+        if (valid && r.first == lane) slot = atomicAdd(&cursor[t], (uint32_t)(r.end - lane));
+        slot = __shfl(slot, r.first, 64) + (uint32_t)(lane - r.first);
+        if (valid) rec[rowp[t] + slot] = make_uint4(h, w[e], (uint32_t)e, t); // (head, weight, edge, tail)
     }
 }
 
@@ -289,50 +296,42 @@ __global__ __launch_bounds__(256) void k_sort_big_rows(const uint64_t *rstart, c
     }
 }
 
-// Row maxima and the duplicate check (rows already sorted by head ID).  Grid-stride waves
-// keep running maxima in registers and issue one atomic per wave at the end.
-__global__ __launch_bounds__(256) void k_row_max(const uint64_t *rstart, const uint32_t *rlen, uint32_t n,
-                                                 const uint32_t *col, const uint32_t *wgt, uint32_t *maxw,
-                                                 uint32_t *flags, uint32_t *gmax) {
+// Row maxima (maxw) and row bounds (hb = max(maxw[u], maxw[v] over out(u))) as streaming
+// segmented reductions over the unsorted rows: each wave reduces the runs of equal tails in
+// its 64 entries with shuffles and issues one atomicMax per run.
+__device__ __forceinline__ uint32_t seg_max(uint32_t v, const WaveRuns &r) {
     const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    uint32_t gw = 0, gd = 0;
-    bool dup = false;
-    for (uint64_t row = wave; row < n; row += nwaves) {
-        const uint64_t b = rstart[row];
-        const uint32_t len = rlen[row];
-        uint32_t mx = 0;
-        for (uint32_t t = lane; t < len; t += 64) {
-            mx = max(mx, wgt[b + t]);
-            if (t > 0 && col[b + t - 1] == col[b + t]) dup = true;
-        }
-        mx = wave_max(mx);
-        if (lane == 0) maxw[row] = mx;
-        gw = max(gw, mx);
-        gd = max(gd, len);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_down(v, o, 64);
+        if (lane + o < r.end) v = max(v, y);
     }
-    const uint64_t anydup = __ballot(dup);
-    if (lane == 0) {
-        if (gw) atomicMax(&gmax[0], gw);
-        if (gd) atomicMax(&gmax[1], gd);
-        if (anydup) atomicOr(flags, F_DUP);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_row_max(const uint4 *rec, uint64_t m, uint32_t *maxw) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
+        const uint64_t e = base + lane;
+        const bool valid = e < m;
+        const uint4 x = valid ? rec[e] : make_uint4(0u, 0u, 0u, 0u);
+        const WaveRuns r = wave_runs(x.w, valid);
+        const uint32_t v = seg_max(x.y, r);
+        if (valid && r.first == lane) atomicMax(&maxw[x.w], v);
     }
 }
 
-// hb[u] = max(maxw[u], maxw[v] for v in out(u))
-__global__ __launch_bounds__(256) void k_row_bound(const uint64_t *rstart, const uint32_t *rlen, uint32_t n,
-                                                   const uint32_t *col, const uint32_t *maxw, uint32_t *hb) {
+__global__ __launch_bounds__(256) void k_row_bound(const uint4 *rec, uint64_t m, const uint32_t *maxw, uint32_t *hb) {
     const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t row = wave; row < n; row += nwaves) {
-        const uint64_t b = rstart[row];
-        const uint32_t len = rlen[row];
-        uint32_t mx = 0;
-        for (uint32_t t = lane; t < len; t += 64) mx = max(mx, maxw[col[b + t]]);
-        mx = wave_max(mx);
-        if (lane == 0) hb[row] = max(mx, maxw[row]);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
+        const uint64_t e = base + lane;
+        const bool valid = e < m;
+        const uint4 x = valid ? rec[e] : make_uint4(0u, 0u, 0u, 0u);
+        const WaveRuns r = wave_runs(x.w, valid);
+        const uint32_t v = seg_max(valid ? maxw[x.x] : 0u, r);
+        if (valid && r.first == lane) atomicMax(&hb[x.w], v);
     }
 }
 
@@ -378,48 +377,186 @@ __global__ __launch_bounds__(256) void k_place_rows(const uint32_t *hb, const ui
     }
 }
 
-// Copies every row to its new start; builds the weight-sorted copy's keys.
-__global__ __launch_bounds__(256) void k_move_rows(const uint64_t *ostart, const uint64_t *rstart, const uint32_t *rlen,
-                                                   uint32_t n, const uint32_t *ocol, const uint32_t *owgt,
-                                                   const uint32_t *oeid, uint32_t *col, uint32_t *wgt, uint32_t *eid,
-                                                   uint64_t *wkey, uint32_t *wpos) {
+constexpr uint32_t SMALL_MAX = 64;   // rows ordered by a wave over a register window
+constexpr uint32_t MID_MAX = 1024;   // rows ordered by a block in LDS
+constexpr int RANK_ITEMS = 2;        // window of RANK_ITEMS * 64 entries per wave
+
+// Writes one entry of a row (tail t, head c, weight w, input edge d) to both copies of the
+// final layout: head order at rank r1, weight order at rank r2; records its tail and the
+// position of its input edge.
+__device__ __forceinline__ void put_entry(uint64_t P, uint32_t r1, uint32_t r2, uint32_t t, uint32_t c, uint32_t w,
+                                          uint32_t d, uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
+                                          uint32_t *opos, uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos) {
+    col[P + r1] = c;
+    wgt[P + r1] = w;
+    eid[P + r1] = d;
+    osrc[P + r1] = t;
+    opos[d] = (uint32_t)(P + r1);
+    wcol[P + r2] = c;
+    wwgt[P + r2] = w;
+    wpos[P + r2] = (uint32_t)(P + r1);
+}
+
+// Rows of at most SMALL_MAX entries.  Window w holds the rows that START in entries
+// [64w, 64w+64) of the scatter layout; they end before 64w+128.  A wave stages that 128-entry
+// window (heads and weights) in LDS and every lane counts its entries' ranks (by head ID; by
+// weight desc, then head ID) over its own row only.  Equal heads in one row are a repeated pair.
+__global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uint64_t *rowp0, uint64_t m,
+                                                    const uint64_t *rstart, const uint32_t *rlen, uint32_t *col,
+                                                    uint32_t *wgt, uint32_t *eid, uint32_t *osrc, uint32_t *opos,
+                                                    uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos, uint32_t *flags) {
+    __shared__ uint32_t sc[4][RANK_ITEMS * 64], sw[4][RANK_ITEMS * 64];
+    const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
+    const uint64_t nw = (m + 63) / 64;
+    bool dup = false;
+    // the whole block steps through windows together, so __syncthreads is uniform
+    for (uint64_t blk = (uint64_t)blockIdx.x * 4; blk < nw; blk += (uint64_t)gridDim.x * 4) {
+        const uint64_t w0 = blk + wib;
+        const uint64_t base = w0 * 64;
+        uint32_t c[RANK_ITEMS], wt[RANK_ITEMS], d[RANK_ITEMS], t[RANK_ITEMS], rb[RANK_ITEMS], len[RANK_ITEMS];
+        bool mine[RANK_ITEMS];
+#pragma unroll
+        for (int k = 0; k < RANK_ITEMS; k++) {
+            const uint64_t e = base + (uint64_t)k * 64 + lane;
+            uint4 r = make_uint4(0u, 0u, 0u, 0u);
+            mine[k] = false;
+            rb[k] = len[k] = 0;
+            if (w0 < nw && e < m) {
+                r = rec0[e];
+                const uint64_t b = rowp0[r.w];
+                len[k] = rlen[r.w];
+                mine[k] = b >= base && b < base + 64 && len[k] <= SMALL_MAX;
+                rb[k] = (uint32_t)(b - base); // window-relative row start (valid when mine)
+            }
+            c[k] = r.x; wt[k] = r.y; d[k] = r.z; t[k] = r.w;
+            sc[wib][k * 64 + lane] = r.x;
+            sw[wib][k * 64 + lane] = r.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < RANK_ITEMS; k++) {
+            if (!mine[k]) continue;
+            const uint32_t me = (uint32_t)(k * 64 + lane);
+            uint32_t r1 = 0, r2 = 0;
+            for (uint32_t f = rb[k]; f < rb[k] + len[k]; f++) {
+                const uint32_t cf = sc[wib][f], wf = sw[wib][f];
+                const bool before_id = cf < c[k] || (cf == c[k] && f < me);
+                r1 += before_id;
+                r2 += wf > wt[k] || (wf == wt[k] && before_id);
+                dup |= cf == c[k] && f != me;
+            }
+            put_entry(rstart[t[k]], r1, r2, t[k], c[k], wt[k], d[k], col, wgt, eid, osrc, opos, wcol, wwgt, wpos);
+        }
+        __syncthreads();
+    }
+    if (__ballot(dup) && lane == 0) atomicOr(flags, F_DUP);
+}
+
+// Lists the rows that need the LDS (mid) or the sorting (big) path; one atomic per wave and list.
+__global__ __launch_bounds__(256) void k_list_long(const uint32_t *rlen, uint32_t n, uint32_t *mid, uint32_t *nmid,
+                                                   uint32_t *big, uint32_t *nbig) {
     const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t row = wave; row < n; row += nwaves) {
-        const uint64_t a = ostart[row], b = rstart[row];
-        const uint32_t len = rlen[row];
-        for (uint32_t t = lane; t < len; t += 64) {
-            const uint32_t c = ocol[a + t], w = owgt[a + t];
-            col[b + t] = c;
-            wgt[b + t] = w;
-            eid[b + t] = oeid[a + t];
-            wkey[b + t] = ((uint64_t)(~w) << 32) | c; // ascending key = weight descending, then ID
-            wpos[b + t] = (uint32_t)(b + t);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
+        const uint64_t u = base + lane;
+        const uint32_t l = u < n ? rlen[u] : 0u;
+        const bool isb = l > MID_MAX, ism = l > SMALL_MAX && l <= MID_MAX;
+        const uint64_t bb = __ballot(isb), bm = __ballot(ism);
+        uint32_t ob = 0, om = 0;
+        if (lane == 0 && bb) ob = atomicAdd(nbig, (uint32_t)__popcll(bb));
+        if (lane == 0 && bm) om = atomicAdd(nmid, (uint32_t)__popcll(bm));
+        ob = __shfl(ob, 0, 64);
+        om = __shfl(om, 0, 64);
+        const uint64_t below = (1ull << lane) - 1ull;
+        if (isb) big[ob + __popcll(bb & below)] = (uint32_t)u;
+        if (ism) mid[om + __popcll(bm & below)] = (uint32_t)u;
+    }
+}
+
+// Rows of SMALL_MAX+1 .. MID_MAX entries: one block per row; the row is staged in LDS and
+// every entry's ranks are counted there.
+__global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t nmid, const uint4 *rec0,
+                                                  const uint64_t *rowp0, const uint64_t *rstart, const uint32_t *rlen,
+                                                  uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
+                                                  uint32_t *opos, uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
+                                                  uint32_t *flags) {
+    __shared__ uint32_t sc[MID_MAX], sw[MID_MAX];
+    bool dup = false;
+    for (uint32_t bi = blockIdx.x; bi < nmid; bi += gridDim.x) {
+        const uint32_t u = mid[bi];
+        const uint64_t b = rowp0[u], P = rstart[u];
+        const uint32_t len = rlen[u];
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+            const uint4 r = rec0[b + i];
+            sc[i] = r.x;
+            sw[i] = r.y;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+            const uint32_t c = sc[i], w = sw[i];
+            uint32_t r1 = 0, r2 = 0;
+            for (uint32_t f = 0; f < len; f++) {
+                const uint32_t cf = sc[f], wf = sw[f];
+                const bool before_id = cf < c || (cf == c && f < i);
+                r1 += before_id;
+                r2 += wf > w || (wf == w && before_id);
+                dup |= cf == c && f != i;
+            }
+            put_entry(P, r1, r2, u, c, w, rec0[b + i].z, col, wgt, eid, osrc, opos, wcol, wwgt, wpos);
+        }
+    }
+    if (__ballot(dup) && (threadIdx.x & 63) == 0) atomicOr(flags, F_DUP);
+}
+
+// Longest rows: copied to the final layout here, sorted by k_sort_big_rows, then finished below.
+__global__ __launch_bounds__(256) void k_move_big(const uint32_t *big, uint32_t nbig, const uint64_t *rowp0,
+                                                  const uint64_t *rstart, const uint32_t *rlen, const uint4 *rec0,
+                                                  uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc) {
+    for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+        const uint32_t u = big[bi];
+        const uint64_t a = rowp0[u], b = rstart[u];
+        for (uint32_t t = threadIdx.x; t < rlen[u]; t += blockDim.x) {
+            const uint4 r = rec0[a + t];
+            col[b + t] = r.x;
+            wgt[b + t] = r.y;
+            eid[b + t] = r.z;
+            osrc[b + t] = u;
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_split_keys(const uint64_t *wkey, uint64_t m, uint32_t *wcol, uint32_t *wwgt) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = wkey[e];
-        wcol[e] = (uint32_t)k;
-        wwgt[e] = ~(uint32_t)(k >> 32);
+// After the head-ID sort of the long rows: positions of their input edges, the duplicate
+// check, and the keys of their weight-sorted copy.
+__global__ __launch_bounds__(256) void k_post_big(const uint32_t *big, uint32_t nbig, const uint64_t *rstart,
+                                                  const uint32_t *rlen, const uint32_t *col, const uint32_t *wgt,
+                                                  const uint32_t *eid, uint32_t *opos, uint64_t *wkey, uint32_t *wpos,
+                                                  uint32_t *flags) {
+    bool dup = false;
+    for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+        const uint32_t u = big[bi];
+        const uint64_t b = rstart[u];
+        for (uint32_t t = threadIdx.x; t < rlen[u]; t += blockDim.x) {
+            const uint32_t c = col[b + t];
+            if (t > 0 && col[b + t - 1] == c) dup = true;
+            opos[eid[b + t]] = (uint32_t)(b + t);
+            wkey[b + t] = ((uint64_t)(~wgt[b + t]) << 32) | c; // ascending = weight desc, then ID
+            wpos[b + t] = (uint32_t)(b + t);
+        }
     }
+    if (__ballot(dup) && (threadIdx.x & 63) == 0) atomicOr(flags, F_DUP);
 }
 
-// Tails and input-edge positions of the final layout.
-__global__ __launch_bounds__(256) void k_row_post(const uint64_t *rstart, const uint32_t *rlen, uint32_t n,
-                                                  const uint32_t *eid, uint32_t *osrc, uint32_t *opos) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t row = wave; row < n; row += nwaves) {
-        const uint64_t b = rstart[row];
-        const uint32_t len = rlen[row];
-        for (uint32_t t = lane; t < len; t += 64) {
-            osrc[b + t] = (uint32_t)row;
-            opos[eid[b + t]] = (uint32_t)(b + t);
+__global__ __launch_bounds__(256) void k_split_big(const uint32_t *big, uint32_t nbig, const uint64_t *rstart,
+                                                   const uint32_t *rlen, const uint64_t *wkey, uint32_t *wcol,
+                                                   uint32_t *wwgt) {
+    for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+        const uint32_t u = big[bi];
+        const uint64_t b = rstart[u];
+        for (uint32_t t = threadIdx.x; t < rlen[u]; t += blockDim.x) {
+            const uint64_t k = wkey[b + t];
+            wcol[b + t] = (uint32_t)k;
+            wwgt[b + t] = ~(uint32_t)(k >> 32);
         }
     }
 }
@@ -489,7 +626,7 @@ void release(tt_graph *g) {
     if (!g) return;
     void *ptrs[] = {g->rstart, g->rlen, g->col,    g->wgt,    g->osrc,   g->eid,   g->opos,  g->wcol,
                     g->wwgt,   g->wpos, g->maxw,   g->hb,     g->deg,    g->buf0,  g->buf1,  g->dcount,
-                    g->dout,   g->emark, g->vflag, g->vflag2, g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->cand, g->ccnt, g->spart};
+                    g->dout,   g->emark, g->vflag, g->vflag2, g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->cand, g->ccnt, g->spart, g->in_w};
     for (void *p : ptrs) dev_free(g, p, 0);
     for (auto &t : g->tables) {
         dev_free(g, t.prefix, 0);
@@ -522,30 +659,23 @@ struct Scratch {
     }
 };
 
+// Sorts the listed long rows by key K (ascending), carrying up to two u32 payloads.
 template <typename K>
-int sort_rows(tt_graph *g, Scratch &S, const uint64_t *rstart, const uint32_t *rlen, K *key, uint32_t *p1, uint32_t *p2,
-              uint32_t *big, uint32_t *nbig_dev) {
+int sort_big(tt_graph *g, Scratch &S, const uint64_t *rstart, const uint32_t *rlen, const uint32_t *big, uint32_t nbig,
+             K *key, uint32_t *p1, uint32_t *p2) {
+    if (!nbig) return TT_OK;
     hipStream_t s = g->stream;
-    const uint32_t n = g->n;
     const uint64_t m = g->m;
-    HIP_TRY(hipMemsetAsync(nbig_dev, 0, 4, s));
-    if (n) k_sort_small_rows<K><<<(unsigned)(((uint64_t)n + 3) / 4), 256, 0, s>>>(rstart, rlen, n, key, p1, p2, big,
-                                                                                 nbig_dev);
-    uint32_t nbig = 0;
-    HIP_TRY(hipMemcpyAsync(&nbig, nbig_dev, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (nbig) {
-        K *tk = nullptr;
-        uint32_t *t12 = nullptr;
-        int rc;
-        if ((rc = S.get((void **)&tk, (m + 1) * sizeof(K))) || (rc = S.get((void **)&t12, 2 * (m + 1) * 4))) return rc;
-        unsigned grid = nbig < 4096u ? nbig : 4096u;
-        k_sort_big_rows<K><<<grid, 256, 0, s>>>(rstart, rlen, big, nbig, key, p1, p2, tk, t12, t12 + (m + 1));
-        HIP_TRY(hipStreamSynchronize(s));
-        S.drop(tk);
-        S.drop(t12);
-    }
+    K *tk = nullptr;
+    uint32_t *t12 = nullptr;
+    int rc;
+    if ((rc = S.get((void **)&tk, (m + 1) * sizeof(K))) || (rc = S.get((void **)&t12, 2 * (m + 1) * 4))) return rc;
+    const unsigned grid = nbig < 4096u ? nbig : 4096u;
+    k_sort_big_rows<K><<<grid, 256, 0, s>>>(rstart, rlen, big, nbig, key, p1, p2, tk, t12, t12 + (m + 1));
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+    S.drop(tk);
+    S.drop(t12);
     return TT_OK;
 }
 
@@ -559,7 +689,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     int rc;
     Scratch S;
     S.stream = s;
-    uint32_t *flags = nullptr, *outdeg = nullptr, *cursor = nullptr, *big = nullptr, *gmax = nullptr;
+    uint32_t *flags = nullptr;
     if ((rc = S.get((void **)&flags, 16))) return rc;
     HIP_TRY(hipMemsetAsync(flags, 0, 16, s));
     if (m) k_validate<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, n, flags);
@@ -572,36 +702,36 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
 
     const uint64_t nn = (uint64_t)n + 1;
     uint64_t *rowp0 = nullptr;
-    uint32_t *col0 = nullptr, *wgt0 = nullptr, *eid0 = nullptr;
+    uint4 *rec0 = nullptr;
+    uint32_t *cursor = nullptr, *big = nullptr, *mid = nullptr;
     if ((rc = dev_alloc(g, (void **)&g->deg, nn * 4)) || (rc = dev_alloc(g, (void **)&g->rstart, nn * 8)) ||
         (rc = dev_alloc(g, (void **)&g->rlen, nn * 4)) || (rc = dev_alloc(g, (void **)&g->maxw, nn * 4)) ||
         (rc = dev_alloc(g, (void **)&g->hb, nn * 4)) || (rc = dev_alloc(g, (void **)&g->col, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->wgt, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->osrc, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->eid, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->opos, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->wcol, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->wwgt, (m + 1) * 4)) ||
-        (rc = dev_alloc(g, (void **)&g->wpos, (m + 1) * 4)) || (rc = S.get((void **)&outdeg, nn * 4)) ||
+        (rc = dev_alloc(g, (void **)&g->wpos, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->in_w, (m + 1) * 4)) ||
         (rc = S.get((void **)&cursor, nn * 4)) || (rc = S.get((void **)&big, nn * 4)) ||
-        (rc = S.get((void **)&gmax, 16)) || (rc = S.get((void **)&rowp0, (nn + 1) * 8)) ||
-        (rc = S.get((void **)&col0, (m + 1) * 4)) || (rc = S.get((void **)&wgt0, (m + 1) * 4)) ||
-        (rc = S.get((void **)&eid0, (m + 1) * 4)))
+        (rc = S.get((void **)&mid, nn * 4)) || (rc = S.get((void **)&rowp0, (nn + 1) * 8)) ||
+        (rc = S.get((void **)&rec0, (m + 1) * 16)))
         return rc;
     HIP_TRY(hipMemsetAsync(g->deg, 0, nn * 4, s));
-    HIP_TRY(hipMemsetAsync(outdeg, 0, nn * 4, s));
+    HIP_TRY(hipMemsetAsync(g->rlen, 0, nn * 4, s));
     HIP_TRY(hipMemsetAsync(cursor, 0, nn * 4, s));
-    HIP_TRY(hipMemsetAsync(gmax, 0, 16, s));
+    HIP_TRY(hipMemsetAsync(g->maxw, 0, nn * 4, s));
     if (m) {
+        HIP_TRY(hipMemcpyAsync(g->in_w, w, m * 4, hipMemcpyDeviceToDevice, s));
         k_degree<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg);
-        k_outdeg<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg, outdeg);
+        k_outdeg<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg, g->rlen);
     }
-    // rows in vertex order first: rowp0[n] = m
-    if ((rc = exclusive_scan_u32_to_u64(outdeg, rowp0, nn, s, nullptr))) return rc;
-    if (m) k_scatter<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, g->deg, rowp0, cursor, col0, wgt0, eid0);
-    HIP_TRY(hipMemcpyAsync(g->rlen, outdeg, nn * 4, hipMemcpyDeviceToDevice, s));
-    if ((rc = sort_rows<uint32_t>(g, S, rowp0, g->rlen, col0, wgt0, eid0, big, flags + 1))) return rc;
-    if (n) {
-        k_row_max<<<wave_grid(n), 256, 0, s>>>(rowp0, g->rlen, n, col0, wgt0, g->maxw, flags, gmax);
-        k_row_bound<<<wave_grid(n), 256, 0, s>>>(rowp0, g->rlen, n, col0, g->maxw, g->hb);
+    // rows in vertex order first (unsorted): rowp0[n] = m
+    if ((rc = exclusive_scan_u32_to_u64(g->rlen, rowp0, nn, s, nullptr))) return rc;
+    if (m) {
+        k_scatter<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, g->deg, rowp0, cursor, rec0);
+        k_row_max<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw);
     }
+    HIP_TRY(hipMemcpyAsync(g->hb, g->maxw, nn * 4, hipMemcpyDeviceToDevice, s));
+    if (m) k_row_bound<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw, g->hb);
     // layout by descending weight_bin(hb)
     unsigned long long *ecnt = nullptr, *bincur = nullptr, *binbase = nullptr;
     if ((rc = S.get((void **)&ecnt, WBINS * 8)) || (rc = S.get((void **)&bincur, WBINS * 8)) ||
@@ -613,9 +743,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     g->ebin.assign(WBINS, 0);
     g->ebase.assign(WBINS, 0);
     HIP_TRY(hipMemcpyAsync(g->ebin.data(), ecnt, WBINS * 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (hf[0] & F_DUP) return fail(TT_E_DUP_EDGE, "the same unordered vertex pair appears twice");
     {
         uint64_t run = 0;
         for (int b = WBINS - 1; b >= 0; b--) { g->ebase[b] = run; run += g->ebin[b]; }
@@ -625,28 +753,52 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         const uint64_t per = 256ull * PLACE_ITEMS;
         k_place_rows<<<(unsigned)(((uint64_t)n + per - 1) / per), 256, 0, s>>>(g->hb, g->rlen, n, binbase, bincur, g->rstart);
     }
-    uint64_t *wkey = nullptr;
-    if ((rc = S.get((void **)&wkey, (m + 1) * 8))) return rc;
-    if (n) k_move_rows<<<wave_grid(n), 256, 0, s>>>(rowp0, g->rstart, g->rlen, n, col0, wgt0, eid0, g->col, g->wgt,
-                                                    g->eid, wkey, g->wpos);
-    S.drop(col0);
-    S.drop(wgt0);
-    S.drop(eid0);
-    if ((rc = sort_rows<uint64_t>(g, S, g->rstart, g->rlen, wkey, g->wpos, nullptr, big, flags + 1))) return rc;
-    if (m) k_split_keys<<<grid_for(m), 256, 0, s>>>(wkey, m, g->wcol, g->wwgt);
-    if (n) k_row_post<<<wave_grid(n), 256, 0, s>>>(g->rstart, g->rlen, n, g->eid, g->osrc, g->opos);
+    // both row orders: counted ranks for rows up to MID_MAX entries, sorts for longer ones
+    if (m) k_rank_small<<<grid_for(m), 256, 0, s>>>(rec0, rowp0, m, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
+                                                    g->opos, g->wcol, g->wwgt, g->wpos, flags);
+    HIP_TRY(hipMemsetAsync(flags + 1, 0, 8, s));
+    if (n) k_list_long<<<grid_for(n), 256, 0, s>>>(g->rlen, n, mid, flags + 2, big, flags + 1);
+    HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t nbig = hf[1], nmid = hf[2];
+    if (nmid) {
+        const unsigned gm = nmid < 8192u ? nmid : 8192u;
+        k_rank_mid<<<gm, 256, 0, s>>>(mid, nmid, rec0, rowp0, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
+                                      g->opos, g->wcol, g->wwgt, g->wpos, flags);
+    }
+    if (nbig) {
+        const unsigned gb = nbig < 4096u ? nbig : 4096u;
+        k_move_big<<<gb, 256, 0, s>>>(big, nbig, rowp0, g->rstart, g->rlen, rec0, g->col, g->wgt, g->eid, g->osrc);
+        if ((rc = sort_big<uint32_t>(g, S, g->rstart, g->rlen, big, nbig, g->col, g->wgt, g->eid))) return rc;
+        uint64_t *wkey = nullptr;
+        if ((rc = S.get((void **)&wkey, (m + 1) * 8))) return rc;
+        k_post_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->opos, wkey, g->wpos, flags);
+        if ((rc = sort_big<uint64_t>(g, S, g->rstart, g->rlen, big, nbig, wkey, g->wpos, nullptr))) return rc;
+        k_split_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, wkey, g->wcol, g->wwgt);
+        S.drop(wkey);
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    S.drop(rec0);
     unsigned long long *hist = nullptr;
     if ((rc = S.get((void **)&hist, WBINS * 8))) return rc;
     HIP_TRY(hipMemsetAsync(hist, 0, WBINS * 8, s));
     if (m) k_weight_hist<<<grid_for(m), 256, 0, s>>>(g->wgt, m, hist);
     g->whist.assign(WBINS, 0);
-    uint32_t hm[4];
     HIP_TRY(hipMemcpyAsync(g->whist.data(), hist, WBINS * 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hm, gmax, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
-    g->wmax = hm[0];
-    g->max_outdeg = hm[1];
+    if (hf[0] & F_DUP) return fail(TT_E_DUP_EDGE, "the same unordered vertex pair appears twice");
+    // an upper bound of the largest weight: the top of the highest non-empty bin
+    g->wmax = 0;
+    for (int b = WBINS - 1; b >= 0; b--)
+        if (g->whist[b]) {
+            // first weight of bin b+1, in 64 bits (it is 2^32 for the top bin)
+            const uint32_t nb = (uint32_t)b + 1;
+            const uint64_t up = nb < 64 ? nb : ((uint64_t)((nb - 64) % 64 + 64) << ((nb - 64) / 64));
+            g->wmax = (uint32_t)std::min<uint64_t>(up - 1, 0xFFFFFFFFull);
+            break;
+        }
     // the weight-ordered stream of entries
     g->wbase.assign(WBINS, 0);
     {

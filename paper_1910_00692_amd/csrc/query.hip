@@ -474,7 +474,7 @@ __device__ __forceinline__ trec worst_rec() {
 }
 
 // Sorts each tile of STILE records (best first) in LDS and keeps its first S0.
-__global__ __launch_bounds__(256) void k_tile_sort(const trec *in, trec *out, uint64_t N, uint32_t S0) {
+__global__ __launch_bounds__(512) void k_tile_sort(const trec *in, trec *out, uint64_t N, uint32_t S0) {
     __shared__ trec sh[STILE];
     const uint64_t base = (uint64_t)blockIdx.x * STILE;
     const uint32_t cover = (uint32_t)((N - base) < (uint64_t)STILE ? (N - base) : (uint64_t)STILE);
@@ -591,26 +591,52 @@ __global__ __launch_bounds__(256) void k_es_guide(const void *prefix, uint64_t m
 
 template <int KIND>
 __global__ __launch_bounds__(256) void k_es_draw(const void *prefix, const uint32_t *G, uint32_t bits, uint64_t m,
-                                                 uint64_t budget, uint64_t seed, const uint32_t *opos,
-                                                 const uint32_t *osrc, uint8_t *emark, uint8_t *vflag) {
+                                                 uint64_t budget, uint64_t seed, const uint32_t *opos, uint8_t *emark) {
     typedef typename Draw<KIND>::T T;
     const T *P = (const T *)prefix;
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < budget; s += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t x = splitmix64_at(seed, s);
         const uint64_t j = x >> (64 - bits);
         const uint64_t e = first_above<T>(P, G[j], G[j + 1], Draw<KIND>::r(P, m, x));
-        const uint32_t pos = opos[e];
-        emark[pos] = 1;
-        vflag[osrc[pos]] = 1;
+        emark[opos[e]] = 1;
     }
 }
 
+// vflag[u] = 1 for every tail u with a drawn out-entry (a streaming pass over the marks).
+__global__ __launch_bounds__(256) void k_mark_tails(const uint8_t *emark, uint64_t m, const uint32_t *osrc,
+                                                    uint8_t *vflag) {
+    const uint64_t nv = (m + 15) / 16;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint4 x = ((const uint4 *)emark)[i];
+        if ((x.x | x.y | x.z | x.w) == 0) continue;
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+        for (int k = 0; k < 16; k++) {
+            const uint64_t e = i * 16 + k;
+            if (e < m && ((w[k >> 2] >> ((k & 3) * 8)) & 0xFFu)) vflag[osrc[e]] = 1;
+        }
+    }
+}
+
+// Number of non-zero bytes in mark[0..m) (16-byte loads; the buffer is 256-byte aligned).
 __global__ __launch_bounds__(256) void k_count_marks(const uint8_t *mark, uint64_t m, unsigned long long *out) {
     unsigned long long c = 0;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
-        c += mark[e] != 0;
+    const uint64_t nv = m / 16;
+    const uint4 *v = (const uint4 *)mark;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = tid; i < nv; i += stride) {
+        const uint4 x = v[i];
+        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            // one bit per non-zero byte
+            const uint32_t y = w[k] | (w[k] >> 4);
+            const uint32_t z = y | (y >> 2);
+            c += __popc((z | (z >> 1)) & 0x01010101u);
+        }
+    }
+    for (uint64_t e = nv * 16 + tid; e < m; e += stride) c += mark[e] != 0;
     c = wave_sum(c);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&out[blockIdx.x & 1023], c);
 }
 
 __global__ __launch_bounds__(256) void k_mark_vertices(const uint32_t *ids, uint32_t cnt, uint32_t n, uint8_t *vflag) {
@@ -725,7 +751,7 @@ int select_topk(tt_graph *g, uint64_t N, uint32_t k, trec **res) {
     const uint32_t S0 = k < (uint32_t)STILE ? k : (uint32_t)STILE;
     uint64_t nruns = (N + STILE - 1) / STILE;
     trec *in = g->buf0, *out = g->buf1;
-    k_tile_sort<<<(unsigned)nruns, 256, 0, s>>>(in, out, N, S0);
+    k_tile_sort<<<(unsigned)nruns, 512, 0, s>>>(in, out, N, S0);
     std::swap(in, out);
     uint64_t C = STILE;
     uint32_t S = S0;
@@ -1092,20 +1118,19 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
     HIP_TRY(hipMemsetAsync(g->vflag, 0, (uint64_t)g->n + 1, s));
     const unsigned grid = (unsigned)std::min<uint64_t>((budget + 255) / 256, (uint64_t)num_cus() * 16);
     const uint32_t bits = g->guide_bits;
-    if (kind == 0)
-        k_es_draw<0><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
-    else if (kind == 1)
-        k_es_draw<1><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
-    else
-        k_es_draw<2><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->osrc, g->emark, g->vflag);
+    if (kind == 0) k_es_draw<0><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
+    else if (kind == 1) k_es_draw<1><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
+    else k_es_draw<2><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
+    k_mark_tails<<<enum_grid(g->m / 16 + 1), 256, 0, s>>>(g->emark, g->m, g->osrc, g->vflag);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(g->ev[7], s));
     rc = run_topk(g, k, p, FILTER_EDGES, out, n_out, stats);
     if (!rc && stats) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, g->ev[6], g->ev[7]) == hipSuccess) stats->sample_ms = ms;
-        HIP_TRY(hipMemsetAsync(g->dcount + 8, 0, 8, s));
-        k_count_marks<<<enum_grid(g->m), 256, 0, s>>>(g->emark, g->m, g->dcount + 8);
+        // marks are counted into the spread slots of counter 0 (cleared after every query)
+        k_count_marks<<<std::min<unsigned>(enum_grid(g->m / 16 + 1), 1024u), 256, 0, s>>>(g->emark, g->m, g->spart);
+        k_reduce_stats<<<1, 256, 0, s>>>(g->spart, g->dcount + 8);
         HIP_TRY(hipMemcpyAsync(g->hcount + 8, g->dcount + 8, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         stats->distinct_sampled = g->hcount[8];

@@ -98,25 +98,25 @@ template <typename T, typename F> int scan_impl(uint64_t n, F f, T *out, int inc
     return TT_OK;
 }
 
-// w^q of input edge e, read through the entry position of e (q = 1, 2, 3 exact)
+// w^q of input edge e (q = 1, 2, 3 exact)
 struct PowU128 {
-    const uint32_t *wgt, *opos;
+    const uint32_t *w_in;
     int q;
     __device__ u128 operator()(uint64_t e) const {
-        u128 w = wgt[opos[e]], t = w;
+        u128 w = w_in[e], t = w;
         if (q >= 2) t *= w;
         if (q >= 3) t *= w;
         return t;
     }
 };
 struct PowU64 {
-    const uint32_t *wgt, *opos;
-    __device__ uint64_t operator()(uint64_t e) const { return wgt[opos[e]]; }
+    const uint32_t *w_in;
+    __device__ uint64_t operator()(uint64_t e) const { return w_in[e]; }
 };
 struct PowF64 {
-    const uint32_t *wgt, *opos;
+    const uint32_t *w_in;
     double q;
-    __device__ double operator()(uint64_t e) const { return pow((double)wgt[opos[e]], q); }
+    __device__ double operator()(uint64_t e) const { return pow((double)w_in[e], q); }
 };
 
 } // namespace
@@ -126,8 +126,7 @@ int exclusive_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hip
 }
 
 int inclusive_weight_prefix(tt_graph *g, double q, void *out) {
-    if (q == 1.0) return scan_impl<uint64_t>(g->m, PowU64{g->wgt, g->opos}, (uint64_t *)out, 1, g->stream, g);
-    if (q == 2.0 || q == 3.0)
-        return scan_impl<u128>(g->m, PowU128{g->wgt, g->opos, (int)q}, (u128 *)out, 1, g->stream, g);
-    return scan_impl<double>(g->m, PowF64{g->wgt, g->opos, q}, (double *)out, 1, g->stream, g);
+    if (q == 1.0) return scan_impl<uint64_t>(g->m, PowU64{g->in_w}, (uint64_t *)out, 1, g->stream, g);
+    if (q == 2.0 || q == 3.0) return scan_impl<u128>(g->m, PowU128{g->in_w, (int)q}, (u128 *)out, 1, g->stream, g);
+    return scan_impl<double>(g->m, PowF64{g->in_w, q}, (double *)out, 1, g->stream, g);
 }
