@@ -49,6 +49,85 @@ WORKLOADS = {
 }
 
 
+def run_serve(args):
+    """Served workload: a resident n=10M, ~200M-edge graph and a Poisson request stream (mean
+    2,000 req/s; k log-uniform in [10, 1e4]; p from {-inf, -1, 0, 1, 2, +inf}; 20% restricted
+    to triangles touching 1,000 random vertices), submitted at its arrival times to the
+    continuous-batching server; compared with the same requests run one at a time."""
+    import threading
+    import torch
+    import graphgen
+    import paper_1910_00692_amd as tt
+
+    t = time.time()
+    g = graphgen.serve_graph(n=args.serve_n, m=args.serve_m)
+    print(f"[bench] serve graph n={g.n} m={g.m} ({time.time() - t:.1f}s)", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    s_d = torch.from_numpy(g.src.view(np.int32)).to(dev)
+    d_d = torch.from_numpy(g.dst.view(np.int32)).to(dev)
+    w_d = torch.from_numpy(g.w.view(np.int32)).to(dev)
+    t = time.perf_counter()
+    G = tt.Graph(g.n, s_d, d_d, w_d, stream=torch.cuda.current_stream(dev))
+    build_ms = (time.perf_counter() - t) * 1e3
+    del s_d, d_d, w_d
+    reqs = graphgen.query_stream(args.requests, g.n, seed=1)
+    print(f"[bench] built in {build_ms:.0f} ms; {len(reqs)} requests", file=sys.stderr, flush=True)
+    # plain single-query path, one request after the other (service time only)
+    for r in reqs[:8]:
+        G.topk(r["k"], r["p"], subset=r["subset"])
+    single = []
+    t0 = time.perf_counter()
+    for r in reqs:
+        a = time.perf_counter()
+        G.topk(r["k"], r["p"], subset=r["subset"])
+        single.append((time.perf_counter() - a) * 1e3)
+    single_s = time.perf_counter() - t0
+    print(f"[bench] single-query path: {len(reqs) / single_s:.1f} req/s", file=sys.stderr, flush=True)
+    S = tt.Server(G, slots=args.slots, scratch_budget=args.budget_gb << 30)
+    for r in reqs[:8]:
+        S.wait(S.submit(r["k"], r["p"], r["subset"]))
+    tickets = [None] * len(reqs)
+    lat = [None] * len(reqs)
+    done_t = [None] * len(reqs)
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for i in range(len(reqs)):
+            ready.acquire()
+            res = S.wait(tickets[i])
+            lat[i] = res["stats"]["total_ms"]
+            done_t[i] = time.perf_counter()
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    start = time.perf_counter()
+    for i, r in enumerate(reqs):
+        now = time.perf_counter() - start
+        if r["t"] > now:
+            time.sleep(r["t"] - now)
+        tickets[i] = S.submit(r["k"], r["p"], r["subset"])
+        ready.release()
+    th.join()
+    span = max(done_t) - start
+    info = S.info()
+    S.close()
+    G.close()
+    out = {
+        "metric": METRIC, "value": len(reqs) / span, "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "served: chung-lu n=10M m~200M gamma2.1 zipf(1.8); Poisson 2000 req/s, k log-uniform "
+                               "[10,1e4], p in {-inf,-1,0,1,2,+inf}, 20% subset(1000) queries",
+                   "n": g.n, "m": g.m, "requests": len(reqs), "slots": args.slots, "budget_gb": args.budget_gb,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
+        "single_query_path": {"queries_per_s": len(reqs) / single_s, "p50_ms": pct(single, 50),
+                              "p99_ms": pct(single, 99)},
+        "offered_rate": len(reqs) / max(reqs[-1]["t"], 1e-9), "server": info, "build_ms": build_ms,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def pct(xs, q):
     return float(np.percentile(np.asarray(xs, np.float64), q)) if xs else None
 
@@ -58,15 +137,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS) + ["serve"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sampling", action="store_true", help="exact queries only")
+    ap.add_argument("--requests", type=int, default=2000, help="served workload: number of requests")
+    ap.add_argument("--slots", type=int, default=4, help="served workload: server slots")
+    ap.add_argument("--budget-gb", type=int, default=16, help="served workload: scratch budget (GiB)")
+    ap.add_argument("--serve-n", type=int, default=10_000_000)
+    ap.add_argument("--serve-m", type=int, default=200_000_000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this library runs on one GPU; a multi-GPU run is not part of this build "
               "(DESIGN.md describes how the path would shard).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serve":
+        return run_serve(args)
 
     import torch
     import graphgen

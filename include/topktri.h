@@ -120,6 +120,45 @@ int sample_heavy_triangles(tt_graph *g, uint32_t k, double p, uint64_t budget, u
 int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed,
                               tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
 
+/*
+ * Serving: a request loop over one resident graph.  Callers: services that answer a stream of
+ * top-k queries (any k, any p, optionally restricted to a vertex subset as in
+ * topk_triangles_ex) on a graph kept in device memory.  Each of `slots` workers owns a HIP
+ * stream and its query scratch, so admitted requests overlap on the device.  Requests wait in
+ * FIFO order and are admitted when a worker is free and their scratch bytes
+ * (server_request_bytes) fit into `scratch_budget` together with the requests already
+ * running; a request arriving while others run is admitted as soon as one finishes.  Every
+ * result is exactly the result of topk_triangles_ex for the same arguments.  The graph must
+ * outlive the server and must not be freed while it runs.  All calls are thread-safe.
+ */
+typedef struct tt_server tt_server;
+
+/* slots in [1, 64]; scratch_budget in bytes of device memory. */
+int server_create(tt_graph *g, uint32_t slots, uint64_t scratch_budget, tt_server **out);
+
+/* Device scratch bytes a request with this k and subset size is charged at admission. */
+uint64_t server_request_bytes(tt_server *s, uint32_t k, uint32_t subset_n);
+
+/* Queues a request; *ticket identifies it.  subset: HOST array copied before return.
+ * TT_E_BUDGET if the request can never fit the budget; TT_E_VERTEX_RANGE for a bad subset. */
+int server_submit(tt_server *s, uint32_t k, double p, const uint32_t *subset, uint32_t subset_n,
+                  uint64_t *ticket);
+
+/* *done = 1 once the request has finished (its result waits for server_wait). */
+int server_poll(tt_server *s, uint64_t ticket, int *done);
+
+/* Blocks until the request has finished, then returns its result (out: HOST, room for k) and
+ * releases the ticket.  stats->total_ms is the time from submission to completion. */
+int server_wait(tt_server *s, uint64_t ticket, tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
+
+/* Counters since creation: admitted and completed requests, peak admitted scratch bytes,
+ * longest queue and most requests running at once.  Any pointer may be NULL. */
+int server_info(tt_server *s, uint64_t *admitted, uint64_t *completed, uint64_t *peak_bytes,
+                uint32_t *max_queue, uint32_t *max_running);
+
+/* Finishes every queued request, then stops the workers and frees their memory.  NULL-safe. */
+void server_destroy(tt_server *s);
+
 /* Number of vertices / undirected edges of a loaded graph (0 for NULL). */
 uint32_t graph_num_vertices(const tt_graph *g);
 uint64_t graph_num_edges(const tt_graph *g);

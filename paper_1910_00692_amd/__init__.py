@@ -24,7 +24,8 @@ TT_E_VERTEX_RANGE, TT_E_NOMEM, TT_E_DEVICE, TT_E_BUDGET, TT_E_TOO_LARGE = -5, -6
 
 EXPORTED = ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles_ex", "sample_heavy_triangles",
             "sample_heavy_triangles_ex", "graph_num_vertices", "graph_num_edges", "graph_device_bytes",
-            "graph_free", "tt_last_error")
+            "graph_free", "tt_last_error", "server_create", "server_request_bytes", "server_submit", "server_poll",
+            "server_wait", "server_info", "server_destroy")
 
 
 class Triangle(ctypes.Structure):
@@ -93,8 +94,20 @@ def library():
         lib.graph_free.restype = None
         lib.tt_last_error.argtypes = []
         lib.tt_last_error.restype = ctypes.c_char_p
+        p64 = ctypes.POINTER(ctypes.c_uint64)
+        pint = ctypes.POINTER(ctypes.c_int)
+        lib.server_create.argtypes = [vp, u32, u64, pg]
+        lib.server_request_bytes.argtypes = [vp, u32, u32]
+        lib.server_request_bytes.restype = u64
+        lib.server_submit.argtypes = [vp, u32, dbl, p32, u32, p64]
+        lib.server_poll.argtypes = [vp, u64, pint]
+        lib.server_wait.argtypes = [vp, u64, ptri, p32, pst]
+        lib.server_info.argtypes = [vp, p64, p64, p64, p32, p32]
+        lib.server_destroy.argtypes = [vp]
+        lib.server_destroy.restype = None
         for name in ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles_ex",
-                     "sample_heavy_triangles", "sample_heavy_triangles_ex"):
+                     "sample_heavy_triangles", "sample_heavy_triangles_ex", "server_create", "server_submit",
+                     "server_poll", "server_wait", "server_info"):
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -183,6 +196,69 @@ class Graph:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             library().graph_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop over a resident Graph (see server_create)."""
+
+    def __init__(self, graph: Graph, slots: int = 4, scratch_budget: int = 4 << 30):
+        self.graph = graph
+        self._h = ctypes.c_void_p()
+        _check(library().server_create(graph.handle, int(slots), int(scratch_budget), ctypes.byref(self._h)))
+        self._k = {}
+
+    def request_bytes(self, k: int, subset_n: int = 0) -> int:
+        return int(library().server_request_bytes(self._h, int(k), int(subset_n)))
+
+    def submit(self, k: int, p: float, subset=None) -> int:
+        t = ctypes.c_uint64(0)
+        sub_p, sub_n = None, 0
+        if subset is not None and len(subset):
+            sub = _u32(subset)
+            sub_p, sub_n = sub.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), int(sub.shape[0])
+        _check(library().server_submit(self._h, int(k), float(p), sub_p, sub_n, ctypes.byref(t)))
+        self._k[t.value] = int(k)
+        return int(t.value)
+
+    def done(self, ticket: int) -> bool:
+        d = ctypes.c_int(0)
+        _check(library().server_poll(self._h, int(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        k = self._k.pop(int(ticket), 1)
+        buf = (Triangle * max(k, 1))()
+        n_out = ctypes.c_uint32(0)
+        st = QueryStats()
+        _check(library().server_wait(self._h, int(ticket), buf, ctypes.byref(n_out), ctypes.byref(st)))
+        out = _result(buf, n_out.value)
+        out["stats"] = st.as_dict()
+        return out
+
+    def info(self):
+        a, c, pk = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        mq, mr = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(library().server_info(self._h, ctypes.byref(a), ctypes.byref(c), ctypes.byref(pk), ctypes.byref(mq),
+                                     ctypes.byref(mr)))
+        return {"admitted": a.value, "completed": c.value, "peak_bytes": pk.value, "max_queue": mq.value,
+                "max_running": mr.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __enter__(self):

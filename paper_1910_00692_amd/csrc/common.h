@@ -41,6 +41,39 @@ struct cand {
     uint32_t u, v, a, pos;
 };
 
+// ----------------------------------------------------------------------------- query state
+// Device state of one query in flight: its stream, candidate buffers and counters.  A graph
+// owns one for its synchronous calls; a server owns one per slot, so that queries on one
+// resident graph run concurrently on separate streams.
+struct QueryCtx {
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    trec *buf0 = nullptr, *buf1 = nullptr; // triangle buffer and its sort ping-pong
+    uint64_t buf_cap = 0;
+    struct cand *cand = nullptr;           // candidate entries of the current piece of a pass
+    uint64_t cand_cap = 0;
+    uint64_t max_cand = 1ull << 25;        // a pass streams its entries in pieces of this size
+    uint64_t min_buf = 1ull << 22;         // smallest triangle buffer (records)
+    uint32_t *ccnt = nullptr;              // candidates per filter block
+    unsigned long long *spart = nullptr;   // spread per-pass counters
+    unsigned long long *dcount = nullptr;  // [16] counters
+    unsigned long long *hcount = nullptr;  // pinned mirror
+    tt_triangle *dout = nullptr;
+    uint64_t dout_cap = 0;
+    uint8_t *vflag = nullptr;              // [n]
+    uint8_t *vflag2 = nullptr;             // [n]
+    // subset queries: the entries that can be the base of a triangle touching the subset
+    uint32_t *sub_src = nullptr, *sub_col = nullptr, *sub_wgt = nullptr, *sub_pos = nullptr;
+    uint32_t *sub_vlist = nullptr;         // in-neighbours of the subset (outside it)
+    uint64_t sub_cap = 1ull << 22;         // capacity of the compact stream and of the list
+    uint64_t sub_len = 0;                  // entries in the compact stream
+    bool sub_active = false;               // the passes stream the compact list
+    hipEvent_t ev[8] = {};
+    std::vector<hipEvent_t> band_ev;       // start/stop pairs of the passes of a query
+};
+void ctx_release(QueryCtx *q); // device memory and events (not the stream)
+int ensure_in_csr(tt_graph *g, hipStream_t s);
+
 // ----------------------------------------------------------------------------- graph
 struct tt_graph {
     uint32_t n = 0;
@@ -71,25 +104,19 @@ struct tt_graph {
                                 //     triangle based at u, for every p
     uint32_t *deg = nullptr;    // [n] undirected degree
     uint32_t *in_w = nullptr;   // [m] weights in input order (sampling prefix sums)
+    // transpose of the oriented CSR, built on the first subset query: for every head v, the
+    // tails u of its in-entries u->v and the positions of those entries
+    uint64_t *irstart = nullptr; // [n+2]
+    uint32_t *itail = nullptr, *ipos = nullptr;
+    std::mutex init_mu;
     uint32_t wmax = 0;          // largest weight in the graph
     uint32_t max_outdeg = 0;
     std::vector<uint64_t> whist; // host: edge count per weight_bin(w)
     std::vector<uint64_t> ebin;  // host: entry count per weight_bin(hb[tail])
     std::vector<uint64_t> ebase; // host: first entry of each bin (bins in descending order)
     uint64_t bytes = 0;
-    // query scratch, grown on demand and kept for later queries
-    trec *buf0 = nullptr, *buf1 = nullptr;
-    struct cand *cand = nullptr;      // [m+1] candidate entries of the current pass (16 B each)
-    uint32_t *ccnt = nullptr;         // candidates per filter block
-    unsigned long long *spart = nullptr; // spread per-pass counters
-    uint64_t buf_cap = 0;
-    unsigned long long *dcount = nullptr; // [16] counters
-    unsigned long long *hcount = nullptr; // pinned mirror
-    tt_triangle *dout = nullptr;
-    uint64_t dout_cap = 0;
+    QueryCtx q;                 // device state of the synchronous query calls
     uint8_t *emark = nullptr;   // [m] per-entry marks (sampling)
-    uint8_t *vflag = nullptr;   // [n]
-    uint8_t *vflag2 = nullptr;  // [n]
     // sampling tables, cached for the two most recent exponents q
     struct SampleTable {
         double q = -1.0;
@@ -99,8 +126,6 @@ struct tt_graph {
     } tables[2];
     uint32_t guide_bits = 0;
     uint64_t use_clock = 0;
-    hipEvent_t ev[8] = {};
-    std::vector<hipEvent_t> band_ev; // start/stop pairs of the enumeration passes of a query
     std::mutex mu;
 };
 

@@ -624,19 +624,15 @@ unsigned wave_grid(uint64_t rows) { // one wave per row, grid-stride
 
 void release(tt_graph *g) {
     if (!g) return;
-    void *ptrs[] = {g->rstart, g->rlen, g->col,    g->wgt,    g->osrc,   g->eid,   g->opos,  g->wcol,
-                    g->wwgt,   g->wpos, g->maxw,   g->hb,     g->deg,    g->buf0,  g->buf1,  g->dcount,
-                    g->dout,   g->emark, g->vflag, g->vflag2, g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->cand, g->ccnt, g->spart, g->in_w};
+    void *ptrs[] = {g->rstart, g->rlen,   g->col,    g->wgt,  g->osrc,    g->eid,   g->opos,
+                    g->wcol,   g->wwgt,   g->wpos,   g->maxw, g->hb,      g->deg,   g->emark,
+                    g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->in_w,  g->irstart, g->itail, g->ipos};
     for (void *p : ptrs) dev_free(g, p, 0);
     for (auto &t : g->tables) {
         dev_free(g, t.prefix, 0);
         dev_free(g, t.guide, 0);
     }
-    if (g->hcount) (void)hipHostFree(g->hcount);
-    for (auto &e : g->ev)
-        if (e) (void)hipEventDestroy(e);
-    for (auto &e : g->band_ev)
-        if (e) (void)hipEventDestroy(e);
+    ctx_release(&g->q);
 }
 
 // Temporary device buffers of one build, freed on every exit path.
@@ -677,6 +673,40 @@ int sort_big(tt_graph *g, Scratch &S, const uint64_t *rstart, const uint32_t *rl
     S.drop(tk);
     S.drop(t12);
     return TT_OK;
+}
+
+// In-degrees of the oriented CSR (heads of all entries), runs merged per wave.
+__global__ __launch_bounds__(256) void k_indeg(const uint32_t *col, uint64_t m, uint32_t *indeg) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
+        const uint64_t e = base + lane;
+        const bool valid = e < m;
+        const uint32_t v = valid ? col[e] : 0u;
+        const WaveRuns r = wave_runs(v, valid);
+        if (valid && r.first == lane) atomicAdd(&indeg[v], (uint32_t)(r.end - lane));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_in_scatter(const uint32_t *col, const uint32_t *osrc, uint64_t m,
+                                                    const uint64_t *irstart, uint32_t *cursor, uint32_t *itail,
+                                                    uint32_t *ipos) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
+        const uint64_t e = base + lane;
+        const bool valid = e < m;
+        const uint32_t v = valid ? col[e] : 0u;
+        const WaveRuns r = wave_runs(v, valid);
+        uint32_t slot = 0;
+        if (valid && r.first == lane) slot = atomicAdd(&cursor[v], (uint32_t)(r.end - lane));
+        slot = __shfl(slot, r.first, 64) + (uint32_t)(lane - r.first);
+        if (valid) {
+            const uint64_t d = irstart[v] + slot;
+            itail[d] = osrc[e];
+            ipos[d] = (uint32_t)e;
+        }
+    }
 }
 
 } // namespace
@@ -820,6 +850,38 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     return TT_OK;
 }
 
+// The transpose of the oriented CSR (built once, on the first subset query).
+int ensure_in_csr(tt_graph *g, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g->init_mu);
+    if (g->irstart) return TT_OK;
+    const uint64_t nn = (uint64_t)g->n + 1, m = g->m;
+    int rc;
+    Scratch S;
+    S.stream = s;
+    uint32_t *indeg = nullptr, *cursor = nullptr;
+    uint64_t *irstart = nullptr;
+    uint32_t *itail = nullptr, *ipos = nullptr;
+    if ((rc = S.get((void **)&indeg, nn * 4)) || (rc = S.get((void **)&cursor, nn * 4)) ||
+        (rc = dev_alloc(g, (void **)&irstart, (nn + 1) * 8)) || (rc = dev_alloc(g, (void **)&itail, (m + 1) * 4)) ||
+        (rc = dev_alloc(g, (void **)&ipos, (m + 1) * 4))) {
+        dev_free(g, irstart, 0);
+        dev_free(g, itail, 0);
+        dev_free(g, ipos, 0);
+        return rc;
+    }
+    HIP_TRY(hipMemsetAsync(indeg, 0, nn * 4, s));
+    HIP_TRY(hipMemsetAsync(cursor, 0, nn * 4, s));
+    if (m) k_indeg<<<grid_for(m), 256, 0, s>>>(g->col, m, indeg);
+    if ((rc = exclusive_scan_u32_to_u64(indeg, irstart, nn, s, nullptr))) return rc;
+    if (m) k_in_scatter<<<grid_for(m), 256, 0, s>>>(g->col, g->osrc, m, irstart, cursor, itail, ipos);
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    g->irstart = irstart;
+    g->itail = itail;
+    g->ipos = ipos;
+    return TT_OK;
+}
+
 static int load_common(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w,
                        void *stream, bool host, tt_graph **out) {
     if (!out) return fail(TT_E_ARG, "out is NULL");
@@ -838,6 +900,7 @@ static int load_common(uint32_t n, uint64_t m, const uint32_t *src, const uint32
         if (e != hipSuccess) { delete g; return fail(TT_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e)); }
         g->owns_stream = true;
     }
+    g->q.stream = g->stream;
     int rc = TT_OK;
     const uint32_t *ds = src, *dd = dst, *dw = w;
     uint32_t *copy = nullptr;
@@ -872,6 +935,29 @@ extern "C" int graph_load_device(uint32_t n, uint64_t m, const uint32_t *src, co
 extern "C" uint32_t graph_num_vertices(const tt_graph *g) { return g ? g->n : 0; }
 extern "C" uint64_t graph_num_edges(const tt_graph *g) { return g ? g->m : 0; }
 extern "C" uint64_t graph_device_bytes(const tt_graph *g) { return g ? g->bytes : 0; }
+
+void ctx_release(QueryCtx *q) {
+    void *ptrs[] = {q->buf0,    q->buf1,    q->cand,    q->ccnt,    q->spart,    q->dcount, q->dout,
+                    q->vflag,   q->vflag2,  q->sub_src, q->sub_col, q->sub_wgt,  q->sub_pos, q->sub_vlist};
+    for (void *p : ptrs) dev_free(nullptr, p, 0);
+    q->buf0 = q->buf1 = nullptr;
+    q->cand = nullptr;
+    q->ccnt = nullptr;
+    q->spart = nullptr;
+    q->dcount = nullptr;
+    q->dout = nullptr;
+    q->vflag = q->vflag2 = nullptr;
+    q->sub_src = q->sub_col = q->sub_wgt = q->sub_pos = q->sub_vlist = nullptr;
+    q->sub_active = false;
+    q->buf_cap = q->cand_cap = q->dout_cap = 0;
+    if (q->hcount) (void)hipHostFree(q->hcount);
+    q->hcount = nullptr;
+    for (auto &e : q->ev)
+        if (e) { (void)hipEventDestroy(e); e = nullptr; }
+    for (auto &e : q->band_ev)
+        if (e) (void)hipEventDestroy(e);
+    q->band_ev.clear();
+}
 
 extern "C" void graph_free(tt_graph *g) {
     if (!g) return;

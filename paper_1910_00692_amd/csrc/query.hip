@@ -22,8 +22,12 @@
 // run by binary search) with runs truncated to k, down to one run.
 #include <cmath>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <new>
+#include <thread>
+#include <unordered_map>
 
 #include "common.h"
 #include "scan.h"
@@ -167,6 +171,7 @@ struct EnumArgs {
     // stream is the head-sorted layout itself) and its length
     const uint32_t *s_src, *s_col, *s_wgt, *s_pos;
     uint64_t E;
+    uint64_t pos_off; // head-sorted position of stream entry 0 when s_pos is NULL
     const unsigned long long *skip; // set (between passes) once the answer is complete
     Band B;
     const uint8_t *emark;  // FILTER_EDGES: drawn entries (head-sorted positions)
@@ -252,7 +257,7 @@ template <int FILTER> __global__ __launch_bounds__(256) void k_filter(EnumArgs A
                 u[k] = A.s_src[e];
                 v[k] = A.s_col[e];
                 a[k] = A.s_wgt[e];
-                pos[k] = A.s_pos ? A.s_pos[e] : (uint32_t)e;
+                pos[k] = A.s_pos ? A.s_pos[e] : (uint32_t)(e + A.pos_off);
             }
         }
         uint32_t n_pass = 0, rank[FILTER_UNROLL];
@@ -652,7 +657,7 @@ __global__ __launch_bounds__(256) void k_mark_out_nbrs(const uint32_t *osrc, con
 }
 
 // ----------------------------------------------------------------------------- host side
-u128 key_of_uniform(int mode, double p, uint32_t t) {
+u128 key_of_uniform(int mode, uint32_t t) {
     switch (mode) {
     case MODE_MAX:
     case MODE_MIN: return t;
@@ -663,7 +668,6 @@ u128 key_of_uniform(int mode, double p, uint32_t t) {
         double d = (double)t;
         uint64_t b;
         std::memcpy(&b, &d, 8);
-        (void)p;
         return b;
     }
     }
@@ -703,37 +707,54 @@ unsigned filter_grid(uint64_t E) {
     return (unsigned)(blocks ? blocks : 1);
 }
 
-int ensure_scratch(tt_graph *g, uint64_t cap, uint64_t kout) {
+// Scratch bytes a query holds while it runs (the admission size of a served request).
+uint64_t query_bytes(const tt_graph *g, const QueryCtx *q, uint32_t k, bool subset) {
+    const uint64_t cap = std::max<uint64_t>(q->min_buf, 16ull * k);
+    const uint64_t cand = std::min<uint64_t>(g->m + 1, q->max_cand);
+    uint64_t b = 2 * cap * sizeof(trec) + cand * sizeof(cand) + (uint64_t)k * sizeof(tt_triangle) +
+                 MAX_SEG * 4 + 5 * STAT_SLOTS * 8 + 256;
+    if (subset) b += 2 * ((uint64_t)g->n + 1);
+    return b;
+}
+
+int ensure_scratch(const tt_graph *g, QueryCtx *q, uint64_t cap, uint64_t kout) {
     int rc;
-    if (!g->cand && (rc = dev_alloc(g, (void **)&g->cand, (g->m + 1) * sizeof(cand)))) return rc;
-    if (!g->ccnt && (rc = dev_alloc(g, (void **)&g->ccnt, MAX_SEG * sizeof(uint32_t)))) return rc;
-    if (!g->spart) {
-        if ((rc = dev_alloc(g, (void **)&g->spart, 5 * STAT_SLOTS * sizeof(unsigned long long)))) return rc;
-        HIP_TRY(hipMemsetAsync(g->spart, 0, 5 * STAT_SLOTS * sizeof(unsigned long long), g->stream));
-    }
-    if (!g->dcount) {
-        if ((rc = dev_alloc(g, (void **)&g->dcount, 16 * sizeof(unsigned long long)))) return rc;
-        if (hipHostMalloc((void **)&g->hcount, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+    if (!q->dcount) {
+        if ((rc = dev_alloc(nullptr, (void **)&q->dcount, 16 * sizeof(unsigned long long)))) return rc;
+        if (hipHostMalloc((void **)&q->hcount, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
             return fail(TT_E_NOMEM, "hipHostMalloc failed");
-        for (auto &e : g->ev)
+        for (auto &e : q->ev)
             if (hipEventCreate(&e) != hipSuccess) return fail(TT_E_DEVICE, "hipEventCreate failed");
     }
-    if (g->buf_cap < cap) {
-        dev_free(g, g->buf0, g->buf_cap * sizeof(trec));
-        dev_free(g, g->buf1, g->buf_cap * sizeof(trec));
-        g->buf0 = g->buf1 = nullptr;
-        g->buf_cap = 0;
-        if ((rc = dev_alloc(g, (void **)&g->buf0, cap * sizeof(trec))) ||
-            (rc = dev_alloc(g, (void **)&g->buf1, cap * sizeof(trec))))
-            return rc;
-        g->buf_cap = cap;
+    if (!q->ccnt && (rc = dev_alloc(nullptr, (void **)&q->ccnt, MAX_SEG * sizeof(uint32_t)))) return rc;
+    if (!q->spart) {
+        if ((rc = dev_alloc(nullptr, (void **)&q->spart, 5 * STAT_SLOTS * sizeof(unsigned long long)))) return rc;
+        HIP_TRY(hipMemsetAsync(q->spart, 0, 5 * STAT_SLOTS * sizeof(unsigned long long), q->stream));
     }
-    if (g->dout_cap < kout) {
-        dev_free(g, g->dout, g->dout_cap * sizeof(tt_triangle));
-        g->dout = nullptr;
-        g->dout_cap = 0;
-        if ((rc = dev_alloc(g, (void **)&g->dout, kout * sizeof(tt_triangle)))) return rc;
-        g->dout_cap = kout;
+    const uint64_t cc = std::min<uint64_t>(g->m + 1, q->max_cand);
+    if (q->cand_cap < cc) {
+        dev_free(nullptr, q->cand, 0);
+        q->cand = nullptr;
+        q->cand_cap = 0;
+        if ((rc = dev_alloc(nullptr, (void **)&q->cand, cc * sizeof(cand)))) return rc;
+        q->cand_cap = cc;
+    }
+    if (q->buf_cap < cap) {
+        dev_free(nullptr, q->buf0, 0);
+        dev_free(nullptr, q->buf1, 0);
+        q->buf0 = q->buf1 = nullptr;
+        q->buf_cap = 0;
+        if ((rc = dev_alloc(nullptr, (void **)&q->buf0, cap * sizeof(trec))) ||
+            (rc = dev_alloc(nullptr, (void **)&q->buf1, cap * sizeof(trec))))
+            return rc;
+        q->buf_cap = cap;
+    }
+    if (q->dout_cap < kout) {
+        dev_free(nullptr, q->dout, 0);
+        q->dout = nullptr;
+        q->dout_cap = 0;
+        if ((rc = dev_alloc(nullptr, (void **)&q->dout, kout * sizeof(tt_triangle)))) return rc;
+        q->dout_cap = kout;
     }
     return TT_OK;
 }
@@ -745,12 +766,12 @@ struct Timer {
     }
 };
 
-// Sorts the first N records of g->buf0 and leaves the best min(N, k) at the front of *res.
-int select_topk(tt_graph *g, uint64_t N, uint32_t k, trec **res) {
-    hipStream_t s = g->stream;
+// Sorts the first N records of q->buf0 and leaves the best min(N, k) at the front of *res.
+int select_topk(QueryCtx *q, uint64_t N, uint32_t k, trec **res) {
+    hipStream_t s = q->stream;
     const uint32_t S0 = k < (uint32_t)STILE ? k : (uint32_t)STILE;
     uint64_t nruns = (N + STILE - 1) / STILE;
-    trec *in = g->buf0, *out = g->buf1;
+    trec *in = q->buf0, *out = q->buf1;
     k_tile_sort<<<(unsigned)nruns, 512, 0, s>>>(in, out, N, S0);
     std::swap(in, out);
     uint64_t C = STILE;
@@ -845,17 +866,18 @@ Stream pick_stream(const tt_graph *g, int mode, double p, u128 L) {
     return r;
 }
 
-int ensure_band_events(tt_graph *g, size_t pairs) {
-    while (g->band_ev.size() < 2 * pairs) {
+int ensure_band_events(QueryCtx *q, size_t pairs) {
+    while (q->band_ev.size() < 2 * pairs) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return fail(TT_E_DEVICE, "hipEventCreate failed");
-        g->band_ev.push_back(e);
+        q->band_ev.push_back(e);
     }
     return TT_OK;
 }
 
-// Enqueues one enumeration pass (no host synchronisation); `slot` picks its event pair.
-int launch_enum(tt_graph *g, const Band &B, int filter, bool gated, size_t slot) {
+// Enqueues one enumeration pass (no host synchronisation): the band's stream is filtered and
+// intersected in pieces of at most cand_cap entries.  `slot` picks its event pair.
+int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool gated, size_t slot) {
     const Stream S = pick_stream(g, B.mode, B.p, B.L);
     EnumArgs A;
     A.rstart = g->rstart;
@@ -866,50 +888,51 @@ int launch_enum(tt_graph *g, const Band &B, int filter, bool gated, size_t slot)
     A.wwgt = g->wwgt;
     A.wpos = g->wpos;
     A.maxw = g->maxw;
-    A.s_src = S.src;
-    A.s_col = S.col;
-    A.s_wgt = S.wgt;
-    A.s_pos = S.pos;
-    A.E = S.E;
-    A.skip = gated ? g->dcount + 7 : nullptr;
+    A.skip = gated ? q->dcount + 7 : nullptr;
     A.B = B;
     A.emark = g->emark;
-    A.vflag = g->vflag;
-    A.vflag2 = g->vflag2;
-    A.out = g->buf0;
-    A.count = g->dcount;
-    A.cap = g->buf_cap;
-    A.stats = g->spart;
-    A.C = g->cand;
-    A.ccnt = g->ccnt;
-    A.nseg = filter_grid(S.E);
-    A.seg = (S.E + A.nseg - 1) / A.nseg;
-    HIP_TRY(hipEventRecord(g->band_ev[2 * slot], g->stream));
-    if (S.E) {
-        const unsigned fgrid = A.nseg;
+    A.vflag = q->vflag;
+    A.vflag2 = q->vflag2;
+    A.out = q->buf0;
+    A.count = q->dcount;
+    A.cap = q->buf_cap;
+    A.stats = q->spart;
+    A.C = q->cand;
+    A.ccnt = q->ccnt;
+    HIP_TRY(hipEventRecord(q->band_ev[2 * slot], q->stream));
+    for (uint64_t off = 0; off < S.E; off += q->cand_cap) {
+        const uint64_t E = std::min<uint64_t>(S.E - off, q->cand_cap);
+        A.s_src = S.src + off;
+        A.s_col = S.col + off;
+        A.s_wgt = S.wgt + off;
+        A.s_pos = S.pos ? S.pos + off : nullptr;
+        A.pos_off = off;
+        A.E = E;
+        A.nseg = filter_grid(E);
+        A.seg = (E + A.nseg - 1) / A.nseg;
         const unsigned igrid = (unsigned)num_cus() * 8;
         if (filter == FILTER_EDGES) {
-            k_filter<FILTER_EDGES><<<fgrid, 256, 0, g->stream>>>(A);
-            k_intersect<FILTER_EDGES><<<igrid, 256, 0, g->stream>>>(A);
+            k_filter<FILTER_EDGES><<<A.nseg, 256, 0, q->stream>>>(A);
+            k_intersect<FILTER_EDGES><<<igrid, 256, 0, q->stream>>>(A);
         } else if (filter == FILTER_VERTICES) {
-            k_filter<FILTER_VERTICES><<<fgrid, 256, 0, g->stream>>>(A);
-            k_intersect<FILTER_VERTICES><<<igrid, 256, 0, g->stream>>>(A);
+            k_filter<FILTER_VERTICES><<<A.nseg, 256, 0, q->stream>>>(A);
+            k_intersect<FILTER_VERTICES><<<igrid, 256, 0, q->stream>>>(A);
         } else {
-            k_filter<FILTER_NONE><<<fgrid, 256, 0, g->stream>>>(A);
-            k_intersect<FILTER_NONE><<<igrid, 256, 0, g->stream>>>(A);
+            k_filter<FILTER_NONE><<<A.nseg, 256, 0, q->stream>>>(A);
+            k_intersect<FILTER_NONE><<<igrid, 256, 0, q->stream>>>(A);
         }
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipEventRecord(g->band_ev[2 * slot + 1], g->stream));
+    HIP_TRY(hipEventRecord(q->band_ev[2 * slot + 1], q->stream));
     return TT_OK;
 }
 
 // After the stream has been synchronised: add the durations of passes [0, n).
-void add_enum_time(tt_graph *g, tt_query_stats *st, size_t n) {
+void add_enum_time(QueryCtx *q, tt_query_stats *st, size_t n) {
     if (!st) return;
     for (size_t i = 0; i < n; i++) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, g->band_ev[2 * i], g->band_ev[2 * i + 1]) == hipSuccess) st->enum_kernel_ms += ms;
+        if (hipEventElapsedTime(&ms, q->band_ev[2 * i], q->band_ev[2 * i + 1]) == hipSuccess) st->enum_kernel_ms += ms;
     }
 }
 
@@ -927,103 +950,103 @@ Band make_band(int mode, double p, u128 L, uint32_t Li, uint32_t Lj, uint32_t Ll
 
 // The threshold descent: bands [L_i, L_{i-1}) until >= k triangles are held, restarts on
 // overflow, then selection.  Writes min(k, T) triangles to `out` (host).
-int run_topk(tt_graph *g, uint32_t k, double p, int filter, tt_triangle *out, uint32_t *n_out, tt_query_stats *st) {
+int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, tt_triangle *out, uint32_t *n_out,
+             tt_query_stats *st) {
     const int mode = mode_of(p);
-    const uint64_t cap = std::max<uint64_t>(1ull << 22, 16ull * k);
-    int rc = ensure_scratch(g, cap, k);
+    const uint64_t cap = std::max<uint64_t>(q->min_buf, 16ull * k);
+    int rc = ensure_scratch(g, q, cap, k);
     if (rc) return rc;
-    hipStream_t s = g->stream;
+    hipStream_t s = q->stream;
     // thresholds: key(t, t, t) for t = weight of the k-th, 4k-th, 16k-th ... heaviest edge
     std::vector<u128> Ls;
     for (uint64_t M = k; M < (1ull << 62); M *= 4) {
         const uint32_t t = weight_at_rank(g->whist, M);
         if (t <= 1) break;
-        const u128 L = key_of_uniform(mode, p, t);
+        const u128 L = key_of_uniform(mode, t);
         if (Ls.empty() || L < Ls.back()) Ls.push_back(L);
         if (M > g->m) break;
     }
     Ls.push_back(0); // exhaustive
-    if ((rc = ensure_band_events(g, Ls.size()))) return rc;
-    HIP_TRY(hipMemsetAsync(g->dcount, 0, 8 * sizeof(unsigned long long), s));
-    HIP_TRY(hipEventRecord(g->ev[0], s));
+    if ((rc = ensure_band_events(q, Ls.size()))) return rc;
+    HIP_TRY(hipMemsetAsync(q->dcount, 0, 8 * sizeof(unsigned long long), s));
+    HIP_TRY(hipEventRecord(q->ev[0], s));
     // all bands are enqueued at once; a band finds the buffer already holding >= k triangles
     // (the answer is complete) or overflowed, and returns at once
     for (size_t i = 0; i < Ls.size(); i++) {
         if (i > 0) {
-            k_band_gate<<<1, 64, 0, s>>>(g->dcount, k, g->dcount + 7);
+            k_band_gate<<<1, 64, 0, s>>>(q->dcount, k, q->dcount + 7);
             HIP_TRY(hipGetLastError());
         }
-        rc = launch_enum(g, make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, i > 0, i > 0 ? Ls[i - 1] : 0), filter, true, i);
+        rc = launch_enum(g, q, make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, i > 0, i > 0 ? Ls[i - 1] : 0), filter, true, i);
         if (rc) return rc;
     }
-    HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    add_enum_time(g, st, Ls.size());
-    uint64_t cnt = g->hcount[0];
-    bool overflow = cnt > g->buf_cap;
+    add_enum_time(q, st, Ls.size());
+    uint64_t cnt = q->hcount[0];
+    bool overflow = cnt > q->buf_cap;
     double sel_ms = 0.0;
     while (overflow) {
         // the k-th best of the records kept is a lower bound on the k-th best overall
         trec *res = nullptr;
-        HIP_TRY(hipEventRecord(g->ev[2], s));
-        if ((rc = select_topk(g, g->buf_cap, k, &res))) return rc;
+        HIP_TRY(hipEventRecord(q->ev[2], s));
+        if ((rc = select_topk(q, q->buf_cap, k, &res))) return rc;
         trec kth;
         HIP_TRY(hipMemcpyAsync(&kth, res + (k - 1), sizeof(trec), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(g->ev[3], s));
-        HIP_TRY(hipMemsetAsync(g->dcount, 0, sizeof(unsigned long long), s));
+        HIP_TRY(hipEventRecord(q->ev[3], s));
+        HIP_TRY(hipMemsetAsync(q->dcount, 0, sizeof(unsigned long long), s));
         HIP_TRY(hipStreamSynchronize(s));
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, g->ev[2], g->ev[3]);
+        (void)hipEventElapsedTime(&ms, q->ev[2], q->ev[3]);
         sel_ms += ms;
         const u128 L = ((u128)kth.khi << 64) | kth.klo;
-        rc = launch_enum(g, make_band(mode, p, L, kth.i, kth.j, kth.l, false, 0), filter, false, 0);
+        rc = launch_enum(g, q, make_band(mode, p, L, kth.i, kth.j, kth.l, false, 0), filter, false, 0);
         if (rc) return rc;
         if (st) st->restarts++;
-        HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        add_enum_time(g, st, 1);
-        cnt = g->hcount[0];
-        overflow = cnt > g->buf_cap;
+        add_enum_time(q, st, 1);
+        cnt = q->hcount[0];
+        overflow = cnt > q->buf_cap;
     }
-    HIP_TRY(hipEventRecord(g->ev[1], s));
+    HIP_TRY(hipEventRecord(q->ev[1], s));
     const uint64_t N = cnt;
     const uint32_t K = (uint32_t)std::min<uint64_t>(N, k);
     if (K > 0) {
         trec *res = nullptr;
-        if ((rc = select_topk(g, N, k, &res))) return rc;
-        k_finalize<<<(K + 255) / 256, 256, 0, s>>>(res, K, mode, g->dout);
+        if ((rc = select_topk(q, N, k, &res))) return rc;
+        k_finalize<<<(K + 255) / 256, 256, 0, s>>>(res, K, mode, q->dout);
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipEventRecord(g->ev[2], s));
-    k_reduce_stats<<<5, 256, 0, s>>>(g->spart, g->dcount + 1);
-    if (K > 0) HIP_TRY(hipMemcpyAsync(out, g->dout, (size_t)K * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(g->hcount, g->dcount, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(q->ev[2], s));
+    k_reduce_stats<<<5, 256, 0, s>>>(q->spart, q->dcount + 1);
+    if (K > 0) HIP_TRY(hipMemcpyAsync(out, q->dout, (size_t)K * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *n_out = K;
     if (st) {
         float e_ms = 0.f, s_ms = 0.f;
-        (void)hipEventElapsedTime(&e_ms, g->ev[0], g->ev[1]);
-        (void)hipEventElapsedTime(&s_ms, g->ev[1], g->ev[2]);
+        (void)hipEventElapsedTime(&e_ms, q->ev[0], q->ev[1]);
+        (void)hipEventElapsedTime(&s_ms, q->ev[1], q->ev[2]);
         st->enum_ms += e_ms;
         st->select_ms += s_ms + sel_ms;
-        st->candidate_edges += g->hcount[1];
-        st->intersected_entries += g->hcount[2];
-        st->triangles_emitted += g->hcount[3];
-        st->edges_streamed += g->hcount[4];
-        st->passes += (uint32_t)g->hcount[5];
+        st->candidate_edges += q->hcount[1];
+        st->intersected_entries += q->hcount[2];
+        st->triangles_emitted += q->hcount[3];
+        st->edges_streamed += q->hcount[4];
+        st->passes += (uint32_t)q->hcount[5];
     }
     return TT_OK;
 }
 
-int ensure_flags(tt_graph *g, bool edges) {
+int ensure_flags(const tt_graph *g, QueryCtx *q) {
     int rc;
-    if (!g->vflag && (rc = dev_alloc(g, (void **)&g->vflag, (uint64_t)g->n + 1))) return rc;
-    if (!g->vflag2 && (rc = dev_alloc(g, (void **)&g->vflag2, (uint64_t)g->n + 1))) return rc;
-    if (edges && !g->emark && (rc = dev_alloc(g, (void **)&g->emark, g->m + 1))) return rc;
+    if (!q->vflag && (rc = dev_alloc(nullptr, (void **)&q->vflag, (uint64_t)g->n + 1))) return rc;
+    if (!q->vflag2 && (rc = dev_alloc(nullptr, (void **)&q->vflag2, (uint64_t)g->n + 1))) return rc;
     return TT_OK;
 }
 
-int check_query(tt_graph *g, double p, tt_triangle *out, uint32_t k, uint32_t *n_out) {
+int check_query(const tt_graph *g, double p, const tt_triangle *out, uint32_t k, uint32_t *n_out) {
     if (n_out) *n_out = 0;
     if (!g) return fail(TT_E_ARG, "graph is NULL");
     if (!n_out) return fail(TT_E_ARG, "n_out is NULL");
@@ -1032,11 +1055,44 @@ int check_query(tt_graph *g, double p, tt_triangle *out, uint32_t k, uint32_t *n
     return TT_OK;
 }
 
+int check_subset(const tt_graph *g, const uint32_t *subset, uint32_t subset_n) {
+    for (uint32_t t = 0; subset && t < subset_n; t++)
+        if (subset[t] >= g->n) return fail(TT_E_VERTEX_RANGE, "subset vertex >= n");
+    return TT_OK;
+}
+
+// Marks the subset (vflag) and the tails with an out-neighbour in it (vflag2).
+int mark_subset(const tt_graph *g, QueryCtx *q, const uint32_t *subset, uint32_t subset_n) {
+    int rc;
+    if ((rc = ensure_flags(g, q))) return rc;
+    uint32_t *dids = nullptr;
+    if ((rc = dev_alloc(nullptr, (void **)&dids, (uint64_t)subset_n * 4))) return rc;
+    HIP_TRY(hipMemsetAsync(q->vflag, 0, (uint64_t)g->n + 1, q->stream));
+    HIP_TRY(hipMemsetAsync(q->vflag2, 0, (uint64_t)g->n + 1, q->stream));
+    HIP_TRY(hipMemcpyAsync(dids, subset, (uint64_t)subset_n * 4, hipMemcpyHostToDevice, q->stream));
+    k_mark_vertices<<<(subset_n + 255) / 256, 256, 0, q->stream>>>(dids, subset_n, g->n, q->vflag);
+    k_mark_out_nbrs<<<enum_grid(g->m), 256, 0, q->stream>>>(g->osrc, g->col, g->m, q->vflag, q->vflag2);
+    HIP_TRY(hipStreamSynchronize(q->stream));
+    dev_free(nullptr, dids, 0);
+    return TT_OK;
+}
+
+// One exact query on context q (the caller serialises use of q).
+int query_on(const tt_graph *g, QueryCtx *q, uint32_t k, double p, const uint32_t *subset, uint32_t subset_n,
+             tt_triangle *out, uint32_t *n_out, tt_query_stats *stats) {
+    int filter = FILTER_NONE, rc;
+    if (subset && subset_n) {
+        if ((rc = mark_subset(g, q, subset, subset_n))) return rc;
+        filter = FILTER_VERTICES;
+    }
+    return run_topk(g, q, k, p, filter, out, n_out, stats);
+}
+
 // Prefix sums of w^q (input order) and their guide table, for the two most recent q.
-int sample_table(tt_graph *g, double q, int kind, tt_graph::SampleTable **out) {
+int sample_table(tt_graph *g, double qexp, int kind, tt_graph::SampleTable **out) {
     g->use_clock++;
     for (auto &t : g->tables)
-        if (t.q == q && t.prefix) { t.last_use = g->use_clock; *out = &t; return TT_OK; }
+        if (t.q == qexp && t.prefix) { t.last_use = g->use_clock; *out = &t; return TT_OK; }
     tt_graph::SampleTable *t = &g->tables[0];
     if (g->tables[1].last_use < t->last_use) t = &g->tables[1];
     int rc;
@@ -1048,14 +1104,14 @@ int sample_table(tt_graph *g, double q, int kind, tt_graph::SampleTable **out) {
     if (!t->prefix && (rc = dev_alloc(g, &t->prefix, g->m * 16))) return rc;
     if (!t->guide && (rc = dev_alloc(g, (void **)&t->guide, ((1ull << g->guide_bits) + 1) * 4))) return rc;
     t->q = -1.0;
-    if ((rc = inclusive_weight_prefix(g, q, t->prefix))) return rc;
+    if ((rc = inclusive_weight_prefix(g, qexp, t->prefix))) return rc;
     const uint64_t nb = (1ull << g->guide_bits) + 1;
     const unsigned grid = (unsigned)std::min<uint64_t>((nb + 255) / 256, (uint64_t)num_cus() * 16);
     if (kind == 0) k_es_guide<0><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
     else if (kind == 1) k_es_guide<1><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
     else k_es_guide<2><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
     HIP_TRY(hipGetLastError());
-    t->q = q;
+    t->q = qexp;
     t->last_use = g->use_clock;
     *out = t;
     return TT_OK;
@@ -1069,26 +1125,11 @@ extern "C" int topk_triangles_ex(tt_graph *g, uint32_t k, double p, const uint32
     int rc = check_query(g, p, out, k, n_out);
     if (rc) return rc;
     if (stats) std::memset(stats, 0, sizeof(*stats));
+    if ((rc = check_subset(g, subset, subset_n))) return rc;
     if (k == 0 || g->m == 0) { set_error(""); return TT_OK; }
     std::lock_guard<std::mutex> lock(g->mu);
     (void)hipSetDevice(g->device);
-    int filter = FILTER_NONE;
-    if (subset && subset_n) {
-        for (uint32_t t = 0; t < subset_n; t++)
-            if (subset[t] >= g->n) return fail(TT_E_VERTEX_RANGE, "subset vertex >= n");
-        if ((rc = ensure_flags(g, false))) return rc;
-        uint32_t *dids = nullptr;
-        if ((rc = dev_alloc(nullptr, (void **)&dids, (uint64_t)subset_n * 4))) return rc;
-        HIP_TRY(hipMemsetAsync(g->vflag, 0, (uint64_t)g->n + 1, g->stream));
-        HIP_TRY(hipMemsetAsync(g->vflag2, 0, (uint64_t)g->n + 1, g->stream));
-        HIP_TRY(hipMemcpyAsync(dids, subset, (uint64_t)subset_n * 4, hipMemcpyHostToDevice, g->stream));
-        k_mark_vertices<<<(subset_n + 255) / 256, 256, 0, g->stream>>>(dids, subset_n, g->n, g->vflag);
-        k_mark_out_nbrs<<<enum_grid(g->m), 256, 0, g->stream>>>(g->osrc, g->col, g->m, g->vflag, g->vflag2);
-        HIP_TRY(hipStreamSynchronize(g->stream));
-        dev_free(nullptr, dids, (uint64_t)subset_n * 4);
-        filter = FILTER_VERTICES;
-    }
-    rc = run_topk(g, k, p, filter, out, n_out, stats);
+    rc = query_on(g, &g->q, k, p, subset, subset_n, out, n_out, stats);
     if (stats) stats->total_ms = timer.ms();
     if (!rc) set_error("");
     return rc;
@@ -1107,33 +1148,35 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
     if (k == 0 || budget == 0 || g->m == 0) { set_error(""); return TT_OK; }
     std::lock_guard<std::mutex> lock(g->mu);
     (void)hipSetDevice(g->device);
-    if ((rc = ensure_flags(g, true)) || (rc = ensure_scratch(g, 1, 1))) return rc;
-    const double q = (std::isfinite(p) && p > 0.0) ? p : 1.0;
-    const int kind = q == 1.0 ? 0 : (q == 2.0 || q == 3.0) ? 1 : 2;
-    hipStream_t s = g->stream;
-    HIP_TRY(hipEventRecord(g->ev[6], s));
+    QueryCtx *q = &g->q;
+    if ((rc = ensure_flags(g, q)) || (rc = ensure_scratch(g, q, 1, 1))) return rc;
+    if (!g->emark && (rc = dev_alloc(g, (void **)&g->emark, g->m + 1))) return rc;
+    const double qexp = (std::isfinite(p) && p > 0.0) ? p : 1.0;
+    const int kind = qexp == 1.0 ? 0 : (qexp == 2.0 || qexp == 3.0) ? 1 : 2;
+    hipStream_t s = q->stream;
+    HIP_TRY(hipEventRecord(q->ev[6], s));
     tt_graph::SampleTable *tab = nullptr;
-    if ((rc = sample_table(g, q, kind, &tab))) return rc;
+    if ((rc = sample_table(g, qexp, kind, &tab))) return rc;
     HIP_TRY(hipMemsetAsync(g->emark, 0, g->m + 1, s));
-    HIP_TRY(hipMemsetAsync(g->vflag, 0, (uint64_t)g->n + 1, s));
+    HIP_TRY(hipMemsetAsync(q->vflag, 0, (uint64_t)g->n + 1, s));
     const unsigned grid = (unsigned)std::min<uint64_t>((budget + 255) / 256, (uint64_t)num_cus() * 16);
     const uint32_t bits = g->guide_bits;
     if (kind == 0) k_es_draw<0><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
     else if (kind == 1) k_es_draw<1><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
     else k_es_draw<2><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
-    k_mark_tails<<<enum_grid(g->m / 16 + 1), 256, 0, s>>>(g->emark, g->m, g->osrc, g->vflag);
+    k_mark_tails<<<enum_grid(g->m / 16 + 1), 256, 0, s>>>(g->emark, g->m, g->osrc, q->vflag);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipEventRecord(g->ev[7], s));
-    rc = run_topk(g, k, p, FILTER_EDGES, out, n_out, stats);
+    HIP_TRY(hipEventRecord(q->ev[7], s));
+    rc = run_topk(g, q, k, p, FILTER_EDGES, out, n_out, stats);
     if (!rc && stats) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, g->ev[6], g->ev[7]) == hipSuccess) stats->sample_ms = ms;
+        if (hipEventElapsedTime(&ms, q->ev[6], q->ev[7]) == hipSuccess) stats->sample_ms = ms;
         // marks are counted into the spread slots of counter 0 (cleared after every query)
-        k_count_marks<<<std::min<unsigned>(enum_grid(g->m / 16 + 1), 1024u), 256, 0, s>>>(g->emark, g->m, g->spart);
-        k_reduce_stats<<<1, 256, 0, s>>>(g->spart, g->dcount + 8);
-        HIP_TRY(hipMemcpyAsync(g->hcount + 8, g->dcount + 8, 8, hipMemcpyDeviceToHost, s));
+        k_count_marks<<<std::min<unsigned>(enum_grid(g->m / 16 + 1), 1024u), 256, 0, s>>>(g->emark, g->m, q->spart);
+        k_reduce_stats<<<1, 256, 0, s>>>(q->spart, q->dcount + 8);
+        HIP_TRY(hipMemcpyAsync(q->hcount + 8, q->dcount + 8, 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        stats->distinct_sampled = g->hcount[8];
+        stats->distinct_sampled = q->hcount[8];
         stats->total_ms = timer.ms();
     }
     if (!rc) set_error("");
@@ -1143,4 +1186,199 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
 extern "C" int sample_heavy_triangles(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed,
                                       tt_triangle *out, uint32_t *n_out) {
     return sample_heavy_triangles_ex(g, k, p, budget, seed, out, n_out, nullptr);
+}
+
+// ----------------------------------------------------------------------------- serving
+// A request loop over one resident graph.  Each slot is a worker thread with its own query
+// context and HIP stream, so admitted requests overlap on the device.  Requests wait in FIFO
+// order and are admitted as soon as a slot is free and their scratch bytes fit the budget
+// (continuous batching: a request that arrives while others run starts when one finishes).
+struct tt_server {
+    struct Req {
+        uint64_t ticket;
+        uint32_t k;
+        double p;
+        std::vector<uint32_t> subset;
+        uint64_t need;
+        std::chrono::steady_clock::time_point t_submit;
+    };
+    struct Res {
+        bool done = false;
+        int rc = TT_OK;
+        std::string err;
+        std::vector<tt_triangle> tri;
+        uint32_t n_out = 0;
+        tt_query_stats st{};
+    };
+    tt_graph *g = nullptr;
+    uint64_t budget = 0, in_use = 0, peak = 0, admitted = 0, completed = 0;
+    uint32_t max_queue = 0, max_running = 0, running = 0;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::deque<Req> queue;
+    std::unordered_map<uint64_t, Res> results;
+    std::vector<QueryCtx> ctx;
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+};
+
+namespace {
+void serve_worker(tt_server *S, size_t slot) {
+    QueryCtx *q = &S->ctx[slot];
+    (void)hipSetDevice(S->g->device);
+    for (;;) {
+        tt_server::Req r;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] {
+                return (S->stop && S->queue.empty()) ||
+                       (!S->queue.empty() && S->in_use + S->queue.front().need <= S->budget);
+            });
+            if (S->queue.empty()) return;
+            r = std::move(S->queue.front());
+            S->queue.pop_front();
+            S->in_use += r.need;
+            S->peak = std::max(S->peak, S->in_use);
+            S->admitted++;
+            S->running++;
+            S->max_running = std::max(S->max_running, S->running);
+        }
+        tt_server::Res res;
+        res.tri.resize(std::max<uint32_t>(r.k, 1));
+        res.rc = query_on(S->g, q, r.k, r.p, r.subset.empty() ? nullptr : r.subset.data(), (uint32_t)r.subset.size(),
+                          res.tri.data(), &res.n_out, &res.st);
+        if (res.rc) res.err = tt_last_error();
+        res.st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - r.t_submit).count();
+        ctx_release(q); // the scratch goes back to the device memory cache
+        res.done = true;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->in_use -= r.need;
+            S->running--;
+            S->completed++;
+            S->results[r.ticket] = std::move(res);
+        }
+        S->cv_done.notify_all();
+        S->cv_work.notify_all();
+    }
+}
+} // namespace
+
+extern "C" int server_create(tt_graph *g, uint32_t slots, uint64_t scratch_budget, tt_server **out) {
+    if (!out) return fail(TT_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!g || slots == 0 || slots > 64) return fail(TT_E_ARG, "graph is NULL or slots not in [1, 64]");
+    tt_server *S = new (std::nothrow) tt_server();
+    if (!S) return fail(TT_E_NOMEM, "host allocation failed");
+    S->g = g;
+    S->budget = scratch_budget;
+    S->ctx.resize(slots);
+    for (auto &q : S->ctx) {
+        q.min_buf = 1ull << 20;
+        q.max_cand = 1ull << 24;
+        if (hipStreamCreateWithFlags(&q.stream, hipStreamNonBlocking) != hipSuccess) {
+            for (auto &c : S->ctx)
+                if (c.stream) (void)hipStreamDestroy(c.stream);
+            delete S;
+            return fail(TT_E_DEVICE, "hipStreamCreate failed");
+        }
+        q.owns_stream = true;
+    }
+    for (size_t i = 0; i < slots; i++) S->workers.emplace_back(serve_worker, S, i);
+    *out = S;
+    set_error("");
+    return TT_OK;
+}
+
+extern "C" uint64_t server_request_bytes(tt_server *S, uint32_t k, uint32_t subset_n) {
+    if (!S) return 0;
+    return query_bytes(S->g, &S->ctx[0], k, subset_n > 0);
+}
+
+extern "C" int server_submit(tt_server *S, uint32_t k, double p, const uint32_t *subset, uint32_t subset_n,
+                             uint64_t *ticket) {
+    if (!S || !ticket) return fail(TT_E_ARG, "server or ticket is NULL");
+    *ticket = 0;
+    if (std::isnan(p)) return fail(TT_E_ARG, "p is NaN");
+    int rc = check_subset(S->g, subset, subset_n);
+    if (rc) return rc;
+    tt_server::Req r;
+    r.k = k;
+    r.p = p;
+    if (subset && subset_n) r.subset.assign(subset, subset + subset_n);
+    r.need = query_bytes(S->g, &S->ctx[0], k, !r.subset.empty());
+    if (r.need > S->budget) return fail(TT_E_BUDGET, "the request needs more scratch than the server's budget");
+    r.t_submit = std::chrono::steady_clock::now();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) return fail(TT_E_ARG, "server is shutting down");
+        r.ticket = S->next_ticket++;
+        *ticket = r.ticket;
+        S->queue.push_back(std::move(r));
+        S->max_queue = std::max<uint32_t>(S->max_queue, (uint32_t)S->queue.size());
+    }
+    S->cv_work.notify_one();
+    set_error("");
+    return TT_OK;
+}
+
+extern "C" int server_poll(tt_server *S, uint64_t ticket, int *done) {
+    if (!S || !done) return fail(TT_E_ARG, "server or done is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->results.find(ticket);
+    *done = it != S->results.end() && it->second.done;
+    if (!*done && ticket >= S->next_ticket) return fail(TT_E_ARG, "unknown ticket");
+    return TT_OK;
+}
+
+extern "C" int server_wait(tt_server *S, uint64_t ticket, tt_triangle *out, uint32_t *n_out, tt_query_stats *stats) {
+    if (n_out) *n_out = 0;
+    if (!S || !n_out) return fail(TT_E_ARG, "server or n_out is NULL");
+    tt_server::Res res;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (ticket == 0 || ticket >= S->next_ticket) return fail(TT_E_ARG, "unknown ticket");
+        S->cv_done.wait(lk, [&] {
+            auto it = S->results.find(ticket);
+            return it != S->results.end() && it->second.done;
+        });
+        auto it = S->results.find(ticket);
+        res = std::move(it->second);
+        S->results.erase(it);
+    }
+    if (res.rc) return fail(res.rc, res.err);
+    if (res.n_out && !out) return fail(TT_E_ARG, "out is NULL");
+    std::memcpy(out, res.tri.data(), (size_t)res.n_out * sizeof(tt_triangle));
+    *n_out = res.n_out;
+    if (stats) *stats = res.st;
+    set_error("");
+    return TT_OK;
+}
+
+extern "C" int server_info(tt_server *S, uint64_t *admitted, uint64_t *completed, uint64_t *peak_bytes,
+                           uint32_t *max_queue, uint32_t *max_running) {
+    if (!S) return fail(TT_E_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (admitted) *admitted = S->admitted;
+    if (completed) *completed = S->completed;
+    if (peak_bytes) *peak_bytes = S->peak;
+    if (max_queue) *max_queue = S->max_queue;
+    if (max_running) *max_running = S->max_running;
+    return TT_OK;
+}
+
+extern "C" void server_destroy(tt_server *S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    for (auto &t : S->workers) t.join();
+    for (auto &q : S->ctx) {
+        ctx_release(&q);
+        if (q.owns_stream && q.stream) (void)hipStreamDestroy(q.stream);
+    }
+    delete S;
 }

@@ -67,3 +67,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(tt, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(tt.LibraryMissing):
         tt.library()
+
+
+def test_server_argument_errors(lib):
+    h = ctypes.c_void_p()
+    assert lib.server_create(None, 4, 1 << 30, ctypes.byref(h)) == tt.TT_E_ARG
+    assert lib.server_create(None, 4, 1 << 30, None) == tt.TT_E_ARG
+    t = ctypes.c_uint64(5)
+    assert lib.server_submit(None, 10, 1.0, None, 0, ctypes.byref(t)) == tt.TT_E_ARG
+    n_out = ctypes.c_uint32(3)
+    assert lib.server_wait(None, 1, None, ctypes.byref(n_out), None) == tt.TT_E_ARG and n_out.value == 0
+    assert lib.server_info(None, None, None, None, None, None) == tt.TT_E_ARG
+    assert lib.server_request_bytes(None, 10, 0) == 0
+    lib.server_destroy(None)  # NULL-safe
