@@ -68,6 +68,7 @@ struct QueryCtx {
     uint64_t sub_cap = 1ull << 22;         // capacity of the compact stream and of the list
     uint64_t sub_len = 0;                  // entries in the compact stream
     bool sub_active = false;               // the passes stream the compact list
+    std::vector<uint64_t> sub_hist;        // host: its entries per weight_bin(w)
     hipEvent_t ev[8] = {};
     std::vector<hipEvent_t> band_ev;       // start/stop pairs of the passes of a query
 };
@@ -105,9 +106,9 @@ struct tt_graph {
     uint32_t *deg = nullptr;    // [n] undirected degree
     uint32_t *in_w = nullptr;   // [m] weights in input order (sampling prefix sums)
     // transpose of the oriented CSR, built on the first subset query: for every head v, the
-    // tails u of its in-entries u->v and the positions of those entries
+    // tails u of its in-entries u->v
     uint64_t *irstart = nullptr; // [n+2]
-    uint32_t *itail = nullptr, *ipos = nullptr;
+    uint32_t *itail = nullptr;
     std::mutex init_mu;
     uint32_t wmax = 0;          // largest weight in the graph
     uint32_t max_outdeg = 0;

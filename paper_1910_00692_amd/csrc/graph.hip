@@ -626,7 +626,7 @@ void release(tt_graph *g) {
     if (!g) return;
     void *ptrs[] = {g->rstart, g->rlen,   g->col,    g->wgt,  g->osrc,    g->eid,   g->opos,
                     g->wcol,   g->wwgt,   g->wpos,   g->maxw, g->hb,      g->deg,   g->emark,
-                    g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->in_w,  g->irstart, g->itail, g->ipos};
+                    g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->in_w,  g->irstart, g->itail};
     for (void *p : ptrs) dev_free(g, p, 0);
     for (auto &t : g->tables) {
         dev_free(g, t.prefix, 0);
@@ -689,8 +689,7 @@ __global__ __launch_bounds__(256) void k_indeg(const uint32_t *col, uint64_t m, 
 }
 
 __global__ __launch_bounds__(256) void k_in_scatter(const uint32_t *col, const uint32_t *osrc, uint64_t m,
-                                                    const uint64_t *irstart, uint32_t *cursor, uint32_t *itail,
-                                                    uint32_t *ipos) {
+                                                    const uint64_t *irstart, uint32_t *cursor, uint32_t *itail) {
     const int lane = threadIdx.x & 63;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
@@ -701,11 +700,7 @@ __global__ __launch_bounds__(256) void k_in_scatter(const uint32_t *col, const u
         uint32_t slot = 0;
         if (valid && r.first == lane) slot = atomicAdd(&cursor[v], (uint32_t)(r.end - lane));
         slot = __shfl(slot, r.first, 64) + (uint32_t)(lane - r.first);
-        if (valid) {
-            const uint64_t d = irstart[v] + slot;
-            itail[d] = osrc[e];
-            ipos[d] = (uint32_t)e;
-        }
+        if (valid) itail[irstart[v] + slot] = osrc[e];
     }
 }
 
@@ -860,25 +855,22 @@ int ensure_in_csr(tt_graph *g, hipStream_t s) {
     S.stream = s;
     uint32_t *indeg = nullptr, *cursor = nullptr;
     uint64_t *irstart = nullptr;
-    uint32_t *itail = nullptr, *ipos = nullptr;
+    uint32_t *itail = nullptr;
     if ((rc = S.get((void **)&indeg, nn * 4)) || (rc = S.get((void **)&cursor, nn * 4)) ||
-        (rc = dev_alloc(g, (void **)&irstart, (nn + 1) * 8)) || (rc = dev_alloc(g, (void **)&itail, (m + 1) * 4)) ||
-        (rc = dev_alloc(g, (void **)&ipos, (m + 1) * 4))) {
+        (rc = dev_alloc(g, (void **)&irstart, (nn + 1) * 8)) || (rc = dev_alloc(g, (void **)&itail, (m + 1) * 4))) {
         dev_free(g, irstart, 0);
         dev_free(g, itail, 0);
-        dev_free(g, ipos, 0);
         return rc;
     }
     HIP_TRY(hipMemsetAsync(indeg, 0, nn * 4, s));
     HIP_TRY(hipMemsetAsync(cursor, 0, nn * 4, s));
     if (m) k_indeg<<<grid_for(m), 256, 0, s>>>(g->col, m, indeg);
     if ((rc = exclusive_scan_u32_to_u64(indeg, irstart, nn, s, nullptr))) return rc;
-    if (m) k_in_scatter<<<grid_for(m), 256, 0, s>>>(g->col, g->osrc, m, irstart, cursor, itail, ipos);
+    if (m) k_in_scatter<<<grid_for(m), 256, 0, s>>>(g->col, g->osrc, m, irstart, cursor, itail);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
     g->irstart = irstart;
     g->itail = itail;
-    g->ipos = ipos;
     return TT_OK;
 }
 

@@ -644,16 +644,128 @@ __global__ __launch_bounds__(256) void k_count_marks(const uint8_t *mark, uint64
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(&out[blockIdx.x & 1023], c);
 }
 
-__global__ __launch_bounds__(256) void k_mark_vertices(const uint32_t *ids, uint32_t cnt, uint32_t n, uint8_t *vflag) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < cnt && ids[t] < n) vflag[ids[t]] = 1;
+// Sets vertex x in a byte-flag array through its 32-bit word; true for the one thread that
+// set it first (the arrays are padded to a multiple of four bytes).
+__device__ __forceinline__ bool flag_first(uint8_t *flags, uint32_t x) {
+    const uint32_t bit = 1u << (8 * (x & 3u));
+    const uint32_t old = atomicOr(reinterpret_cast<uint32_t *>(flags + (x & ~3u)), bit);
+    return !(old & bit);
 }
 
-// vflag2[u] = 1 if some out-neighbour of u is in the subset
-__global__ __launch_bounds__(256) void k_mark_out_nbrs(const uint32_t *osrc, const uint32_t *col, uint64_t m,
-                                                       const uint8_t *vflag, uint8_t *vflag2) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
-        if (vflag[col[e]]) vflag2[osrc[e]] = 1;
+// Subset queries.  A triangle u->v, u->c, v->c (base u->v) touches the subset S iff u in S, or
+// v in S, or c in S; in the last case u and v both have an out-neighbour in S.  So its base is
+// (A) an out-entry of a vertex of S, or (B/C) an out-entry u->v of an in-neighbour u of S
+// (u outside S) whose head v is in S or has an out-neighbour in S.  The three kernels below mark
+// S (vflag), mark every vertex with an out-neighbour in S (vflag2) through the in-rows of S,
+// list the in-neighbours outside S, and copy the base entries of those rows into a compact
+// stream.  Sources are disjoint, so no entry appears twice.
+//
+// Marks S and drops repeated ids: own[t] = 1 for the first copy of ids[t]; lens[t] = in-degree
+// of an owned id (else 0), lens[cnt] = 0; cnt8[1] += out-degrees of the owned ids.
+__global__ __launch_bounds__(256) void k_sub_mark(const uint32_t *ids, uint32_t cnt, const uint64_t *irstart,
+                                                  const uint32_t *rlen, uint8_t *vflag, uint8_t *own, uint32_t *lens,
+                                                  unsigned long long *cnt8) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long out_sum = 0;
+    if (t < cnt) {
+        const uint32_t x = ids[t];
+        const bool first = flag_first(vflag, x);
+        own[t] = first ? 1 : 0;
+        lens[t] = first ? (uint32_t)(irstart[x + 1] - irstart[x]) : 0u;
+        if (first) out_sum = rlen[x];
+    } else if (t == cnt) {
+        lens[t] = 0;
+    }
+    out_sum = wave_sum(out_sum);
+    if ((threadIdx.x & 63) == 0 && out_sum) atomicAdd(&cnt8[1], out_sum);
+}
+
+// One thread per in-entry u->s of the (owned) subset vertices, flattened through the exclusive
+// prefix pre[] of lens[]: sets vflag2[u]; the first setter with u outside S appends u to vlist
+// (cnt8[0]) and adds its out-degree to cnt8[1].
+__global__ __launch_bounds__(256) void k_sub_in(const uint32_t *ids, uint32_t cnt, const uint64_t *pre,
+                                                const uint64_t *irstart, const uint32_t *itail, const uint32_t *rlen,
+                                                const uint8_t *vflag, uint8_t *vflag2, uint32_t *vlist, uint64_t vcap,
+                                                unsigned long long *cnt8) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t total = pre[cnt];
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t base = wave * 64; base < total; base += nwaves * 64) {
+        const uint64_t idx = base + lane;
+        bool app = false;
+        uint32_t u = 0;
+        if (idx < total) {
+            uint32_t lo = 0, hi = cnt; // last t with pre[t] <= idx
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (pre[mid] <= idx) lo = mid; else hi = mid;
+            }
+            u = itail[irstart[ids[lo]] + (idx - pre[lo])];
+            app = flag_first(vflag2, u) && !vflag[u];
+        }
+        const uint64_t bal = __ballot(app);
+        if (bal) {
+            unsigned long long b0 = 0;
+            if (lane == 0) b0 = atomicAdd(&cnt8[0], (unsigned long long)__popcll(bal));
+            b0 = __shfl(b0, 0, 64);
+            const uint64_t slot = b0 + __popcll(bal & ((1ull << lane) - 1ull));
+            if (app && slot < vcap) vlist[slot] = u;
+            const unsigned long long d = wave_sum((unsigned long long)(app ? rlen[u] : 0u));
+            if (lane == 0 && d) atomicAdd(&cnt8[1], d);
+        }
+    }
+}
+
+// One wave per row: rows 0..cnt-1 are the subset ids (owned copies only, every entry kept),
+// rows cnt..cnt+nv-1 the listed in-neighbours (entries whose head is in S or has an
+// out-neighbour in S).  Kept entries go to the compact stream (cnt8[2]) with their weight
+// histogram (hist, by weight_bin).
+__global__ __launch_bounds__(256) void k_sub_rows(const uint32_t *ids, const uint8_t *own, uint32_t cnt,
+                                                  const uint32_t *vlist, uint32_t nv, const uint64_t *rstart,
+                                                  const uint32_t *rlen, const uint32_t *col, const uint32_t *wgt,
+                                                  const uint8_t *vflag, const uint8_t *vflag2, uint32_t *o_src,
+                                                  uint32_t *o_col, uint32_t *o_wgt, uint32_t *o_pos, uint64_t cap,
+                                                  unsigned long long *cnt8, unsigned long long *hist) {
+    __shared__ uint32_t h[WBINS];
+    for (int t = threadIdx.x; t < WBINS; t += blockDim.x) h[t] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const uint64_t rows = (uint64_t)cnt + nv;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < rows; r += nwaves) {
+        const bool in_s = r < cnt;
+        if (in_s && !own[r]) continue;
+        const uint32_t u = in_s ? ids[r] : vlist[r - cnt];
+        const uint64_t b = rstart[u];
+        const uint32_t len = rlen[u];
+        for (uint32_t t0 = 0; t0 < len; t0 += 64) {
+            const uint32_t t = t0 + lane;
+            bool keep = false;
+            uint32_t v = 0;
+            if (t < len) {
+                v = col[b + t];
+                keep = in_s || vflag[v] || vflag2[v];
+            }
+            const uint64_t bal = __ballot(keep);
+            if (!bal) continue;
+            unsigned long long b0 = 0;
+            if (lane == 0) b0 = atomicAdd(&cnt8[2], (unsigned long long)__popcll(bal));
+            b0 = __shfl(b0, 0, 64);
+            const uint64_t slot = b0 + __popcll(bal & ((1ull << lane) - 1ull));
+            if (keep && slot < cap) {
+                const uint32_t w = wgt[b + t];
+                o_src[slot] = u;
+                o_col[slot] = v;
+                o_wgt[slot] = w;
+                o_pos[slot] = (uint32_t)(b + t);
+                atomicAdd(&h[weight_bin(w)], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < WBINS; t += blockDim.x)
+        if (h[t]) atomicAdd(&hist[t], (unsigned long long)h[t]);
 }
 
 // ----------------------------------------------------------------------------- host side
@@ -708,12 +820,18 @@ unsigned filter_grid(uint64_t E) {
 }
 
 // Scratch bytes a query holds while it runs (the admission size of a served request).
-uint64_t query_bytes(const tt_graph *g, const QueryCtx *q, uint32_t k, bool subset) {
+uint64_t sub_stream_cap(const tt_graph *g, const QueryCtx *q) { return std::min<uint64_t>(q->sub_cap, g->m + 1); }
+uint64_t sub_list_cap(const tt_graph *g, const QueryCtx *q) { return std::min<uint64_t>(q->sub_cap, (uint64_t)g->n + 1); }
+uint64_t flag_bytes(const tt_graph *g) { return (((uint64_t)g->n + 4) & ~3ull) + 4; }
+
+uint64_t query_bytes(const tt_graph *g, const QueryCtx *q, uint32_t k, uint32_t subset_n) {
     const uint64_t cap = std::max<uint64_t>(q->min_buf, 16ull * k);
     const uint64_t cand = std::min<uint64_t>(g->m + 1, q->max_cand);
     uint64_t b = 2 * cap * sizeof(trec) + cand * sizeof(cand) + (uint64_t)k * sizeof(tt_triangle) +
                  MAX_SEG * 4 + 5 * STAT_SLOTS * 8 + 256;
-    if (subset) b += 2 * ((uint64_t)g->n + 1);
+    if (subset_n)
+        b += 2 * flag_bytes(g) + 16 * sub_stream_cap(g, q) + 4 * sub_list_cap(g, q) + 17ull * (subset_n + 1) +
+             WBINS * 8 + 256;
     return b;
 }
 
@@ -878,7 +996,8 @@ int ensure_band_events(QueryCtx *q, size_t pairs) {
 // Enqueues one enumeration pass (no host synchronisation): the band's stream is filtered and
 // intersected in pieces of at most cand_cap entries.  `slot` picks its event pair.
 int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool gated, size_t slot) {
-    const Stream S = pick_stream(g, B.mode, B.p, B.L);
+    const Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len}
+                                   : pick_stream(g, B.mode, B.p, B.L);
     EnumArgs A;
     A.rstart = g->rstart;
     A.rlen = g->rlen;
@@ -958,13 +1077,16 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     if (rc) return rc;
     hipStream_t s = q->stream;
     // thresholds: key(t, t, t) for t = weight of the k-th, 4k-th, 16k-th ... heaviest edge
+    // (for a subset query: of the k-th, 4k-th ... heaviest entry of its compact stream)
+    const std::vector<uint64_t> &hist = q->sub_active ? q->sub_hist : g->whist;
+    const uint64_t total = q->sub_active ? q->sub_len : g->m;
     std::vector<u128> Ls;
     for (uint64_t M = k; M < (1ull << 62); M *= 4) {
-        const uint32_t t = weight_at_rank(g->whist, M);
+        if (M > total) break;
+        const uint32_t t = weight_at_rank(hist, M);
         if (t <= 1) break;
         const u128 L = key_of_uniform(mode, t);
         if (Ls.empty() || L < Ls.back()) Ls.push_back(L);
-        if (M > g->m) break;
     }
     Ls.push_back(0); // exhaustive
     if ((rc = ensure_band_events(q, Ls.size()))) return rc;
@@ -1041,8 +1163,8 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
 
 int ensure_flags(const tt_graph *g, QueryCtx *q) {
     int rc;
-    if (!q->vflag && (rc = dev_alloc(nullptr, (void **)&q->vflag, (uint64_t)g->n + 1))) return rc;
-    if (!q->vflag2 && (rc = dev_alloc(nullptr, (void **)&q->vflag2, (uint64_t)g->n + 1))) return rc;
+    if (!q->vflag && (rc = dev_alloc(nullptr, (void **)&q->vflag, flag_bytes(g)))) return rc;
+    if (!q->vflag2 && (rc = dev_alloc(nullptr, (void **)&q->vflag2, flag_bytes(g)))) return rc;
     return TT_OK;
 }
 
@@ -1061,31 +1183,83 @@ int check_subset(const tt_graph *g, const uint32_t *subset, uint32_t subset_n) {
     return TT_OK;
 }
 
-// Marks the subset (vflag) and the tails with an out-neighbour in it (vflag2).
-int mark_subset(const tt_graph *g, QueryCtx *q, const uint32_t *subset, uint32_t subset_n) {
+// Marks the subset (vflag) and the vertices with an out-neighbour in it (vflag2), then builds
+// the compact stream of the entries that can be the base of a triangle touching the subset.
+// If the stream or the list would not fit (huge subsets), the passes stream every entry with
+// the vertex pre-tests instead.
+int prepare_subset(tt_graph *g, QueryCtx *q, const uint32_t *subset, uint32_t cnt) {
     int rc;
-    if ((rc = ensure_flags(g, q))) return rc;
-    uint32_t *dids = nullptr;
-    if ((rc = dev_alloc(nullptr, (void **)&dids, (uint64_t)subset_n * 4))) return rc;
-    HIP_TRY(hipMemsetAsync(q->vflag, 0, (uint64_t)g->n + 1, q->stream));
-    HIP_TRY(hipMemsetAsync(q->vflag2, 0, (uint64_t)g->n + 1, q->stream));
-    HIP_TRY(hipMemcpyAsync(dids, subset, (uint64_t)subset_n * 4, hipMemcpyHostToDevice, q->stream));
-    k_mark_vertices<<<(subset_n + 255) / 256, 256, 0, q->stream>>>(dids, subset_n, g->n, q->vflag);
-    k_mark_out_nbrs<<<enum_grid(g->m), 256, 0, q->stream>>>(g->osrc, g->col, g->m, q->vflag, q->vflag2);
-    HIP_TRY(hipStreamSynchronize(q->stream));
-    dev_free(nullptr, dids, 0);
-    return TT_OK;
+    q->sub_active = false;
+    if ((rc = ensure_in_csr(g, q->stream)) || (rc = ensure_flags(g, q))) return rc;
+    const uint64_t scap = sub_stream_cap(g, q), vcap = sub_list_cap(g, q);
+    if (!q->sub_src) {
+        if ((rc = dev_alloc(nullptr, (void **)&q->sub_src, scap * 4)) ||
+            (rc = dev_alloc(nullptr, (void **)&q->sub_col, scap * 4)) ||
+            (rc = dev_alloc(nullptr, (void **)&q->sub_wgt, scap * 4)) ||
+            (rc = dev_alloc(nullptr, (void **)&q->sub_pos, scap * 4)) ||
+            (rc = dev_alloc(nullptr, (void **)&q->sub_vlist, vcap * 4)))
+            return rc;
+    }
+    // per-query scratch: ids[cnt] | lens[cnt+1] | pre[cnt+1] (u64) | hist[WBINS] (u64) | own[cnt]
+    const uint64_t o_lens = ((uint64_t)cnt * 4 + 7) & ~7ull, o_pre = (o_lens + ((uint64_t)cnt + 1) * 4 + 7) & ~7ull;
+    const uint64_t o_hist = o_pre + ((uint64_t)cnt + 1) * 8, o_own = o_hist + WBINS * 8;
+    const uint64_t bytes = o_own + cnt;
+    char *tmp = nullptr;
+    if ((rc = dev_alloc(nullptr, (void **)&tmp, bytes))) return rc;
+    uint32_t *ids = (uint32_t *)tmp, *lens = (uint32_t *)(tmp + o_lens);
+    uint64_t *pre = (uint64_t *)(tmp + o_pre);
+    unsigned long long *hist = (unsigned long long *)(tmp + o_hist);
+    uint8_t *own = (uint8_t *)(tmp + o_own);
+    unsigned long long *cnt8 = q->dcount + 8; // [0] listed in-neighbours [1] row entries [2] kept
+    hipStream_t s = q->stream;
+    auto body = [&]() -> int {
+        HIP_TRY(hipMemsetAsync(q->vflag, 0, flag_bytes(g), s));
+        HIP_TRY(hipMemsetAsync(q->vflag2, 0, flag_bytes(g), s));
+        HIP_TRY(hipMemsetAsync(cnt8, 0, 3 * sizeof(unsigned long long), s));
+        HIP_TRY(hipMemsetAsync(hist, 0, WBINS * 8, s));
+        HIP_TRY(hipMemcpyAsync(ids, subset, (uint64_t)cnt * 4, hipMemcpyHostToDevice, s));
+        k_sub_mark<<<(cnt + 1 + 255) / 256, 256, 0, s>>>(ids, cnt, g->irstart, g->rlen, q->vflag, own, lens, cnt8);
+        HIP_TRY(hipGetLastError());
+        if ((rc = exclusive_scan_u32_to_u64(lens, pre, (uint64_t)cnt + 1, s, nullptr))) return rc;
+        k_sub_in<<<num_cus() * 8, 256, 0, s>>>(ids, cnt, pre, g->irstart, g->itail, g->rlen, q->vflag, q->vflag2,
+                                               q->sub_vlist, vcap, cnt8);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(q->hcount + 8, cnt8, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const uint64_t nv = q->hcount[8], bound = q->hcount[9];
+        if (nv > vcap || bound > scap) return TT_OK; // the full stream with vertex pre-tests
+        k_sub_rows<<<num_cus() * 8, 256, 0, s>>>(ids, own, cnt, q->sub_vlist, (uint32_t)nv, g->rstart, g->rlen,
+                                                 g->col, g->wgt, q->vflag, q->vflag2, q->sub_src, q->sub_col,
+                                                 q->sub_wgt, q->sub_pos, scap, cnt8, hist);
+        HIP_TRY(hipGetLastError());
+        q->sub_hist.assign(WBINS, 0);
+        HIP_TRY(hipMemcpyAsync(q->sub_hist.data(), hist, WBINS * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(q->hcount + 10, cnt8 + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        q->sub_len = q->hcount[10];
+        q->sub_active = true;
+        return TT_OK;
+    };
+    rc = body();
+    (void)hipStreamSynchronize(s);
+    dev_free(nullptr, tmp, bytes);
+    return rc;
 }
 
 // One exact query on context q (the caller serialises use of q).
-int query_on(const tt_graph *g, QueryCtx *q, uint32_t k, double p, const uint32_t *subset, uint32_t subset_n,
+int query_on(tt_graph *g, QueryCtx *q, uint32_t k, double p, const uint32_t *subset, uint32_t subset_n,
              tt_triangle *out, uint32_t *n_out, tt_query_stats *stats) {
     int filter = FILTER_NONE, rc;
+    q->sub_active = false;
     if (subset && subset_n) {
-        if ((rc = mark_subset(g, q, subset, subset_n))) return rc;
+        if ((rc = ensure_scratch(g, q, std::max<uint64_t>(q->min_buf, 16ull * k), k)) ||
+            (rc = prepare_subset(g, q, subset, subset_n)))
+            return rc;
         filter = FILTER_VERTICES;
     }
-    return run_topk(g, q, k, p, filter, out, n_out, stats);
+    rc = run_topk(g, q, k, p, filter, out, n_out, stats);
+    q->sub_active = false;
+    return rc;
 }
 
 // Prefix sums of w^q (input order) and their guide table, for the two most recent q.
@@ -1293,7 +1467,7 @@ extern "C" int server_create(tt_graph *g, uint32_t slots, uint64_t scratch_budge
 
 extern "C" uint64_t server_request_bytes(tt_server *S, uint32_t k, uint32_t subset_n) {
     if (!S) return 0;
-    return query_bytes(S->g, &S->ctx[0], k, subset_n > 0);
+    return query_bytes(S->g, &S->ctx[0], k, subset_n);
 }
 
 extern "C" int server_submit(tt_server *S, uint32_t k, double p, const uint32_t *subset, uint32_t subset_n,
@@ -1307,7 +1481,7 @@ extern "C" int server_submit(tt_server *S, uint32_t k, double p, const uint32_t 
     r.k = k;
     r.p = p;
     if (subset && subset_n) r.subset.assign(subset, subset + subset_n);
-    r.need = query_bytes(S->g, &S->ctx[0], k, !r.subset.empty());
+    r.need = query_bytes(S->g, &S->ctx[0], k, (uint32_t)r.subset.size());
     if (r.need > S->budget) return fail(TT_E_BUDGET, "the request needs more scratch than the server's budget");
     r.t_submit = std::chrono::steady_clock::now();
     {

@@ -60,3 +60,22 @@ def test_medium_sampling(medium, p):
     log(f"  stats {got['stats']}")
     assert got["stats"]["distinct_sampled"] == want["distinct_edges"]
     assert_parity(got, want, p, ei, ctx=f"medium es p={p}")
+
+
+@pytest.mark.parametrize("size,p", [(1000, 1.0), (1000, 0.0), (300_000, 2.0)])
+def test_medium_subset(medium, size, p):
+    """A 1,000-vertex subset takes the compact stream of its possible base entries; a
+    300,000-vertex subset has more such entries than that stream holds and streams every
+    entry with the vertex pre-tests instead.  Both against the oracle."""
+    g, G, ei = medium
+    rng = np.random.default_rng(size)
+    sub = rng.choice(g.n, size=size, replace=False).astype(np.uint32)
+    log(f"medium subset size={size} p={p}")
+    got = G.topk(500, p, subset=sub, with_stats=True)
+    log(f"  stats {got['stats']}")
+    vm = np.zeros(g.n, np.uint8)
+    vm[sub.astype(np.int64)] = 1
+    want = oracle.topk(g.n, g.src, g.dst, g.w, 500, p, vertex_mark=vm)
+    assert_parity(got, want, p, ei, ctx=f"medium subset={size} p={p}")
+    if size == 1000:
+        assert got["stats"]["edges_streamed"] < g.m  # the compact stream, not the graph

@@ -136,6 +136,24 @@ def test_subset_queries(tt, small):
             check(tt, g.n, g.src, g.dst, g.w, 50, p, G=G, subset=sub, ctx=f"subset{size}")
 
 
+def test_subset_repeats_hubs_and_everything(tt, small):
+    """Repeated ids count once; a subset made of the highest-degree vertices; the subset of all
+    vertices gives the unrestricted answer."""
+    g, G = small
+    deg = np.bincount(np.concatenate([g.src, g.dst]).astype(np.int64), minlength=g.n)
+    hubs = np.argsort(-deg, kind="stable")[:5].astype(np.uint32)
+    rep = np.concatenate([hubs, hubs[::-1], hubs[:2]])
+    for p in (1.0, -math.inf, 0.0):
+        log(f"subset hubs p={p}")
+        a, _ = check(tt, g.n, g.src, g.dst, g.w, 200, p, G=G, subset=rep, ctx="subset-rep")
+        b = G.topk(200, p, subset=hubs)
+        assert triples(a) == triples(b) and np.array_equal(a["score"], b["score"])
+    every = np.arange(g.n, dtype=np.uint32)[::-1].copy()
+    for p in (2.0, -1.0):
+        a, b = G.topk(300, p, subset=every), G.topk(300, p)
+        assert triples(a) == triples(b) and np.array_equal(a["score"], b["score"])
+
+
 def test_validation_errors(tt):
     cases = [
         (3, [0, 1], [1, 1], [1, 1]),
