@@ -154,12 +154,21 @@ def batch_specs(count: int = 4096, seed: int = 0, n_lo: int = 50, n_hi: int = 20
     return [(int(a), int(b), int(c)) for a, b, c in zip(ns, ms, seeds)]
 
 
-def batch(count: int = 4096, seed: int = 0, **kw):
-    """The batched workload: a list of independent Chung-Lu graphs (gamma 2.5, Zipf(s=2))."""
-    out = []
-    for i, (n, m, s) in enumerate(batch_specs(count, seed, **kw)):
-        out.append(chung_lu(n, m, 2.5, 2.0, seed=s, name=f"batch[{i}]"))
-    return out
+def batch(count: int = 4096, seed: int = 0, workers: int = 0, **kw):
+    """The batched workload: a list of independent Chung-Lu graphs (gamma 2.5, Zipf(s=2)).
+
+    Graphs are generated on a thread pool (the C generator releases the GIL); each graph has its
+    own seed, so the result does not depend on the number of workers."""
+    from concurrent.futures import ThreadPoolExecutor
+    specs = batch_specs(count, seed, **kw)
+    workers = workers or min(16, os.cpu_count() or 1)
+
+    def one(i):
+        n, m, s = specs[i]
+        return chung_lu(n, m, 2.5, 2.0, seed=s, name=f"batch[{i}]")
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(one, range(len(specs))))
 
 
 P_CHOICES = (-math.inf, -1.0, 0.0, 1.0, 2.0, math.inf)

@@ -159,6 +159,61 @@ int server_info(tt_server *s, uint64_t *admitted, uint64_t *completed, uint64_t 
 /* Finishes every queued request, then stops the workers and frees their memory.  NULL-safe. */
 void server_destroy(tt_server *s);
 
+/*
+ * Batched form: one top-k per graph for many independent graphs (the problem of Sec. 1 for
+ * each of them), answered by one captured launch sequence.  The graphs are concatenated:
+ * graph g has n[g] vertices with LOCAL ids 0..n[g]-1 and m[g] edges, stored at positions
+ * eoff[g] .. eoff[g]+m[g]-1 of src/dst/w, eoff being the exclusive prefix sum of m.  Every
+ * graph must be simple with positive weights (validated as in graph_load; a vertex id >= n[g]
+ * gives TT_E_VERTEX_RANGE naming the graph).  Together the graphs may hold at most 2^32 - 2
+ * vertices and 2^32 - 2 edges.  Inputs are copied; *out receives the handle.
+ */
+typedef struct tt_batch tt_batch;
+
+/* n[count], m[count]: HOST arrays; src/dst/w: HOST arrays of sum(m) entries. */
+int batch_load(uint32_t count, const uint32_t *n, const uint64_t *m, const uint32_t *src,
+               const uint32_t *dst, const uint32_t *w, tt_batch **out);
+
+/* As batch_load with src/dst/w in DEVICE memory (n and m stay on the host), read on `stream`
+ * (a hipStream_t) in order with the work that produced them; with NULL the null stream is
+ * synchronised first. */
+int batch_load_device(uint32_t count, const uint32_t *n, const uint64_t *m, const uint32_t *src,
+                      const uint32_t *dst, const uint32_t *w, void *stream, tt_batch **out);
+
+/* Counters and launch choices of one batched query (optional output of batch_topk_ex). */
+typedef struct {
+    uint64_t candidate_edges, intersected_entries, triangles_emitted, edges_streamed;
+    uint32_t config;           /* launch configuration used (index, see batch_topk_ex) */
+    uint32_t growth;           /* rank ratio between consecutive score bands */
+    uint32_t filter_blocks, intersect_blocks, passes;
+    uint32_t restarts;         /* graphs redone because their triangle region overflowed */
+    double launch_ms;          /* device time of the captured sequence (HIP events) */
+    double tune_ms;            /* host time spent by the autotuner in this call (first use) */
+    double total_ms;           /* host wall time of the call */
+} tt_batch_stats;
+
+enum { TT_BATCH_EAGER = 1 }; /* run the launch sequence directly instead of its captured graph */
+
+/*
+ * out: HOST, count*k triangles; graph g's top min(k, T_g) are out[g*k ...] in local ids,
+ * sorted as topk_triangles sorts them; n_out: HOST, count values.  config = -1 uses the
+ * autotuner's choice for this (k, p) (timed on first use over every configuration), or
+ * 0 .. batch_num_configs()-1 forces one.  Every configuration and both launch modes return
+ * exactly the same result.  Calls on one batch are serialised.
+ */
+int batch_topk_ex(tt_batch *b, uint32_t k, double p, int config, uint32_t flags, tt_triangle *out,
+                  uint32_t *n_out, tt_batch_stats *stats);
+int batch_topk(tt_batch *b, uint32_t k, double p, tt_triangle *out, uint32_t *n_out);
+
+/* Number of launch configurations the autotuner chooses from. */
+uint32_t batch_num_configs(void);
+
+/* Number of graphs (0 for NULL). */
+uint32_t batch_num_graphs(const tt_batch *b);
+
+/* Releases every resource of b.  NULL-safe. */
+void batch_free(tt_batch *b);
+
 /* Number of vertices / undirected edges of a loaded graph (0 for NULL). */
 uint32_t graph_num_vertices(const tt_graph *g);
 uint64_t graph_num_edges(const tt_graph *g);

@@ -25,7 +25,9 @@ TT_E_VERTEX_RANGE, TT_E_NOMEM, TT_E_DEVICE, TT_E_BUDGET, TT_E_TOO_LARGE = -5, -6
 EXPORTED = ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles_ex", "sample_heavy_triangles",
             "sample_heavy_triangles_ex", "graph_num_vertices", "graph_num_edges", "graph_device_bytes",
             "graph_free", "tt_last_error", "server_create", "server_request_bytes", "server_submit", "server_poll",
-            "server_wait", "server_info", "server_destroy")
+            "server_wait", "server_info", "server_destroy", "batch_load", "batch_load_device", "batch_topk",
+            "batch_topk_ex", "batch_num_configs", "batch_num_graphs", "batch_free")
+TT_BATCH_EAGER = 1
 
 
 class Triangle(ctypes.Structure):
@@ -39,6 +41,17 @@ class QueryStats(ctypes.Structure):
                 ("distinct_sampled", ctypes.c_uint64), ("passes", ctypes.c_uint32), ("restarts", ctypes.c_uint32),
                 ("enum_ms", ctypes.c_double), ("select_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("enum_kernel_ms", ctypes.c_double), ("sample_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("candidate_edges", ctypes.c_uint64), ("intersected_entries", ctypes.c_uint64),
+                ("triangles_emitted", ctypes.c_uint64), ("edges_streamed", ctypes.c_uint64),
+                ("config", ctypes.c_uint32), ("growth", ctypes.c_uint32), ("filter_blocks", ctypes.c_uint32),
+                ("intersect_blocks", ctypes.c_uint32), ("passes", ctypes.c_uint32), ("restarts", ctypes.c_uint32),
+                ("launch_ms", ctypes.c_double), ("tune_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -105,9 +118,21 @@ def library():
         lib.server_info.argtypes = [vp, p64, p64, p64, p32, p32]
         lib.server_destroy.argtypes = [vp]
         lib.server_destroy.restype = None
+        pbst = ctypes.POINTER(BatchStats)
+        lib.batch_load.argtypes = [u32, p32, p64, p32, p32, p32, pg]
+        lib.batch_load_device.argtypes = [u32, p32, p64, vp, vp, vp, vp, pg]
+        lib.batch_topk.argtypes = [vp, u32, dbl, ptri, p32]
+        lib.batch_topk_ex.argtypes = [vp, u32, dbl, i32, u32, ptri, p32, pbst]
+        lib.batch_num_configs.argtypes = []
+        lib.batch_num_configs.restype = u32
+        lib.batch_num_graphs.argtypes = [vp]
+        lib.batch_num_graphs.restype = u32
+        lib.batch_free.argtypes = [vp]
+        lib.batch_free.restype = None
         for name in ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles_ex",
                      "sample_heavy_triangles", "sample_heavy_triangles_ex", "server_create", "server_submit",
-                     "server_poll", "server_wait", "server_info"):
+                     "server_poll", "server_wait", "server_info", "batch_load", "batch_load_device", "batch_topk",
+                     "batch_topk_ex"):
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -259,6 +284,82 @@ class Server:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             library().server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent graphs resident on the GPU, queried together (see batch_load).
+
+    ``graphs`` is a sequence of (n, src, dst, w) with local vertex ids, or the concatenated
+    form ``(ns, ms, src, dst, w)`` given through ``Batch.concat``."""
+
+    def __init__(self, graphs=None, *, ns=None, ms=None, src=None, dst=None, w=None, stream=None):
+        lib = library()
+        if graphs is not None:
+            graphs = list(graphs)
+            ns = np.array([int(g[0]) for g in graphs], np.uint32)
+            ms = np.array([len(g[1]) for g in graphs], np.uint64)
+            src = np.concatenate([_u32(g[1]) for g in graphs]) if graphs else np.zeros(0, np.uint32)
+            dst = np.concatenate([_u32(g[2]) for g in graphs]) if graphs else np.zeros(0, np.uint32)
+            w = np.concatenate([_u32(g[3]) for g in graphs]) if graphs else np.zeros(0, np.uint32)
+        ns = np.ascontiguousarray(ns, dtype=np.uint32)
+        ms = np.ascontiguousarray(ms, dtype=np.uint64)
+        if ns.shape != ms.shape or ns.ndim != 1:
+            raise ValueError("ns and ms must be 1-D arrays of equal length")
+        self._h = ctypes.c_void_p()
+        p32, p64 = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64)
+        if hasattr(src, "is_cuda") and src.is_cuda:
+            import torch
+            s, d, ww = (x.contiguous().to(torch.int32) for x in (src, dst, w))
+            if stream is None:
+                stream = torch.cuda.current_stream(src.device)
+            st = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+            _check(lib.batch_load_device(len(ns), ns.ctypes.data_as(p32), ms.ctypes.data_as(p64),
+                                         ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(d.data_ptr()),
+                                         ctypes.c_void_p(ww.data_ptr()), st, ctypes.byref(self._h)))
+        else:
+            s, d, ww = _u32(src), _u32(dst), _u32(w)
+            if not (s.shape == d.shape == ww.shape) or int(ms.sum()) != s.shape[0]:
+                raise ValueError("src, dst, w must hold sum(ms) edges each")
+            _check(lib.batch_load(len(ns), ns.ctypes.data_as(p32), ms.ctypes.data_as(p64), s.ctypes.data_as(p32),
+                                  d.ctypes.data_as(p32), ww.ctypes.data_as(p32), ctypes.byref(self._h)))
+        self.count = int(len(ns))
+
+    @staticmethod
+    def num_configs() -> int:
+        return int(library().batch_num_configs())
+
+    def topk(self, k: int, p: float, config: int = -1, eager: bool = False, with_stats: bool = False):
+        """Top-k of every graph.  Returns dict(i, j, l, score: [count, k] arrays, n_out: [count])."""
+        lib = library()
+        k = int(k)
+        buf = (Triangle * max(self.count * k, 1))()
+        n_out = np.zeros(max(self.count, 1), np.uint32)
+        st = BatchStats()
+        _check(lib.batch_topk_ex(self._h, k, float(p), int(config), TT_BATCH_EAGER if eager else 0, buf,
+                                 n_out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(st)))
+        r = np.frombuffer(buf, dtype=TRI_DTYPE, count=self.count * k).copy().reshape(self.count, k)
+        r[np.arange(k)[None, :] >= n_out[: self.count, None]] = 0  # rows hold n_out[g] triangles
+        out = {"i": r["i"], "j": r["j"], "l": r["l"], "score": r["score"], "n_out": n_out[: self.count].copy()}
+        if with_stats:
+            out["stats"] = st.as_dict()
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().batch_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __enter__(self):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtopktri.so")
-SOURCES = ["graph.hip", "query.hip", "scan.hip"]
+SOURCES = ["graph.hip", "query.hip", "scan.hip", "batch.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # strict IEEE evaluation of the FP64 scores: no contraction into FMA

@@ -30,444 +30,10 @@
 #include <unordered_map>
 
 #include "common.h"
+#include "enum.h"
 #include "scan.h"
 
 namespace {
-
-// ----------------------------------------------------------------------------- scoring
-__device__ __forceinline__ double u128_to_double(u128 x) {
-    return (double)(uint64_t)(x >> 64) * 18446744073709551616.0 + (double)(uint64_t)x;
-}
-
-// Eq. 1 for a generic p, rewritten so that no power overflows and small |p| loses nothing:
-// m = s * exp(log1p(mean(expm1(p * log(x/s)))) / p), s = max (p > 0) or min (p < 0).
-__device__ double gen_mean(double p, double a, double b, double c) {
-    const double s = p > 0.0 ? fmax(a, fmax(b, c)) : fmin(a, fmin(b, c));
-    const double acc = expm1(p * log(a / s)) + expm1(p * log(b / s)) + expm1(p * log(c / s));
-    return s * exp(log1p(acc / 3.0) / p);
-}
-
-__device__ __forceinline__ u128 score_key(int mode, double p, uint32_t a, uint32_t b, uint32_t c) {
-    switch (mode) {
-    case MODE_MAX: return (u128)max(a, max(b, c));
-    case MODE_MIN: return (u128)min(a, min(b, c));
-    case MODE_SUM: return (u128)((uint64_t)a + b + c);
-    case MODE_SUMSQ: return (u128)((uint64_t)a * a) + (u128)((uint64_t)b * b) + (u128)((uint64_t)c * c);
-    case MODE_PROD: {
-        const uint64_t ab = (uint64_t)a * b;
-        const uint64_t lo = ab * (uint64_t)c, hi = __umul64hi(ab, (uint64_t)c);
-        return ((u128)hi << 64) | lo;
-    }
-    default: return (u128)(uint64_t)__double_as_longlong(gen_mean(p, (double)a, (double)b, (double)c));
-    }
-}
-
-__device__ double key_to_score(int mode, u128 key) {
-    switch (mode) {
-    case MODE_MAX:
-    case MODE_MIN: return (double)(uint64_t)key;
-    case MODE_SUM: return (double)(uint64_t)key / 3.0;
-    case MODE_SUMSQ: return sqrt(u128_to_double(key) / 3.0);
-    case MODE_PROD: return cbrt(u128_to_double(key));
-    default: return __longlong_as_double((long long)(uint64_t)key);
-    }
-}
-
-__device__ __forceinline__ bool better(const trec &a, const trec &b) {
-    if (a.khi != b.khi) return a.khi > b.khi;
-    if (a.klo != b.klo) return a.klo > b.klo;
-    if (a.i != b.i) return a.i < b.i;
-    if (a.j != b.j) return a.j < b.j;
-    return a.l < b.l;
-}
-
-// ----------------------------------------------------------------------------- bounds
-struct Band {
-    u128 L;              // inclusive lower bound on the order key ...
-    uint32_t Li, Lj, Ll; // ... and, at key == L, on (i, j, l) (all 0xFFFFFFFF: no restriction)
-    u128 U;              // exclusive upper bound on the order key if hasU
-    int hasU;
-    int mode;
-    double p;
-    double theta;        // generic p: the score L as a double
-};
-
-// key(a, Wu, Wv) >= L : no triangle on this entry can reach the band otherwise
-__device__ __forceinline__ bool bound_ok(const Band &B, uint32_t a, uint32_t Wu, uint32_t Wv) {
-    if (B.L == 0) return true;
-    if (B.mode == MODE_GEN) {
-        // cheap upper bounds first: m_p <= max for every p, m_p <= arithmetic mean for p <= 1
-        const double lim = B.theta * (1.0 - 1e-12);
-        const double da = (double)a, du = (double)Wu, dv = (double)Wv;
-        if (fmax(da, fmax(du, dv)) < lim) return false;
-        if (B.p <= 1.0 && (da + du + dv) / 3.0 < lim * (1.0 - 1e-12)) return false;
-        return gen_mean(B.p, da, du, dv) >= lim;
-    }
-    return score_key(B.mode, B.p, a, Wu, Wv) >= B.L;
-}
-
-// Smallest weight x (never above the exact one) with m_p(a, x, W) >= theta, generic p.
-__host__ __device__ uint64_t gen_min_other(double p, double theta, double a, double W) {
-    if (p > 0.0) {
-        const double s = fmax(theta, fmax(a, W));
-        const double t3 = 3.0 * pow(theta / s, p);
-        double D = t3 - pow(a / s, p) - pow(W / s, p);
-        D -= 1e-12 * (t3 + 2.0);
-        if (!(D > 0.0)) return 0;
-        const double x = s * pow(D, 1.0 / p) * (1.0 - 1e-9);
-        return x < 1.0 ? 0 : (x >= 1.8e19 ? ~0ull : (uint64_t)floor(x));
-    } else {
-        const double s = fmin(theta, fmin(a, W));
-        const double t3 = 3.0 * pow(theta / s, p);
-        double D = t3 - pow(a / s, p) - pow(W / s, p);
-        D += 1e-12 * (t3 + 2.0);
-        if (!(D > 0.0)) return ~0ull;
-        const double x = s * pow(D, 1.0 / p) * (1.0 - 1e-9);
-        return x < 1.0 ? 0 : (x >= 1.8e19 ? ~0ull : (uint64_t)floor(x));
-    }
-}
-
-// Smallest weight x (a lower bound of it) for which key(a, x, W) can still reach L.
-__device__ uint64_t min_other(const Band &B, uint32_t a, uint32_t W) {
-    if (B.L == 0) return 0;
-    switch (B.mode) {
-    case MODE_MAX: return ((u128)a >= B.L || (u128)W >= B.L) ? 0 : (uint64_t)B.L;
-    case MODE_MIN: return (uint64_t)B.L;
-    case MODE_SUM: {
-        const uint64_t aw = (uint64_t)a + W, L = (uint64_t)B.L;
-        return L > aw ? L - aw : 0;
-    }
-    case MODE_SUMSQ: {
-        const u128 aw = (u128)((uint64_t)a * a) + (u128)((uint64_t)W * W);
-        if (B.L <= aw) return 0;
-        const uint64_t z = (uint64_t)sqrt(u128_to_double(B.L - aw));
-        return z > 1 ? z - 1 : 0;
-    }
-    case MODE_PROD: {
-        const double q = u128_to_double(B.L) / ((double)a * (double)W);
-        if (q <= 1.0) return 0;
-        if (q >= 1.8e19) return ~0ull;
-        const uint64_t z = (uint64_t)q;
-        return z > 1 ? z - 1 : 0;
-    }
-    default: return gen_min_other(B.p, B.theta, (double)a, (double)W);
-    }
-}
-
-__device__ __forceinline__ bool in_band(const Band &B, u128 key, uint32_t i, uint32_t j, uint32_t l) {
-    if (B.hasU && key >= B.U) return false;
-    if (key != B.L) return key > B.L;
-    return i < B.Li || (i == B.Li && (j < B.Lj || (j == B.Lj && l <= B.Ll)));
-}
-
-// ----------------------------------------------------------------------------- enumeration
-enum { FILTER_NONE = 0, FILTER_EDGES = 1, FILTER_VERTICES = 2 };
-enum { FL_MARK_UV = 1, FL_REQ_A = 2, FL_REQ_B = 4, FL_REQ_C = 8 };
-
-struct EnumArgs {
-    const uint64_t *rstart;
-    const uint32_t *rlen, *col, *wgt, *wcol, *wwgt, *wpos, *maxw;
-    // the stream of candidate entries (tail, head, weight, head-sorted position or NULL if the
-    // stream is the head-sorted layout itself) and its length
-    const uint32_t *s_src, *s_col, *s_wgt, *s_pos;
-    uint64_t E;
-    uint64_t pos_off; // head-sorted position of stream entry 0 when s_pos is NULL
-    const unsigned long long *skip; // set (between passes) once the answer is complete
-    Band B;
-    const uint8_t *emark;  // FILTER_EDGES: drawn entries (head-sorted positions)
-    const uint8_t *vflag;  // FILTER_EDGES: vertex has a drawn out-entry; FILTER_VERTICES: vertex in subset
-    const uint8_t *vflag2; // FILTER_VERTICES: vertex has an out-neighbour in the subset
-    trec *out;
-    unsigned long long *count;
-    uint64_t cap;
-    // per-pass counters, each spread over STAT_SLOTS slots to avoid same-address atomics:
-    // [0] candidates [1] intersected entries [2] emitted [3] streamed [4] passes
-    unsigned long long *stats;
-    // candidate list: block b of the filter writes its candidates to C[b*seg ...] and their
-    // number to ccnt[b]
-    cand *C;
-    uint32_t *ccnt;
-    uint64_t seg;
-    uint32_t nseg;
-};
-
-constexpr int STAT_SLOTS = 1024;
-__device__ __forceinline__ void stat_add(unsigned long long *stats, int c, unsigned long long v) {
-    if (v) atomicAdd(&stats[c * STAT_SLOTS + (blockIdx.x & (STAT_SLOTS - 1))], v);
-}
-
-// Number of entries of a weight-sorted (descending) row with weight >= z.
-__device__ __forceinline__ uint32_t count_at_least(const uint32_t *ww, uint64_t b, uint32_t len, uint64_t z) {
-    if (z == 0) return len;
-    uint32_t lo = 0, hi = len;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if ((uint64_t)ww[b + mid] >= z) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-// Number of entries of two weight-sorted rows at or above their floors; both binary searches
-// advance together so that their loads overlap.
-__device__ __forceinline__ void count_pair(const uint32_t *ww, uint64_t b1, uint32_t n1, uint64_t z1, uint64_t b2,
-                                           uint32_t n2, uint64_t z2, uint32_t &q1, uint32_t &q2) {
-    uint32_t lo1 = z1 ? 0 : n1, hi1 = n1, lo2 = z2 ? 0 : n2, hi2 = n2;
-    while (lo1 < hi1 || lo2 < hi2) {
-        if (lo1 < hi1) {
-            const uint32_t mid = (lo1 + hi1) >> 1;
-            if ((uint64_t)ww[b1 + mid] >= z1) lo1 = mid + 1; else hi1 = mid;
-        }
-        if (lo2 < hi2) {
-            const uint32_t mid = (lo2 + hi2) >> 1;
-            if ((uint64_t)ww[b2 + mid] >= z2) lo2 = mid + 1; else hi2 = mid;
-        }
-    }
-    q1 = lo1;
-    q2 = lo2;
-}
-
-constexpr int FILTER_UNROLL = 4;
-
-// Phase 1: stream the first E entries of the chosen order; an entry that can be the base of a
-// triangle in the band (bound test + subset / sampling pre-test) is appended to the candidate
-// list (wave ballot, one atomic per wave).  Pure streaming: FILTER_UNROLL entries per lane
-// are in flight at once.
-template <int FILTER> __global__ __launch_bounds__(256) void k_filter(EnumArgs A) {
-    __shared__ uint32_t lcount;
-    if (A.skip && *A.skip) return; // written only between passes
-    if (threadIdx.x == 0) lcount = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        stat_add(A.stats, 3, A.E);
-        stat_add(A.stats, 4, 1);
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const uint64_t lo = (uint64_t)blockIdx.x * A.seg;
-    const uint64_t hi = lo + A.seg < A.E ? lo + A.seg : A.E;
-    cand *out = A.C + lo;
-    for (uint64_t base = lo + (threadIdx.x >> 6) * 64 * FILTER_UNROLL; base < hi; base += blockDim.x * FILTER_UNROLL) {
-        uint32_t u[FILTER_UNROLL], v[FILTER_UNROLL], a[FILTER_UNROLL], pos[FILTER_UNROLL];
-        bool pass[FILTER_UNROLL];
-#pragma unroll
-        for (int k = 0; k < FILTER_UNROLL; k++) {
-            const uint64_t e = base + (uint64_t)k * 64 + lane;
-            pass[k] = e < hi;
-            u[k] = v[k] = a[k] = pos[k] = 0;
-            if (pass[k]) {
-                u[k] = A.s_src[e];
-                v[k] = A.s_col[e];
-                a[k] = A.s_wgt[e];
-                pos[k] = A.s_pos ? A.s_pos[e] : (uint32_t)(e + A.pos_off);
-            }
-        }
-        uint32_t n_pass = 0, rank[FILTER_UNROLL];
-#pragma unroll
-        for (int k = 0; k < FILTER_UNROLL; k++) {
-            if (pass[k]) {
-                bool pre = true;
-                if (FILTER == FILTER_EDGES) pre = A.emark[pos[k]] || A.vflag[u[k]] || A.vflag[v[k]];
-                else if (FILTER == FILTER_VERTICES)
-                    pre = A.vflag[u[k]] || A.vflag[v[k]] || (A.vflag2[u[k]] && A.vflag2[v[k]]);
-                pass[k] = pre && bound_ok(A.B, a[k], A.maxw[u[k]], A.maxw[v[k]]);
-            }
-            const uint64_t bal = __ballot(pass[k]);
-            rank[k] = n_pass + __popcll(bal & ((1ull << lane) - 1ull));
-            n_pass += __popcll(bal);
-        }
-        if (n_pass) {
-            uint32_t b0 = 0;
-            if (lane == 0) b0 = atomicAdd(&lcount, n_pass); // LDS atomic: block-local offset
-            b0 = __shfl(b0, 0, 64);
-#pragma unroll
-            for (int k = 0; k < FILTER_UNROLL; k++)
-                if (pass[k]) out[b0 + rank[k]] = cand{u[k], v[k], a[k], pos[k]};
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        A.ccnt[blockIdx.x] = lcount;
-        stat_add(A.stats, 0, lcount);
-    }
-}
-
-// Phase 2: persistent waves over the candidate list (its length is read on the device).  A
-// candidate u->v gets the weight floors zu (for w_uc) and zv (for w_vc); the entries of each
-// row at or above its floor are a prefix of the weight-sorted copy of the row.  The side with
-// fewer such entries is iterated: the wave flattens the (candidate, qualifying element) pairs
-// of its 64 candidates across its lanes, and each lane binary-searches its element in the
-// other row's head-sorted copy.
-constexpr int MAX_SEG = 4096;
-
-template <int FILTER> __global__ __launch_bounds__(256) void k_intersect(EnumArgs A) {
-    __shared__ uint32_t pre[MAX_SEG + 1]; // exclusive prefix of 64-candidate chunks per segment
-    __shared__ uint32_t wsum[4];
-    if (A.skip && *A.skip) return;
-    const int lane = threadIdx.x & 63;
-    {
-        // block scan of the per-segment chunk counts (each thread owns 16 consecutive segments)
-        constexpr int PER = (MAX_SEG + 255) / 256;
-        uint32_t loc[PER], sum = 0;
-#pragma unroll
-        for (int i = 0; i < PER; i++) {
-            const uint32_t sg = threadIdx.x * PER + i;
-            loc[i] = sg < A.nseg ? (A.ccnt[sg] + 63) >> 6 : 0;
-            sum += loc[i];
-        }
-        const uint32_t incl = wave_incl_scan(sum);
-        if (lane == 63) wsum[threadIdx.x >> 6] = incl;
-        __syncthreads();
-        uint32_t run = incl - sum;
-        for (int w = 0; w < (int)(threadIdx.x >> 6); w++) run += wsum[w];
-#pragma unroll
-        for (int i = 0; i < PER; i++) {
-            pre[threadIdx.x * PER + i] = run;
-            run += loc[i];
-        }
-        if (threadIdx.x == 255) pre[MAX_SEG] = run;
-        __syncthreads();
-    }
-    const uint32_t nchunks = pre[MAX_SEG];
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    unsigned long long s_inter = 0, s_emit = 0;
-    for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
-        // segment holding chunk ch: the last sg with pre[sg] <= ch
-        uint32_t lo_s = 0, hi_s = MAX_SEG;
-        while (hi_s - lo_s > 1) {
-            const uint32_t mid = (lo_s + hi_s) >> 1;
-            if (pre[mid] <= ch) lo_s = mid; else hi_s = mid;
-        }
-        const uint32_t sg = lo_s;
-        const uint64_t j = ((uint64_t)(ch - pre[sg]) << 6) + (uint64_t)lane;
-        bool pass = false;
-        uint32_t a = 0, u = 0, v = 0, qA = 0, Blen = 0, fl = 0;
-        uint64_t Ab = 0, Bb = 0, zB = 0;
-        if (j < A.ccnt[sg]) {
-            const cand c = A.C[(uint64_t)sg * A.seg + j];
-            u = c.u;
-            v = c.v;
-            a = c.a;
-            const uint32_t Wu = A.maxw[u], Wv = A.maxw[v];
-            const uint64_t ub = A.rstart[u], vb = A.rstart[v];
-            const uint32_t ul = A.rlen[u], vl = A.rlen[v];
-            if (FILTER == FILTER_EDGES && A.emark[c.pos]) fl |= FL_MARK_UV;
-            if (FILTER == FILTER_VERTICES && !A.vflag[u] && !A.vflag[v]) fl |= FL_REQ_C;
-            const uint64_t zu = min_other(A.B, a, Wv), zv = min_other(A.B, a, Wu);
-            pass = zu <= Wu && zv <= Wv;
-            if (pass) {
-                uint32_t qu, qv;
-                count_pair(A.wwgt, ub, ul, zu, vb, vl, zv, qu, qv);
-                const bool uA = qu <= qv;
-                qA = uA ? qu : qv;
-                Ab = uA ? ub : vb;
-                Bb = uA ? vb : ub;
-                Blen = uA ? vl : ul;
-                zB = uA ? zv : zu;
-                if (qu == 0 || qv == 0) pass = false;
-                if (FILTER == FILTER_EDGES && !(fl & FL_MARK_UV)) {
-                    // a drawn edge must be one of the other two
-                    const bool fa = A.vflag[uA ? u : v], fb = A.vflag[uA ? v : u];
-                    if (!fa && !fb) pass = false;
-                    if (!fb) fl |= FL_REQ_A; // only drawn entries of the iterated row can help
-                    if (!fa) fl |= FL_REQ_B;
-                }
-            }
-        }
-        const uint32_t work = pass ? qA : 0;
-        const uint32_t incl = wave_incl_scan(work);
-        const uint32_t total = __shfl(incl, 63, 64);
-        if (lane == 0) s_inter += total;
-        for (uint32_t base = 0; base < total; base += 64) {
-            const uint32_t t = base + (uint32_t)lane;
-            const uint32_t tt = t < total ? t : total - 1;
-            int s = 0; // owner lane: number of lanes whose inclusive end is <= tt
-#pragma unroll
-            for (int st = 32; st > 0; st >>= 1) {
-                const uint32_t im = __shfl(incl, s + st - 1, 64);
-                if (im <= tt) s += st;
-            }
-            const uint32_t o_incl = __shfl(incl, s, 64), o_work = __shfl(work, s, 64);
-            const uint64_t oAb = __shfl(Ab, s, 64), oBb = __shfl(Bb, s, 64), ozB = __shfl(zB, s, 64);
-            const uint32_t oBlen = __shfl(Blen, s, 64), oa = __shfl(a, s, 64), ou = __shfl(u, s, 64),
-                           ov = __shfl(v, s, 64), ofl = __shfl(fl, s, 64);
-            bool ok = false;
-            trec r;
-            if (t < total) {
-                const uint64_t pa = oAb + (tt - (o_incl - o_work));
-                const uint32_t c = A.wcol[pa], x = A.wwgt[pa];
-                bool go = true;
-                if (FILTER == FILTER_VERTICES && (ofl & FL_REQ_C)) go = A.vflag[c];
-                uint8_t markA = 0;
-                if (FILTER == FILTER_EDGES) {
-                    markA = A.emark[A.wpos[pa]];
-                    if (ofl & FL_REQ_A) go = markA;
-                }
-                if (go) {
-                    uint64_t lo = oBb, hi = oBb + oBlen;
-                    while (lo < hi) {
-                        const uint64_t mid = (lo + hi) >> 1;
-                        if (A.col[mid] < c) lo = mid + 1; else hi = mid;
-                    }
-                    if (lo < oBb + oBlen && A.col[lo] == c) {
-                        const uint32_t y = A.wgt[lo];
-                        bool adm = (uint64_t)y >= ozB;
-                        if (FILTER == FILTER_EDGES) {
-                            const uint8_t markB = A.emark[lo];
-                            if (ofl & FL_REQ_B) adm = adm && markB;
-                            adm = adm && ((ofl & FL_MARK_UV) || markA || markB);
-                        }
-                        if (adm) {
-                            const u128 key = score_key(A.B.mode, A.B.p, oa, x, y);
-                            uint32_t i = ou, j = ov, l = c, tmp;
-                            if (i > j) { tmp = i; i = j; j = tmp; }
-                            if (j > l) { tmp = j; j = l; l = tmp; }
-                            if (i > j) { tmp = i; i = j; j = tmp; }
-                            ok = in_band(A.B, key, i, j, l);
-                            r.khi = (uint64_t)(key >> 64);
-                            r.klo = (uint64_t)key;
-                            r.i = i; r.j = j; r.l = l; r.pad = 0;
-                        }
-                    }
-                }
-            }
-            const uint64_t bal = __ballot(ok);
-            if (bal) {
-                const uint32_t nb = __popcll(bal);
-                unsigned long long b0 = 0;
-                if (lane == 0) b0 = atomicAdd(A.count, (unsigned long long)nb);
-                b0 = __shfl(b0, 0, 64);
-                const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
-                if (ok && b0 + rank < A.cap) A.out[b0 + rank] = r;
-                if (lane == 0) s_emit += nb;
-            }
-        }
-    }
-    if (lane == 0) {
-        stat_add(A.stats, 1, s_inter);
-        stat_add(A.stats, 2, s_emit);
-    }
-}
-
-// Sums the spread counters into out[0..5) and clears them.
-__global__ void k_reduce_stats(unsigned long long *stats, unsigned long long *out) {
-    const int c = blockIdx.x;
-    unsigned long long v = 0;
-    for (int t = threadIdx.x; t < STAT_SLOTS; t += blockDim.x) {
-        v += stats[c * STAT_SLOTS + t];
-        stats[c * STAT_SLOTS + t] = 0;
-    }
-    v = wave_sum(v);
-    __shared__ unsigned long long ws[4];
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) out[c] = ws[0] + ws[1] + ws[2] + ws[3];
-}
-
-// Between two passes: the later bands are skipped once the buffer holds >= k triangles (the
-// answer is complete) or has overflowed (the host restarts).
-__global__ void k_band_gate(const unsigned long long *count, unsigned long long k, unsigned long long *skip) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && *count >= k) *skip = 1;
-}
 
 // ----------------------------------------------------------------------------- selection
 constexpr int STILE = 1024;
@@ -769,29 +335,6 @@ __global__ __launch_bounds__(256) void k_sub_rows(const uint32_t *ids, const uin
 }
 
 // ----------------------------------------------------------------------------- host side
-u128 key_of_uniform(int mode, uint32_t t) {
-    switch (mode) {
-    case MODE_MAX:
-    case MODE_MIN: return t;
-    case MODE_SUM: return (u128)3 * t;
-    case MODE_SUMSQ: return (u128)3 * ((uint64_t)t * t);
-    case MODE_PROD: return (u128)((uint64_t)t * t) * t;
-    default: {
-        double d = (double)t;
-        uint64_t b;
-        std::memcpy(&b, &d, 8);
-        return b;
-    }
-    }
-}
-
-double key_as_double(u128 L) {
-    uint64_t b = (uint64_t)L;
-    double d;
-    std::memcpy(&d, &b, 8);
-    return d;
-}
-
 // The weight of (a lower bound of) the M-th heaviest edge, from the load-time histogram.
 uint32_t weight_at_rank(const std::vector<uint64_t> &h, uint64_t M) {
     uint64_t cum = 0;
@@ -935,33 +478,6 @@ uint64_t entries_for(const tt_graph *g, int mode, u128 L) {
     if (t > 0xFFFFFFFFull) return 0;
     const uint32_t b = weight_bin((uint32_t)t);
     return g->ebase[b] + g->ebin[b];
-}
-
-// The lightest edge of any triangle whose key is >= L weighs at least this (a lower bound):
-// with the other two edges at the graph's largest weight W, key(W, W, z) must still reach L.
-uint64_t weight_floor(int mode, double p, u128 L, uint32_t W) {
-    if (L == 0) return 0;
-    switch (mode) {
-    case MODE_MAX: return 0;
-    case MODE_MIN: return (uint64_t)L;
-    case MODE_SUM: {
-        const u128 w2 = (u128)2 * W;
-        return L > w2 ? (uint64_t)(L - w2) : 0;
-    }
-    case MODE_SUMSQ: {
-        const u128 w2 = (u128)2 * ((uint64_t)W * W);
-        if (L <= w2) return 0;
-        const uint64_t z = (uint64_t)std::sqrt((double)(L - w2));
-        return z > 1 ? z - 1 : 0;
-    }
-    case MODE_PROD: {
-        const double q = (double)L / ((double)W * (double)W);
-        if (q <= 1.0) return 0;
-        const uint64_t z = q >= 1.8e19 ? ~0ull : (uint64_t)q;
-        return z > 1 ? z - 1 : 0;
-    }
-    default: return gen_min_other(p, key_as_double(L), (double)W, (double)W);
-    }
 }
 
 struct Stream {

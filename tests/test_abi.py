@@ -80,3 +80,20 @@ def test_server_argument_errors(lib):
     assert lib.server_info(None, None, None, None, None, None) == tt.TT_E_ARG
     assert lib.server_request_bytes(None, 10, 0) == 0
     lib.server_destroy(None)  # NULL-safe
+
+
+def test_batch_argument_errors(lib):
+    h = ctypes.c_void_p()
+    n = (ctypes.c_uint32 * 1)(3)
+    m = (ctypes.c_uint64 * 1)(2)
+    assert lib.batch_load(1, n, m, None, None, None, ctypes.byref(h)) == tt.TT_E_ARG
+    assert lib.batch_load(1, None, m, None, None, None, ctypes.byref(h)) == tt.TT_E_ARG
+    assert lib.batch_load(0, None, None, None, None, None, None) == tt.TT_E_ARG
+    big = (ctypes.c_uint32 * 2)(2**31, 2**31)
+    zero = (ctypes.c_uint64 * 2)(0, 0)
+    assert lib.batch_load(2, big, zero, None, None, None, ctypes.byref(h)) == tt.TT_E_TOO_LARGE
+    n_out = (ctypes.c_uint32 * 2)(5, 5)
+    assert lib.batch_topk(None, 10, 1.0, None, n_out) == tt.TT_E_ARG
+    assert lib.batch_topk_ex(None, 10, 1.0, -1, 0, None, n_out, None) == tt.TT_E_ARG
+    assert lib.batch_num_graphs(None) == 0 and lib.batch_num_configs() >= 2
+    lib.batch_free(None)  # NULL-safe
