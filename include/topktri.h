@@ -185,7 +185,9 @@ typedef struct {
     uint64_t candidate_edges, intersected_entries, triangles_emitted, edges_streamed;
     uint32_t config;           /* launch configuration used (index, see batch_topk_ex) */
     uint32_t growth;           /* rank ratio between consecutive score bands */
-    uint32_t filter_blocks, intersect_blocks, passes;
+    uint32_t filter_blocks, intersect_blocks;
+    uint32_t passes;           /* score bands captured (the last one exhaustive) */
+    uint32_t restart_rounds;   /* overflow restart rounds captured after the selection */
     uint32_t restarts;         /* graphs redone because their triangle region overflowed */
     double launch_ms;          /* device time of the captured sequence (HIP events) */
     double tune_ms;            /* host time spent by the autotuner in this call (first use) */
@@ -197,9 +199,10 @@ enum { TT_BATCH_EAGER = 1 }; /* run the launch sequence directly instead of its 
 /*
  * out: HOST, count*k triangles; graph g's top min(k, T_g) are out[g*k ...] in local ids,
  * sorted as topk_triangles sorts them; n_out: HOST, count values.  config = -1 uses the
- * autotuner's choice for this (k, p) (timed on first use over every configuration), or
- * 0 .. batch_num_configs()-1 forces one.  Every configuration and both launch modes return
- * exactly the same result.  Calls on one batch are serialised.
+ * autotuner's choice for this (k, p) (launch shape, number of bands and of captured restart
+ * rounds, timed on first use), or 0 .. batch_num_configs()-1 forces a launch shape with the
+ * full number of bands.  Every choice and both launch modes return exactly the same result.
+ * Calls on one batch are serialised.
  */
 int batch_topk_ex(tt_batch *b, uint32_t k, double p, int config, uint32_t flags, tt_triangle *out,
                   uint32_t *n_out, tt_batch_stats *stats);

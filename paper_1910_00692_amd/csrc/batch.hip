@@ -4,17 +4,19 @@
 // Layout.  The graphs are loaded as one disjoint union (vertex ids offset by voff[g]); the
 // degree orientation, the CSR and its weight-sorted row copies are those of the single-graph
 // path, since a triangle never spans two graphs and orientation only compares endpoints of
-// one edge.  On top of it every graph gets a weight-ordered segment of its entries, grouped
-// by 256 coarse weight bins (heaviest first) with the bin offsets kept per graph.
+// one edge.  For each p queried (the two latest are kept) every graph gets a segment of its
+// entries ordered by their bound m_p(w_uv, maxw(u), maxw(v)) (the heaviest triangle an entry
+// can be the base of, Sec. 3.2), grouped by 256 coarse bins, highest first, with the bin
+// offsets kept per graph.
 //
 // Query.  The threshold descent of the single-graph path runs for all graphs at once: pass i
-// gives graph g the band [L_{g,i}, L_{g,i-1}) with L_{g,i} = key(t, t, t), t = the weight of
-// the k*G^i-th heaviest edge of g, and streams only the prefix of g's segment whose weights can
-// still reach the band (weight floor of Sec. 3.2 with g's largest weight).  A graph drops out
-// as soon as it holds >= k triangles (the argument of Sec. 3.2: its top k are among them).
+// gives graph g the band [L_{g,i}, L_{g,i-1}) with L_{g,i} = key(t, t, t), t = the bound of
+// the k*G^i-th entry of g's segment, and streams exactly the prefix of the segment whose
+// bounds reach t (no other entry can be the base of a triangle in the band).  A graph drops
+// out as soon as it holds >= k triangles (the argument of Sec. 3.2: its top k are among them).
 // Triangles go to a region of R records per graph.  A graph whose region overflows is redone
 // above the k-th best full key it holds (a valid lower bound), outside the captured sequence.
-// The per-graph top-k is taken by rank counting in LDS.  The whole sequence (plan, scan,
+// The per-graph top-k is taken by block-wide selection rounds (small k) or rank counting.  The whole sequence (plan, scan,
 // filter, intersect per pass; selection) is captured once per (k, p, launch configuration)
 // into a hipGraph and replayed; an autotuner picks the configuration by timing replays.
 #include <chrono>
@@ -63,37 +65,41 @@ __global__ __launch_bounds__(256) void k_globalize(uint32_t *src, uint32_t *dst,
     }
 }
 
-// One block per graph: entries per coarse bin (bucket g*NB + NB-1-bin) and the largest weight.
-__global__ __launch_bounds__(256) void k_bcount(const uint64_t *voff, const uint64_t *rstart, const uint32_t *rlen,
-                                                const uint32_t *wgt, uint32_t *bcnt, uint32_t *gwmax) {
-    __shared__ uint32_t h[NB];
-    __shared__ uint32_t wmax;
-    const uint32_t g = blockIdx.x;
-    for (uint32_t t = threadIdx.x; t < NB; t += blockDim.x) h[t] = 0;
-    if (threadIdx.x == 0) wmax = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    uint32_t mx = 0;
-    for (uint64_t v = voff[g] + (threadIdx.x >> 6); v < voff[g + 1]; v += blockDim.x >> 6) {
-        const uint64_t b = rstart[v];
-        const uint32_t len = rlen[v];
-        for (uint32_t t = lane; t < len; t += 64) {
-            const uint32_t w = wgt[b + t];
-            mx = w > mx ? w : mx;
-            atomicAdd(&h[NB - 1 - coarse_bin(w)], 1u);
-        }
-    }
-    mx = wave_max(mx);
-    if (lane == 0) atomicMax(&wmax, mx);
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < NB; t += blockDim.x) bcnt[(uint64_t)g * NB + t] = h[t];
-    if (threadIdx.x == 0) gwmax[g] = wmax;
+// An integer >= the score of every triangle based at entry u->v (m_p of the entry's weight
+// and the two row maxima), at most the largest of the three.
+__device__ __forceinline__ uint32_t entry_bound(int mode, double p, uint32_t a, uint32_t Wu, uint32_t Wv) {
+    const uint32_t mx = max(a, max(Wu, Wv));
+    const double sc = key_to_score(mode, score_key(mode, p, a, Wu, Wv));
+    const double up = ceil(sc * (1.0 + 1e-9));
+    return up >= (double)mx ? mx : (uint32_t)up;
 }
 
-// One block per graph: scatter the graph's entries into its weight-ordered segment.
-__global__ __launch_bounds__(256) void k_bscatter(const uint64_t *voff, const uint64_t *rstart, const uint32_t *rlen,
-                                                  const uint32_t *col, const uint32_t *wgt, const uint64_t *boff,
-                                                  uint32_t *bs_src, uint32_t *bs_col, uint32_t *bs_wgt) {
+// One block per graph: entries per coarse bound bin (bucket g*NB + NB-1-bin).
+__global__ __launch_bounds__(256) void k_ocount(const uint64_t *voff, const uint64_t *rstart, const uint32_t *rlen,
+                                                const uint32_t *col, const uint32_t *wgt, const uint32_t *maxw,
+                                                int mode, double p, uint32_t *bcnt) {
+    __shared__ uint32_t h[NB];
+    const uint32_t g = blockIdx.x;
+    for (uint32_t t = threadIdx.x; t < NB; t += blockDim.x) h[t] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    for (uint64_t v = voff[g] + (threadIdx.x >> 6); v < voff[g + 1]; v += blockDim.x >> 6) {
+        const uint64_t b = rstart[v];
+        const uint32_t len = rlen[v], Wu = maxw[v];
+        for (uint32_t t = lane; t < len; t += 64) {
+            const uint32_t ub = entry_bound(mode, p, wgt[b + t], Wu, maxw[col[b + t]]);
+            atomicAdd(&h[NB - 1 - coarse_bin(ub)], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < NB; t += blockDim.x) bcnt[(uint64_t)g * NB + t] = h[t];
+}
+
+// One block per graph: scatter the graph's entries into its bound-ordered segment.
+__global__ __launch_bounds__(256) void k_oscatter(const uint64_t *voff, const uint64_t *rstart, const uint32_t *rlen,
+                                                  const uint32_t *col, const uint32_t *wgt, const uint32_t *maxw,
+                                                  int mode, double p, const uint64_t *boff, uint32_t *o_src,
+                                                  uint32_t *o_col, uint32_t *o_wgt) {
     __shared__ uint32_t cur[NB];
     const uint32_t g = blockIdx.x;
     for (uint32_t t = threadIdx.x; t < NB; t += blockDim.x) cur[t] = 0;
@@ -101,25 +107,25 @@ __global__ __launch_bounds__(256) void k_bscatter(const uint64_t *voff, const ui
     const int lane = threadIdx.x & 63;
     for (uint64_t v = voff[g] + (threadIdx.x >> 6); v < voff[g + 1]; v += blockDim.x >> 6) {
         const uint64_t b = rstart[v];
-        const uint32_t len = rlen[v];
+        const uint32_t len = rlen[v], Wu = maxw[v];
         for (uint32_t t = lane; t < len; t += 64) {
-            const uint32_t w = wgt[b + t];
-            const uint32_t j = NB - 1 - coarse_bin(w);
+            const uint32_t c = col[b + t], w = wgt[b + t];
+            const uint32_t j = NB - 1 - coarse_bin(entry_bound(mode, p, w, Wu, maxw[c]));
             const uint64_t d = boff[(uint64_t)g * NB + j] + atomicAdd(&cur[j], 1u);
-            bs_src[d] = (uint32_t)v;
-            bs_col[d] = col[b + t];
-            bs_wgt[d] = w;
+            o_src[d] = (uint32_t)v;
+            o_col[d] = c;
+            o_wgt[d] = w;
         }
     }
 }
 
 // ----------------------------------------------------------------------------- query kernels
 // Pass `pass` of the descent, one thread per graph: the graph's band and how many entries of
-// its segment to stream (0 once it holds >= k triangles or has had its exhaustive band).
+// its bound-ordered segment to stream (0 once it holds >= k triangles or has had its
+// exhaustive band).
 __global__ __launch_bounds__(256) void k_bplan(uint32_t pass, uint32_t count, uint32_t k, int mode, double p,
-                                               unsigned long long M, const uint64_t *boff, const uint64_t *gm,
-                                               const uint32_t *gwmax, unsigned long long *gcount, BState *st,
-                                               Band *bands, uint32_t *Eg) {
+                                               unsigned long long M, const uint64_t *boff,
+                                               unsigned long long *gcount, BState *st, Band *bands, uint32_t *Eg) {
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= count) return;
     BState S;
@@ -133,15 +139,21 @@ __global__ __launch_bounds__(256) void k_bplan(uint32_t pass, uint32_t count, ui
     uint32_t E = 0;
     if (gcount[g] < k && !(S.flags & ST_EXHAUSTED)) {
         const uint64_t *bo = boff + (uint64_t)g * NB;
+        const uint64_t all = bo[NB] - bo[0];
         u128 L = 0;
-        if (M < gm[g]) {
+        uint64_t En = all;
+        if (M < all) {
             uint32_t lo = 0, hi = NB - 1; // first bucket j with (entries in buckets 0..j) >= M
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
                 if (bo[mid + 1] - bo[0] >= M) hi = mid; else lo = mid + 1;
             }
+            // every triangle scoring >= t has its base entry's bound >= t, in buckets 0..lo
             const uint32_t t = weight_bin_low((NB - 1 - lo) << 3);
-            if (t > 1) L = key_of_uniform(mode, t);
+            if (t > 1) {
+                L = key_of_uniform(mode, t);
+                En = bo[lo + 1] - bo[0];
+            }
         }
         const bool has_prev = S.flags & ST_HAS_PREV;
         if (!has_prev || L < S.Lprev) {
@@ -154,45 +166,13 @@ __global__ __launch_bounds__(256) void k_bplan(uint32_t pass, uint32_t count, ui
             B.p = p;
             B.theta = mode == MODE_GEN ? key_as_double(L) : 0.0;
             bands[g] = B;
-            const uint64_t z = weight_floor(mode, p, L, gwmax[g]);
-            if (z == 0) E = (uint32_t)(bo[NB] - bo[0]);
-            else if (z <= 0xFFFFFFFFull) E = (uint32_t)(bo[NB - coarse_bin((uint32_t)z)] - bo[0]);
+            E = (uint32_t)En;
             S.Lprev = L;
             S.flags |= ST_HAS_PREV | (L == 0 ? ST_EXHAUSTED : 0);
         }
     }
     Eg[g] = E;
     st[g] = S;
-}
-
-// Restart of the listed graphs above the k-th best full key they hold (kth[g]); every other
-// graph streams nothing.
-__global__ __launch_bounds__(256) void k_brestart(uint32_t count, const uint8_t *redo, const trec *kth, int mode,
-                                                  double p, const uint64_t *boff, const uint32_t *gwmax,
-                                                  unsigned long long *gcount, Band *bands, uint32_t *Eg) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= count) return;
-    uint32_t E = 0;
-    if (redo[g]) {
-        const trec r = kth[g];
-        Band B;
-        B.L = ((u128)r.khi << 64) | r.klo;
-        B.Li = r.i;
-        B.Lj = r.j;
-        B.Ll = r.l;
-        B.U = 0;
-        B.hasU = 0;
-        B.mode = mode;
-        B.p = p;
-        B.theta = mode == MODE_GEN ? key_as_double(B.L) : 0.0;
-        bands[g] = B;
-        gcount[g] = 0;
-        const uint64_t *bo = boff + (uint64_t)g * NB;
-        const uint64_t z = weight_floor(mode, p, B.L, gwmax[g]);
-        if (z == 0) E = (uint32_t)(bo[NB] - bo[0]);
-        else if (z <= 0xFFFFFFFFull) E = (uint32_t)(bo[NB - coarse_bin((uint32_t)z)] - bo[0]);
-    }
-    Eg[g] = E;
 }
 
 // Exclusive prefix of Eg[0..count) into poff[0..count] (one block; count is a few thousand).
@@ -216,55 +196,268 @@ __global__ __launch_bounds__(1024) void k_bscan(const uint32_t *Eg, uint32_t cou
 }
 
 constexpr uint32_t SEL_TILE = 1024;
+constexpr uint32_t SEL_ROUNDS = 32; // up to this k, the thresholded selection
+constexpr uint32_t SEL_REG = 8;     // records per thread held in registers by it
 
-// Per-graph top-k by rank counting: a record's rank is the number of records of its graph
-// that are better under (key desc, i, j, l asc).  Writes the first min(k, N) triangles with
-// local ids, or marks the graph OVERFLOWED when its region overflowed.  With `kth` set, the
-// listed (overflowed) graphs instead report their record of rank k-1 among the R kept.
+__device__ __forceinline__ void put_result(const trec &me, uint32_t off, int mode, tt_triangle *dst) {
+    tt_triangle o;
+    o.i = me.i - off;
+    o.j = me.j - off;
+    o.l = me.l - off;
+    o._pad = 0;
+    o.score = key_to_score(mode, ((u128)me.khi << 64) | me.klo);
+    *dst = o;
+}
+
+// Lane src's record, broadcast to the whole wave (src is wave-uniform).
+__device__ __forceinline__ trec readlane_rec(const trec &r, int src) {
+    trec o;
+    o.khi = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(r.khi >> 32), src) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r.khi, src);
+    o.klo = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(r.klo >> 32), src) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)r.klo, src);
+    o.i = (uint32_t)__builtin_amdgcn_readlane((int)r.i, src);
+    o.j = (uint32_t)__builtin_amdgcn_readlane((int)r.j, src);
+    o.l = (uint32_t)__builtin_amdgcn_readlane((int)r.l, src);
+    o.pad = 0;
+    return o;
+}
+
+// Rank of each lane's `me` among the `v` of the lanes in `mask` (records better than it).
+__device__ __forceinline__ uint32_t wave_rank(const trec &me, const trec &v, uint64_t mask) {
+    uint32_t rank = 0;
+    while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        rank += better(readlane_rec(v, src), me) ? 1u : 0u;
+    }
+    return rank;
+}
+
+constexpr uint32_t WSEL_MAX = 64 * SEL_REG; // records a wave selects from
+
+// The best K (<= SEL_ROUNDS) of N (<= WSEL_MAX) records at `base`, by one wave, in registers
+// only.  N <= 64: every lane holds one record and ranks it against the others.  Otherwise the
+// K-th best of the 64 lane bests is a lower bound on the K-th best record, at most SEL_REG*K
+// records reach it, and only those are ranked.  Rank r goes to out[r] (ids minus off).
+__device__ __forceinline__ void wave_topk(const trec *base, uint32_t N, uint32_t K, uint32_t off, int mode,
+                                          tt_triangle *out) {
+    const uint32_t lane = threadIdx.x & 63;
+    if (N <= 64) {
+        const bool has = lane < N;
+        const trec me = has ? base[lane] : worst_rec();
+        const uint32_t rank = wave_rank(me, me, __ballot(has));
+        if (has && rank < K) put_result(me, off, mode, out + rank);
+        return;
+    }
+    trec loc[SEL_REG];
+    trec lb = worst_rec();
+#pragma unroll
+    for (uint32_t q = 0; q < SEL_REG; q++) {
+        const uint32_t idx = lane + q * 64;
+        loc[q] = idx < N ? base[idx] : worst_rec();
+        if (better(loc[q], lb)) lb = loc[q];
+    }
+    // every lane holds a record (N > 64); the lane best of rank K-1 is the bound
+    const uint32_t rb = wave_rank(lb, lb, ~0ull);
+    const int xl = __ffsll((unsigned long long)__ballot(rb == K - 1)) - 1;
+    const trec x = readlane_rec(lb, xl);
+    bool keep[SEL_REG];
+    uint32_t rank[SEL_REG];
+#pragma unroll
+    for (uint32_t q = 0; q < SEL_REG; q++) {
+        keep[q] = lane + q * 64 < N && !better(x, loc[q]);
+        rank[q] = 0;
+    }
+#pragma unroll
+    for (uint32_t q2 = 0; q2 < SEL_REG; q2++) {
+        uint64_t m = __ballot(keep[q2]);
+        while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const trec o = readlane_rec(loc[q2], src);
+#pragma unroll
+            for (uint32_t q = 0; q < SEL_REG; q++) rank[q] += better(o, loc[q]) ? 1u : 0u;
+        }
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < SEL_REG; q++)
+        if (keep[q] && rank[q] < K) put_result(loc[q], off, mode, out + rank[q]);
+}
+
+union SelShared {
+    struct {
+        trec wtop[4][SEL_ROUNDS];        // each wave's best K per-thread bests
+        trec cand[SEL_REG * SEL_ROUNDS]; // records at or above the threshold
+        trec x;
+        uint32_t ccount;
+    } small;
+    trec tile[SEL_TILE];
+};
+
+// The best K of the N records at `base` under (key desc, i, j, l asc), by one block of 256
+// threads.  Small K with N <= 256*SEL_REG: every thread holds its records in registers; the
+// K-th best of the 256 per-thread bests (found from each wave's best K) is a lower bound on
+// the K-th best record (K real records reach it), and at most SEL_REG*K records reach that
+// bound (only threads whose best does), so ranks are counted among those alone.  Otherwise
+// rank counting over all N records.  Rank r goes to out[r] (local ids, ids minus off) if out
+// is set; the record of rank K-1 to *kth if kth is set.
+__device__ __forceinline__ void block_topk(const trec *base, uint32_t N, uint32_t K, uint32_t off, int mode,
+                                           tt_triangle *out, trec *kth, SelShared &sh) {
+    const uint32_t tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    if (K == 0) return;
+    if (K <= SEL_ROUNDS && N <= SEL_REG * 256) {
+        trec loc[SEL_REG];
+        trec v = worst_rec();
+#pragma unroll
+        for (uint32_t q = 0; q < SEL_REG; q++) {
+            const uint32_t idx = tid + q * 256;
+            loc[q] = idx < N ? base[idx] : worst_rec();
+            if (better(loc[q], v)) v = loc[q];
+        }
+        const bool has = tid < N;
+        const uint32_t rw = wave_rank(v, v, __ballot(has));
+        if (has && rw < K) sh.small.wtop[wv][rw] = v;
+        if (!has && (uint32_t)lane < K) sh.small.wtop[wv][lane] = worst_rec(); // ranks of real lanes come first
+        if (tid == 0) sh.small.ccount = 0;
+        __syncthreads();
+        const uint32_t nreal = N < 256 ? N : 256; // threads holding at least one record
+        const uint32_t Kp = K < nreal ? K : nreal;
+        if (tid < 4 * K) {
+            const trec me = sh.small.wtop[tid / K][tid % K];
+            if (better(me, worst_rec())) {
+                uint32_t rank = 0;
+                for (uint32_t t = 0; t < 4 * K; t++) rank += better(sh.small.wtop[t / K][t % K], me) ? 1u : 0u;
+                if (rank == Kp - 1) sh.small.x = me;
+            }
+        }
+        __syncthreads();
+        const trec x = sh.small.x;
+#pragma unroll
+        for (uint32_t q = 0; q < SEL_REG; q++) {
+            if (tid + q * 256 < N && !better(x, loc[q])) {
+                const uint32_t slot = atomicAdd(&sh.small.ccount, 1u);
+                sh.small.cand[slot] = loc[q];
+            }
+        }
+        __syncthreads();
+        const uint32_t C = sh.small.ccount;
+        for (uint32_t t = tid; t < C; t += 256) {
+            const trec me = sh.small.cand[t];
+            uint32_t rank = 0;
+            for (uint32_t u = 0; u < C; u++) rank += better(sh.small.cand[u], me) ? 1u : 0u;
+            if (rank < K) {
+                if (out) put_result(me, off, mode, out + rank);
+                if (kth && rank == K - 1) *kth = me;
+            }
+        }
+        __syncthreads();
+        return;
+    }
+    for (uint32_t r0 = 0; r0 < N; r0 += blockDim.x) {
+        const uint32_t idx = r0 + tid;
+        const bool has = idx < N;
+        trec me;
+        if (has) me = base[idx];
+        uint32_t rank = 0;
+        for (uint32_t t0 = 0; t0 < N; t0 += SEL_TILE) {
+            const uint32_t cover = N - t0 < SEL_TILE ? N - t0 : SEL_TILE;
+            __syncthreads();
+            for (uint32_t t = tid; t < cover; t += blockDim.x) sh.tile[t] = base[t0 + t];
+            __syncthreads();
+            if (has)
+                for (uint32_t t = 0; t < cover; t++) rank += better(sh.tile[t], me) ? 1u : 0u;
+        }
+        if (has && rank < K) {
+            if (out) put_result(me, off, mode, out + rank);
+            if (kth && rank == K - 1) *kth = me;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool wave_selects(uint32_t N, uint32_t K) { return K <= SEL_ROUNDS && N <= WSEL_MAX; }
+
+// Per-graph top-k of the triangles held (graphs with only[g] == 0 skipped when `only` is set),
+// one wave per graph: the first min(k, N) triangles with local ids, or n_out[g] = OVERFLOWED
+// when the graph's region overflowed.  Graphs with more records than a wave selects from are
+// left to k_bselect_big.
 __global__ __launch_bounds__(256) void k_bselect(const trec *rec, uint32_t R, const unsigned long long *gcount,
                                                  const uint8_t *only, uint32_t count, uint32_t k, int mode,
-                                                 const uint64_t *voff, tt_triangle *out, uint32_t *n_out, trec *kth) {
-    __shared__ trec tile[SEL_TILE];
+                                                 const uint64_t *voff, tt_triangle *out, uint32_t *n_out) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t g = wave; g < count; g += nwaves) {
+        if (only && !only[g]) continue;
+        const unsigned long long cnt = gcount[g];
+        if (cnt > R) {
+            if (lane == 0) n_out[g] = OVERFLOWED;
+            continue;
+        }
+        const uint32_t N = (uint32_t)cnt, K = N < k ? N : k;
+        if (!wave_selects(N, K)) continue;
+        if (K) wave_topk(rec + (uint64_t)g * R, N, K, (uint32_t)voff[g], mode, out + (uint64_t)g * k);
+        if (lane == 0) n_out[g] = K;
+    }
+}
+
+// The graphs k_bselect leaves: one block per graph.
+__global__ __launch_bounds__(256) void k_bselect_big(const trec *rec, uint32_t R, const unsigned long long *gcount,
+                                                     const uint8_t *only, uint32_t count, uint32_t k, int mode,
+                                                     const uint64_t *voff, tt_triangle *out, uint32_t *n_out) {
+    __shared__ SelShared sh;
     for (uint32_t g = blockIdx.x; g < count; g += gridDim.x) {
         if (only && !only[g]) continue;
         const unsigned long long cnt = gcount[g];
-        if (!kth && cnt > R) {
-            if (threadIdx.x == 0) n_out[g] = OVERFLOWED;
+        if (cnt > R) continue;
+        const uint32_t N = (uint32_t)cnt, K = N < k ? N : k;
+        if (wave_selects(N, K)) continue;
+        block_topk(rec + (uint64_t)g * R, N, K, (uint32_t)voff[g], mode, out + (uint64_t)g * k, nullptr, sh);
+        if (threadIdx.x == 0) n_out[g] = K;
+    }
+}
+
+// One restart round, per graph: a graph whose region overflowed (gcount > R) is redone above
+// the k-th best full key among the R records it kept (a valid lower bound on its k-th best
+// triangle): band [that key, +inf), streaming the segment entries whose bound reaches the
+// key's score floor; redo[g] = 1.  Every other graph streams nothing (redo[g] = 0).
+__global__ __launch_bounds__(256) void k_brestart(const trec *rec, uint32_t R, unsigned long long *gcount,
+                                                  uint32_t count, uint32_t k, int mode, double p,
+                                                  const uint64_t *boff, Band *bands, uint32_t *Eg, uint8_t *redo,
+                                                  unsigned long long *stats) {
+    __shared__ SelShared sh;
+    __shared__ trec kth;
+    for (uint32_t g = blockIdx.x; g < count; g += gridDim.x) {
+        const unsigned long long cnt = gcount[g];
+        if (cnt <= R) {
+            if (threadIdx.x == 0) {
+                Eg[g] = 0;
+                redo[g] = 0;
+            }
             continue;
         }
-        const uint32_t N = (uint32_t)(cnt < R ? cnt : R);
-        const uint32_t K = N < k ? N : k;
-        const trec *base = rec + (uint64_t)g * R;
-        const uint32_t off = (uint32_t)voff[g];
-        for (uint32_t r0 = 0; r0 < N; r0 += blockDim.x) {
-            const uint32_t idx = r0 + threadIdx.x;
-            const bool has = idx < N;
-            trec me;
-            if (has) me = base[idx];
-            uint32_t rank = 0;
-            for (uint32_t t0 = 0; t0 < N; t0 += SEL_TILE) {
-                const uint32_t cover = N - t0 < SEL_TILE ? N - t0 : SEL_TILE;
-                __syncthreads();
-                for (uint32_t t = threadIdx.x; t < cover; t += blockDim.x) tile[t] = base[t0 + t];
-                __syncthreads();
-                if (has)
-                    for (uint32_t t = 0; t < cover; t++) rank += better(tile[t], me) ? 1u : 0u;
-            }
-            if (has && rank < K) {
-                if (kth) {
-                    if (rank == K - 1) kth[g] = me;
-                } else {
-                    tt_triangle o;
-                    o.i = me.i - off;
-                    o.j = me.j - off;
-                    o.l = me.l - off;
-                    o._pad = 0;
-                    o.score = key_to_score(mode, ((u128)me.khi << 64) | me.klo);
-                    out[(uint64_t)g * k + rank] = o;
-                }
-            }
+        block_topk(rec + (uint64_t)g * R, R, k, 0, mode, nullptr, &kth, sh);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Band B;
+            B.L = ((u128)kth.khi << 64) | kth.klo;
+            B.Li = kth.i;
+            B.Lj = kth.j;
+            B.Ll = kth.l;
+            B.U = 0;
+            B.hasU = 0;
+            B.mode = mode;
+            B.p = p;
+            B.theta = mode == MODE_GEN ? key_as_double(B.L) : 0.0;
+            bands[g] = B;
+            const uint64_t *bo = boff + (uint64_t)g * NB;
+            const uint64_t f = score_floor(mode, B.L); // base entries of the band have bound >= f
+            Eg[g] = f <= 0xFFFFFFFFull ? (uint32_t)(bo[NB - coarse_bin((uint32_t)f)] - bo[0]) : 0u;
+            gcount[g] = 0;
+            redo[g] = 1;
+            stat_add(stats, 5, 1); // counter 5: graphs restarted
         }
-        if (!kth && threadIdx.x == 0) n_out[g] = K;
         __syncthreads();
     }
 }
@@ -280,6 +473,14 @@ const BatchCfg CONFIGS[] = {
     {16, 4, 4}, {16, 4, 8}, {16, 4, 16}, {16, 16, 4}, {16, 16, 8}, {16, 16, 16},
 };
 constexpr int NCONFIGS = (int)(sizeof(CONFIGS) / sizeof(CONFIGS[0]));
+constexpr uint32_t IN_GRAPH_RESTARTS = 2; // default restart rounds inside the captured sequence
+
+// A launch choice: configuration, number of passes (the last one exhaustive) and restart
+// rounds captured after the selection.
+struct Choice {
+    int ci;
+    uint32_t passes, rounds;
+};
 
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -294,10 +495,15 @@ struct tt_batch {
     std::vector<uint64_t> voff_h;
     uint64_t *voff = nullptr; // [count+1]
     uint64_t *gm = nullptr;   // [count] edges per graph
-    uint32_t *gwmax = nullptr;
-    uint64_t *boff = nullptr; // [count*NB+1]
-    uint64_t *goff = nullptr; // [count+1] start of graph g's segment (= boff[g*NB])
-    uint32_t *bs_src = nullptr, *bs_col = nullptr, *bs_wgt = nullptr;
+    // bound-ordered segments for the two most recent p
+    struct Order {
+        bool valid = false;
+        uint64_t pb = 0, last_use = 0;
+        uint64_t *boff = nullptr; // [count*NB+1] exclusive prefix of bucket sizes
+        uint64_t *goff = nullptr; // [count+1] start of graph g's segment (= boff[g*NB])
+        uint32_t *src = nullptr, *col = nullptr, *wgt = nullptr;
+    } ord[2];
+    uint64_t clock = 0;
     hipStream_t stream = nullptr;
     bool owns_stream = false;
     // query state (sized for the largest k seen)
@@ -307,22 +513,23 @@ struct tt_batch {
     uint32_t *Eg = nullptr;
     uint64_t *poff = nullptr;
     unsigned long long *gcount = nullptr;
-    trec *rec = nullptr, *kth = nullptr;
+    trec *rec = nullptr;
     cand *C = nullptr;
     uint32_t *ccnt = nullptr;
     unsigned long long *spart = nullptr, *dstat = nullptr;
     tt_triangle *dout = nullptr;
     uint32_t *dn = nullptr;
     uint8_t *redo = nullptr;
-    unsigned long long extra[5] = {}; // counters of the restart passes of the latest query
+    unsigned long long extra[6] = {}; // counters of the host-driven restart rounds of the latest query
     hipEvent_t ev[2] = {};
     struct Plan {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         uint32_t passes = 0;
     };
-    std::map<std::tuple<uint32_t, uint64_t, int>, Plan> plans; // (k, bits of p, config)
-    std::map<std::pair<uint32_t, uint64_t>, int> tuned;        // (k, bits of p) -> config
+    // (k, bits of p, config, passes, restart rounds) -> captured sequence
+    std::map<std::tuple<uint32_t, uint64_t, int, uint32_t, uint32_t>, Plan> plans;
+    std::map<std::pair<uint32_t, uint64_t>, Choice> tuned; // (k, bits of p) -> autotuned choice
     std::mutex mu;
 };
 
@@ -335,11 +542,11 @@ uint64_t p_bits(double p) {
 }
 
 void free_query_state(tt_batch *b) {
-    void *ptrs[] = {b->bands, b->st, b->Eg, b->poff, b->gcount, b->rec, b->kth, b->C, b->ccnt,
+    void *ptrs[] = {b->bands, b->st, b->Eg, b->poff, b->gcount, b->rec, b->C, b->ccnt,
                     b->spart, b->dstat, b->dout, b->dn, b->redo};
     for (void *p : ptrs) dev_free(nullptr, p, 0);
     b->bands = nullptr; b->st = nullptr; b->Eg = nullptr; b->poff = nullptr; b->gcount = nullptr;
-    b->rec = b->kth = nullptr; b->C = nullptr; b->ccnt = nullptr; b->spart = b->dstat = nullptr;
+    b->rec = nullptr; b->C = nullptr; b->ccnt = nullptr; b->spart = b->dstat = nullptr;
     b->dout = nullptr; b->dn = nullptr; b->redo = nullptr;
     b->R = b->kcap = 0;
 }
@@ -367,10 +574,9 @@ int ensure_query_state(tt_batch *b, uint32_t k) {
         (rc = dev_alloc(nullptr, (void **)&b->poff, (n + 1) * 8)) ||
         (rc = dev_alloc(nullptr, (void **)&b->gcount, n * 8)) ||
         (rc = dev_alloc(nullptr, (void **)&b->rec, n * R * sizeof(trec))) ||
-        (rc = dev_alloc(nullptr, (void **)&b->kth, n * sizeof(trec))) ||
         (rc = dev_alloc(nullptr, (void **)&b->C, (m + 1) * sizeof(cand))) ||
         (rc = dev_alloc(nullptr, (void **)&b->ccnt, MAX_SEG * 4)) ||
-        (rc = dev_alloc(nullptr, (void **)&b->spart, 5 * STAT_SLOTS * 8)) ||
+        (rc = dev_alloc(nullptr, (void **)&b->spart, 6 * STAT_SLOTS * 8)) ||
         (rc = dev_alloc(nullptr, (void **)&b->dstat, 16 * 8)) ||
         (rc = dev_alloc(nullptr, (void **)&b->dout, n * k * sizeof(tt_triangle) + 8)) ||
         (rc = dev_alloc(nullptr, (void **)&b->dn, n * 4)) ||
@@ -378,7 +584,7 @@ int ensure_query_state(tt_batch *b, uint32_t k) {
         free_query_state(b);
         return rc;
     }
-    HIP_TRY(hipMemsetAsync(b->spart, 0, 5 * STAT_SLOTS * 8, b->stream));
+    HIP_TRY(hipMemsetAsync(b->spart, 0, 6 * STAT_SLOTS * 8, b->stream));
     HIP_TRY(hipMemsetAsync(b->ccnt, 0, MAX_SEG * 4, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->R = R;
@@ -392,7 +598,7 @@ uint32_t passes_for(const tt_batch *b, uint32_t k, uint32_t growth) {
     return P;
 }
 
-EnumArgs batch_args(const tt_batch *b, uint32_t k, double p, const BatchCfg &c) {
+EnumArgs batch_args(const tt_batch *b, const tt_batch::Order &o, double p, const BatchCfg &c) {
     const tt_graph *g = b->g;
     EnumArgs A;
     std::memset(&A, 0, sizeof(A));
@@ -404,9 +610,9 @@ EnumArgs batch_args(const tt_batch *b, uint32_t k, double p, const BatchCfg &c) 
     A.wwgt = g->wwgt;
     A.wpos = g->wpos;
     A.maxw = g->maxw;
-    A.s_src = b->bs_src;
-    A.s_col = b->bs_col;
-    A.s_wgt = b->bs_wgt;
+    A.s_src = o.src;
+    A.s_col = o.col;
+    A.s_wgt = o.wgt;
     A.B.mode = mode_of(p);
     A.B.p = p;
     A.out = b->rec;
@@ -416,11 +622,10 @@ EnumArgs batch_args(const tt_batch *b, uint32_t k, double p, const BatchCfg &c) 
     A.nseg = std::min<uint32_t>((uint32_t)num_cus() * c.filter_mul, MAX_SEG);
     A.bands = b->bands;
     A.poff = b->poff;
-    A.goff = b->boff; // graph g's segment starts at bucket g*NB: goff[g] = boff[g*NB] (stride NB)
+    A.goff = o.goff;
     A.ng = b->count;
     A.gcount = b->gcount;
     A.R = b->R;
-    (void)k;
     return A;
 }
 
@@ -439,28 +644,54 @@ int enqueue_pass(tt_batch *b, const EnumArgs &A, const BatchCfg &c) {
     return TT_OK;
 }
 
-// The launch sequence of one query: every pass of the descent, then the per-graph selection
-// and the counters.  Nothing in it allocates, copies or sets memory, so it can be captured.
-int enqueue_query(tt_batch *b, uint32_t k, double p, const BatchCfg &c, const uint64_t *goff) {
+unsigned sel_grid(const tt_batch *b) { return std::min<unsigned>(b->count, (unsigned)num_cus() * 8); }
+
+// Per-graph selection: a wave per graph, then a block per graph for the few with many records.
+void enqueue_select(tt_batch *b, uint32_t k, int mode, const uint8_t *only) {
+    hipStream_t s = b->stream;
+    k_bselect<<<(b->count + 3) / 4, 256, 0, s>>>(b->rec, b->R, b->gcount, only, b->count, k, mode, b->voff, b->dout,
+                                                  b->dn);
+    k_bselect_big<<<sel_grid(b), 256, 0, s>>>(b->rec, b->R, b->gcount, only, b->count, k, mode, b->voff, b->dout,
+                                              b->dn);
+}
+
+int enqueue_restart_round(tt_batch *b, const EnumArgs &A, const BatchCfg &c, uint32_t k, double p,
+                          const tt_batch::Order &o) {
     hipStream_t s = b->stream;
     const int mode = mode_of(p);
-    EnumArgs A = batch_args(b, k, p, c);
-    A.goff = goff;
-    const uint32_t P = passes_for(b, k, c.growth);
+    k_brestart<<<sel_grid(b), 256, 0, s>>>(b->rec, b->R, b->gcount, b->count, k, mode, p, o.boff, b->bands, b->Eg,
+                                           b->redo, b->spart);
+    int rc = enqueue_pass(b, A, c);
+    if (rc) return rc;
+    enqueue_select(b, k, mode, b->redo);
+    HIP_TRY(hipGetLastError());
+    return TT_OK;
+}
+
+// The launch sequence of one query: every pass of the descent, then the per-graph selection
+// and the counters.  Nothing in it allocates, copies or sets memory, so it can be captured.
+int enqueue_query(tt_batch *b, const tt_batch::Order &o, uint32_t k, double p, const BatchCfg &c, uint32_t P,
+                  uint32_t rounds) {
+    hipStream_t s = b->stream;
+    const int mode = mode_of(p);
+    EnumArgs A = batch_args(b, o, p, c);
     const unsigned pg = (b->count + 255) / 256;
     unsigned long long M = k;
     for (uint32_t i = 0; i < P; i++) {
         const unsigned long long Mi = i + 1 == P ? ~0ull : M; // the last band is exhaustive
-        k_bplan<<<pg, 256, 0, s>>>(i, b->count, k, mode, p, Mi, b->boff, b->gm, b->gwmax, b->gcount, b->st,
-                                   b->bands, b->Eg);
+        k_bplan<<<pg, 256, 0, s>>>(i, b->count, k, mode, p, Mi, o.boff, b->gcount, b->st, b->bands, b->Eg);
         int rc = enqueue_pass(b, A, c);
         if (rc) return rc;
         M = M > (~0ull / c.growth) ? ~0ull : M * c.growth;
     }
-    const unsigned sg = std::min<unsigned>(b->count, (unsigned)num_cus() * 8);
-    k_bselect<<<sg, 256, 0, s>>>(b->rec, b->R, b->gcount, nullptr, b->count, k, mode, b->voff, b->dout, b->dn,
-                                 nullptr);
-    k_reduce_stats<<<5, 256, 0, s>>>(b->spart, b->dstat);
+    enqueue_select(b, k, mode, nullptr);
+    // restart rounds decided on the device: graphs whose region overflowed are redone above the
+    // k-th best key they hold; a round with nothing to redo streams nothing
+    for (uint32_t round = 0; round < rounds; round++) {
+        int rc = enqueue_restart_round(b, A, c, k, p, o);
+        if (rc) return rc;
+    }
+    k_reduce_stats<<<6, 256, 0, s>>>(b->spart, b->dstat);
     HIP_TRY(hipGetLastError());
     return TT_OK;
 }
@@ -511,8 +742,7 @@ int batch_load_common(uint32_t count, const uint32_t *n, const uint64_t *m, cons
             (rc = dev_alloc(nullptr, (void **)&eoff_d, (count + 1) * 8)) ||
             (rc = dev_alloc(nullptr, (void **)&bad, 8)) ||
             (rc = dev_alloc(nullptr, (void **)&b->voff, (count + 1) * 8)) ||
-            (rc = dev_alloc(nullptr, (void **)&b->gm, (count + 1) * 8)) ||
-            (rc = dev_alloc(nullptr, (void **)&b->gwmax, (count + 1) * 4)))
+            (rc = dev_alloc(nullptr, (void **)&b->gm, (count + 1) * 8)))
             return rc;
         const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
         if (M) {
@@ -535,37 +765,6 @@ int batch_load_common(uint32_t count, const uint32_t *n, const uint64_t *m, cons
         HIP_TRY(hipStreamSynchronize(s));
         if (hb[0]) return fail(TT_E_VERTEX_RANGE, "graph " + std::to_string(hb[1]) + ": vertex id >= its n");
         if ((rc = graph_load_device((uint32_t)N, M, us, us + M, us + 2 * M, s, &b->g))) return rc;
-        // per-graph weight-ordered segments
-        const uint64_t nb = (uint64_t)count * NB + 1;
-        uint32_t *bcnt = nullptr;
-        if ((rc = dev_alloc(nullptr, (void **)&bcnt, nb * 4)) ||
-            (rc = dev_alloc(nullptr, (void **)&b->boff, nb * 8)) ||
-            (rc = dev_alloc(nullptr, (void **)&b->goff, ((uint64_t)count + 1) * 8)) ||
-            (rc = dev_alloc(nullptr, (void **)&b->bs_src, (M + 1) * 4)) ||
-            (rc = dev_alloc(nullptr, (void **)&b->bs_col, (M + 1) * 4)) ||
-            (rc = dev_alloc(nullptr, (void **)&b->bs_wgt, (M + 1) * 4))) {
-            dev_free(nullptr, bcnt, 0);
-            return rc;
-        }
-        HIP_TRY(hipMemsetAsync(bcnt, 0, nb * 4, s));
-        if (count) {
-            k_bcount<<<count, 256, 0, s>>>(b->voff, b->g->rstart, b->g->rlen, b->g->wgt, bcnt, b->gwmax);
-            HIP_TRY(hipGetLastError());
-        }
-        rc = exclusive_scan_u32_to_u64(bcnt, b->boff, nb, s, nullptr);
-        if (!rc && count) {
-            k_bscatter<<<count, 256, 0, s>>>(b->voff, b->g->rstart, b->g->rlen, b->g->col, b->g->wgt, b->boff,
-                                             b->bs_src, b->bs_col, b->bs_wgt);
-            HIP_TRY(hipGetLastError());
-        }
-        if (!rc && count) {
-            HIP_TRY(hipMemsetAsync(b->goff, 0, ((uint64_t)count + 1) * 8, s));
-            k_goff<<<(count + 255) / 256, 256, 0, s>>>(b->boff, count, b->goff);
-            HIP_TRY(hipGetLastError());
-        }
-        (void)hipStreamSynchronize(s);
-        dev_free(nullptr, bcnt, 0);
-        if (rc) return rc;
         HIP_TRY(hipEventCreate(&b->ev[0]));
         HIP_TRY(hipEventCreate(&b->ev[1]));
         return TT_OK;
@@ -584,23 +783,86 @@ int batch_load_common(uint32_t count, const uint32_t *n, const uint64_t *m, cons
     return TT_OK;
 }
 
+// The bound-ordered segments for p (built on first use, the two most recent p kept).  Plans
+// captured for the p whose segments are replaced are dropped with them.
+int ensure_order(tt_batch *b, double p, const tt_batch::Order **out) {
+    const uint64_t pb = p_bits(p);
+    b->clock++;
+    for (auto &o : b->ord)
+        if (o.valid && o.pb == pb) {
+            o.last_use = b->clock;
+            *out = &o;
+            return TT_OK;
+        }
+    tt_batch::Order &o = b->ord[0].last_use <= b->ord[1].last_use ? b->ord[0] : b->ord[1];
+    if (o.valid) {
+        for (auto it = b->plans.begin(); it != b->plans.end();) {
+            if (std::get<1>(it->first) == o.pb) {
+                (void)hipGraphExecDestroy(it->second.exec);
+                (void)hipGraphDestroy(it->second.graph);
+                it = b->plans.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    o.valid = false;
+    const uint64_t count = b->count, M = b->g->m, nb = count * NB + 1;
+    int rc;
+    if (!o.src && ((rc = dev_alloc(nullptr, (void **)&o.boff, nb * 8)) ||
+                   (rc = dev_alloc(nullptr, (void **)&o.goff, (count + 1) * 8)) ||
+                   (rc = dev_alloc(nullptr, (void **)&o.src, (M + 1) * 4)) ||
+                   (rc = dev_alloc(nullptr, (void **)&o.col, (M + 1) * 4)) ||
+                   (rc = dev_alloc(nullptr, (void **)&o.wgt, (M + 1) * 4))))
+        return rc;
+    hipStream_t s = b->stream;
+    uint32_t *bcnt = nullptr;
+    if ((rc = dev_alloc(nullptr, (void **)&bcnt, nb * 4))) return rc;
+    const tt_graph *g = b->g;
+    const int mode = mode_of(p);
+    auto body = [&]() -> int {
+        HIP_TRY(hipMemsetAsync(bcnt, 0, nb * 4, s));
+        HIP_TRY(hipMemsetAsync(o.goff, 0, (count + 1) * 8, s));
+        k_ocount<<<(unsigned)count, 256, 0, s>>>(b->voff, g->rstart, g->rlen, g->col, g->wgt, g->maxw, mode, p, bcnt);
+        HIP_TRY(hipGetLastError());
+        int r2 = exclusive_scan_u32_to_u64(bcnt, o.boff, nb, s, nullptr);
+        if (r2) return r2;
+        k_oscatter<<<(unsigned)count, 256, 0, s>>>(b->voff, g->rstart, g->rlen, g->col, g->wgt, g->maxw, mode, p,
+                                                  o.boff, o.src, o.col, o.wgt);
+        k_goff<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(o.boff, (uint32_t)count, o.goff);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+        return TT_OK;
+    };
+    rc = body();
+    (void)hipStreamSynchronize(s);
+    dev_free(nullptr, bcnt, 0);
+    if (rc) return rc;
+    o.valid = true;
+    o.pb = pb;
+    o.last_use = b->clock;
+    *out = &o;
+    return TT_OK;
+}
+
 // Runs one query with configuration c: replays (or first captures) its plan, or enqueues it
 // directly when `eager`; then redoes overflowed graphs.  Results stay in b->dout / b->dn.
-int run_batch(tt_batch *b, uint32_t k, double p, int ci, bool eager, uint32_t *restarts, double *ms) {
-    const BatchCfg &c = CONFIGS[ci];
+int run_batch(tt_batch *b, uint32_t k, double p, const Choice &ch, bool eager, double *ms) {
+    const BatchCfg &c = CONFIGS[ch.ci];
     hipStream_t s = b->stream;
-    uint64_t *goff = b->goff;
+    const tt_batch::Order *o = nullptr;
     int rc;
+    if ((rc = ensure_order(b, p, &o))) return rc;
     HIP_TRY(hipEventRecord(b->ev[0], s));
     if (eager) {
-        if ((rc = enqueue_query(b, k, p, c, goff))) return rc;
+        if ((rc = enqueue_query(b, *o, k, p, c, ch.passes, ch.rounds))) return rc;
     } else {
-        auto key = std::make_tuple(k, p_bits(p), ci);
+        auto key = std::make_tuple(k, p_bits(p), ch.ci, ch.passes, ch.rounds);
         auto it = b->plans.find(key);
         if (it == b->plans.end()) {
             tt_batch::Plan pl;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            rc = enqueue_query(b, k, p, c, goff);
+            rc = enqueue_query(b, *o, k, p, c, ch.passes, ch.rounds);
             hipGraph_t graph = nullptr;
             const hipError_t e = hipStreamEndCapture(s, &graph);
             if (rc) {
@@ -610,7 +872,7 @@ int run_batch(tt_batch *b, uint32_t k, double p, int ci, bool eager, uint32_t *r
             if (e != hipSuccess) return fail(TT_E_DEVICE, std::string("stream capture: ") + hipGetErrorString(e));
             pl.graph = graph;
             HIP_TRY(hipGraphInstantiate(&pl.exec, graph, nullptr, nullptr, 0));
-            pl.passes = passes_for(b, k, c.growth);
+            pl.passes = ch.passes;
             it = b->plans.emplace(key, pl).first;
         }
         HIP_TRY(hipGraphLaunch(it->second.exec, s));
@@ -626,54 +888,66 @@ int run_batch(tt_batch *b, uint32_t k, double p, int ci, bool eager, uint32_t *r
         *ms = f;
     }
     // graphs whose region overflowed: redo above the k-th best key they hold
-    const int mode = mode_of(p);
-    EnumArgs A = batch_args(b, k, p, c);
-    A.goff = goff;
-    const unsigned pg = (b->count + 255) / 256;
+    EnumArgs A = batch_args(b, *o, p, c);
     for (int round = 0; round < 64; round++) {
-        std::vector<uint8_t> redo(b->count + 1, 0);
-        uint32_t nredo = 0;
-        for (uint32_t g = 0; g < b->count; g++)
-            if (hn[g] == OVERFLOWED) { redo[g] = 1; nredo++; }
-        if (!nredo) return TT_OK;
-        if (restarts) *restarts += nredo;
-        HIP_TRY(hipMemcpyAsync(b->redo, redo.data(), b->count + 1, hipMemcpyHostToDevice, s));
-        const unsigned sg = std::min<unsigned>(b->count, (unsigned)num_cus() * 8);
-        k_bselect<<<sg, 256, 0, s>>>(b->rec, b->R, b->gcount, b->redo, b->count, k, mode, b->voff, nullptr, nullptr,
-                                     b->kth);
-        k_brestart<<<pg, 256, 0, s>>>(b->count, b->redo, b->kth, mode, p, b->boff, b->gwmax, b->gcount, b->bands,
-                                      b->Eg);
-        if ((rc = enqueue_pass(b, A, c))) return rc;
-        k_bselect<<<sg, 256, 0, s>>>(b->rec, b->R, b->gcount, b->redo, b->count, k, mode, b->voff, b->dout, b->dn,
-                                     nullptr);
-        k_reduce_stats<<<5, 256, 0, s>>>(b->spart, b->dstat + 8);
+        bool any = false;
+        for (uint32_t g = 0; g < b->count && !any; g++) any = hn[g] == OVERFLOWED;
+        if (!any) return TT_OK;
+        if ((rc = enqueue_restart_round(b, A, c, k, p, *o))) return rc;
+        k_reduce_stats<<<6, 256, 0, s>>>(b->spart, b->dstat + 8);
         HIP_TRY(hipGetLastError());
-        unsigned long long st[5];
+        unsigned long long st[6];
         HIP_TRY(hipMemcpyAsync(hn.data(), b->dn, (uint64_t)b->count * 4, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(st, b->dstat + 8, sizeof(st), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        for (int c2 = 0; c2 < 5; c2++) b->extra[c2] += st[c2];
+        for (int c2 = 0; c2 < 6; c2++) b->extra[c2] += st[c2];
     }
     return fail(TT_E_DEVICE, "batched query: overflow restarts did not converge");
 }
 
-int autotune(tt_batch *b, uint32_t k, double p, int *best, double *tune_ms) {
+// Mean device time of a few replays of choice ch (after one capture / warm-up run).
+int time_choice(tt_batch *b, uint32_t k, double p, const Choice &ch, double *out) {
+    double ms = 0, tot = 0;
+    int rc = run_batch(b, k, p, ch, false, &ms);
+    if (rc) return rc;
+    for (int r = 0; r < 3; r++) {
+        if ((rc = run_batch(b, k, p, ch, false, &ms))) return rc;
+        tot += ms;
+    }
+    *out = tot / 3;
+    return TT_OK;
+}
+
+// Picks, by timing replays: the launch configuration (all passes, default restart rounds),
+// then the number of passes (fewer passes make the exhaustive last one larger), then the
+// number of restart rounds captured (rounds not captured run from the host when needed).
+// Every choice returns the same result.
+int autotune(tt_batch *b, uint32_t k, double p, Choice *best, double *tune_ms) {
     const double t0 = now_ms();
-    double best_ms = 1e300;
-    int bi = 0;
+    double best_ms = 1e300, ms = 0;
+    Choice bc{0, 0, IN_GRAPH_RESTARTS};
+    int rc;
     for (int ci = 0; ci < NCONFIGS; ci++) {
-        double ms = 0, tot = 0;
-        int rc = run_batch(b, k, p, ci, false, nullptr, &ms); // capture + warm-up
-        if (rc) return rc;
-        for (int r = 0; r < 3; r++) {
-            if ((rc = run_batch(b, k, p, ci, false, nullptr, &ms))) return rc;
-            tot += ms;
-        }
-        if (tot < best_ms) { best_ms = tot; bi = ci; }
+        const Choice ch{ci, passes_for(b, k, CONFIGS[ci].growth), IN_GRAPH_RESTARTS};
+        if ((rc = time_choice(b, k, p, ch, &ms))) return rc;
+        if (ms < best_ms) { best_ms = ms; bc = ch; }
+    }
+    int worse = 0;
+    for (uint32_t P = bc.passes; P-- > 1 && worse < 2;) {
+        const Choice ch{bc.ci, P, bc.rounds};
+        if ((rc = time_choice(b, k, p, ch, &ms))) return rc;
+        if (ms < best_ms) { best_ms = ms; bc = ch; worse = 0; } else worse++;
+    }
+    for (uint32_t r = 0; r < IN_GRAPH_RESTARTS; r++) {
+        const Choice ch{bc.ci, bc.passes, r};
+        if ((rc = time_choice(b, k, p, ch, &ms))) return rc;
+        if (ms < best_ms) { best_ms = ms; bc = ch; }
     }
     // plans that lost are released
     for (auto it = b->plans.begin(); it != b->plans.end();) {
-        if (std::get<0>(it->first) == k && std::get<1>(it->first) == p_bits(p) && std::get<2>(it->first) != bi) {
+        const auto &key = it->first;
+        if (std::get<0>(key) == k && std::get<1>(key) == p_bits(p) &&
+            !(std::get<2>(key) == bc.ci && std::get<3>(key) == bc.passes && std::get<4>(key) == bc.rounds)) {
             (void)hipGraphExecDestroy(it->second.exec);
             (void)hipGraphDestroy(it->second.graph);
             it = b->plans.erase(it);
@@ -681,7 +955,7 @@ int autotune(tt_batch *b, uint32_t k, double p, int *best, double *tune_ms) {
             ++it;
         }
     }
-    *best = bi;
+    *best = bc;
     if (tune_ms) *tune_ms = now_ms() - t0;
     return TT_OK;
 }
@@ -718,25 +992,27 @@ extern "C" int batch_topk_ex(tt_batch *b, uint32_t k, double p, int config, uint
     (void)hipSetDevice(b->g->device);
     int rc = ensure_query_state(b, k);
     if (rc) return rc;
-    int ci = config;
+    Choice ch{config, 0, IN_GRAPH_RESTARTS};
     double tune_ms = 0.0;
-    if (ci < 0) {
+    if (config < 0) {
         auto key = std::make_pair(k, p_bits(p));
         auto it = b->tuned.find(key);
         if (it == b->tuned.end()) {
-            if ((rc = autotune(b, k, p, &ci, &tune_ms))) return rc;
-            b->tuned[key] = ci;
+            if ((rc = autotune(b, k, p, &ch, &tune_ms))) return rc;
+            b->tuned[key] = ch;
         } else {
-            ci = it->second;
+            ch = it->second;
         }
+    } else {
+        ch.passes = passes_for(b, k, CONFIGS[config].growth);
     }
-    uint32_t restarts = 0;
+    const int ci = ch.ci;
     double ms = 0.0;
-    if ((rc = run_batch(b, k, p, ci, (flags & TT_BATCH_EAGER) != 0, &restarts, &ms))) return rc;
+    if ((rc = run_batch(b, k, p, ch, (flags & TT_BATCH_EAGER) != 0, &ms))) return rc;
     hipStream_t s = b->stream;
     HIP_TRY(hipMemcpyAsync(n_out, b->dn, (uint64_t)b->count * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(out, b->dout, (uint64_t)b->count * k * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
-    unsigned long long st[5] = {};
+    unsigned long long st[6] = {};
     HIP_TRY(hipMemcpyAsync(st, b->dstat, sizeof(st), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (stats) {
@@ -744,8 +1020,9 @@ extern "C" int batch_topk_ex(tt_batch *b, uint32_t k, double p, int config, uint
         stats->growth = CONFIGS[ci].growth;
         stats->filter_blocks = std::min<uint32_t>((uint32_t)num_cus() * CONFIGS[ci].filter_mul, MAX_SEG);
         stats->intersect_blocks = (uint32_t)num_cus() * CONFIGS[ci].inter_mul;
-        stats->passes = passes_for(b, k, CONFIGS[ci].growth);
-        stats->restarts = restarts;
+        stats->passes = ch.passes;
+        stats->restart_rounds = ch.rounds;
+        stats->restarts = (uint32_t)(st[5] + b->extra[5]);
         stats->candidate_edges = st[0] + b->extra[0];
         stats->intersected_entries = st[1] + b->extra[1];
         stats->triangles_emitted = st[2] + b->extra[2];
@@ -767,7 +1044,11 @@ extern "C" void batch_free(tt_batch *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_plans(b);
     free_query_state(b);
-    void *ptrs[] = {b->voff, b->gm, b->gwmax, b->boff, b->goff, b->bs_src, b->bs_col, b->bs_wgt};
+    for (auto &o : b->ord) {
+        void *op[] = {o.boff, o.goff, o.src, o.col, o.wgt};
+        for (void *p : op) dev_free(nullptr, p, 0);
+    }
+    void *ptrs[] = {b->voff, b->gm};
     for (void *p : ptrs) dev_free(nullptr, p, 0);
     for (auto &e : b->ev)
         if (e) (void)hipEventDestroy(e);

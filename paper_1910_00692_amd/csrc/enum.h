@@ -53,6 +53,13 @@ __device__ __forceinline__ bool better(const trec &a, const trec &b) {
     return a.l < b.l;
 }
 
+// The record every real triangle beats (keys are >= 1).
+__device__ __forceinline__ trec worst_rec() {
+    trec r;
+    r.khi = 0; r.klo = 0; r.i = r.j = r.l = 0xFFFFFFFFu; r.pad = 0;
+    return r;
+}
+
 // ----------------------------------------------------------------------------- bounds
 struct Band {
     u128 L;              // inclusive lower bound on the order key ...
@@ -100,7 +107,7 @@ __host__ __device__ uint64_t gen_min_other(double p, double theta, double a, dou
 }
 
 // Smallest weight x (a lower bound of it) for which key(a, x, W) can still reach L.
-__device__ uint64_t min_other(const Band &B, uint32_t a, uint32_t W) {
+__device__ __forceinline__ uint64_t min_other(const Band &B, uint32_t a, uint32_t W) {
     if (B.L == 0) return 0;
     switch (B.mode) {
     case MODE_MAX: return ((u128)a >= B.L || (u128)W >= B.L) ? 0 : (uint64_t)B.L;
@@ -225,20 +232,35 @@ template <bool BATCH> __device__ __forceinline__ void stream_extent(const EnumAr
     }
 }
 
-// Batched form: the graph of stream index e, moving forward from a graph g at or before it.
-__device__ __forceinline__ uint32_t graph_at(const uint64_t *poff, uint32_t g, uint64_t e) {
-    while (poff[g + 1] <= e) g++;
-    return g;
-}
-
-// Batched form: the first graph whose part of the stream ends after e.
-__device__ __forceinline__ uint32_t graph_search(const uint64_t *poff, uint32_t ng, uint64_t e) {
-    uint32_t lo = 0, hi = ng; // last g with poff[g] <= e
+// Batched form: the last graph in [lo, hi) with poff[g] <= e, given poff[lo] <= e < poff[hi]
+// (graphs streaming nothing share their offset with the next one, so it is the graph whose
+// part of the stream holds e).
+__device__ __forceinline__ uint32_t graph_bsearch(const uint64_t *poff, uint32_t lo, uint32_t hi, uint64_t e) {
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (poff[mid] <= e) lo = mid; else hi = mid;
     }
-    return graph_at(poff, lo, e);
+    return lo;
+}
+
+// Batched form: the graph of stream index e (< poff[ng]), moving forward from a graph g at or
+// before it by galloping, so that runs of graphs streaming few entries cost a logarithm.
+__device__ __forceinline__ uint32_t graph_at(const uint64_t *poff, uint32_t ng, uint32_t g, uint64_t e) {
+    if (poff[g + 1] > e) return g;
+    uint32_t lo = g + 1, step = 1, hi;
+    for (;;) {
+        hi = lo + step;
+        if (hi >= ng) { hi = ng; break; }
+        if (poff[hi] > e) break;
+        lo = hi;
+        step <<= 1;
+    }
+    return graph_bsearch(poff, lo, hi, e);
+}
+
+// Batched form: the graph whose part of the stream holds e.
+__device__ __forceinline__ uint32_t graph_search(const uint64_t *poff, uint32_t ng, uint64_t e) {
+    return graph_bsearch(poff, 0, ng, e);
 }
 
 template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void k_filter(EnumArgs A) {
@@ -269,7 +291,7 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
             if (pass[k]) {
                 uint64_t x = e;
                 if (BATCH) {
-                    gcur = graph_at(A.poff, gcur, e);
+                    gcur = graph_at(A.poff, A.ng, gcur, e);
                     x = A.goff[gcur] + (e - A.poff[gcur]);
                     pos[k] = gcur;
                 }
@@ -557,6 +579,24 @@ __host__ __device__ inline uint64_t weight_floor(int mode, double p, u128 L, uin
     }
     default: return gen_min_other(p, key_as_double(L), (double)W, (double)W);
     }
+}
+
+// An integer t <= the score of any triangle whose key is >= L (so rows with hb < t can be
+// skipped): the score of key L, rounded down, lowered once more for the inexact roots.
+__host__ __device__ inline uint64_t score_floor(int mode, u128 L) {
+    if (L == 0) return 0;
+    double v;
+    switch (mode) {
+    case MODE_MAX:
+    case MODE_MIN: return (uint64_t)L;
+    case MODE_SUM: return (uint64_t)(L / 3);
+    case MODE_SUMSQ: v = sqrt(u128_to_double(L) / 3.0); break;
+    case MODE_PROD: v = cbrt(u128_to_double(L)); break;
+    default: v = key_as_double(L) * (1.0 - 1e-9); break;
+    }
+    if (!(v > 1.0)) return 0;
+    const uint64_t f = (uint64_t)floor(v);
+    return f > 0 ? f - 1 : 0;
 }
 
 } // namespace

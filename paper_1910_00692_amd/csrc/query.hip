@@ -38,11 +38,6 @@ namespace {
 // ----------------------------------------------------------------------------- selection
 constexpr int STILE = 1024;
 
-__device__ __forceinline__ trec worst_rec() {
-    trec r;
-    r.khi = 0; r.klo = 0; r.i = r.j = r.l = 0xFFFFFFFFu; r.pad = 0;
-    return r;
-}
 
 // Sorts each tile of STILE records (best first) in LDS and keeps its first S0.
 __global__ __launch_bounds__(512) void k_tile_sort(const trec *in, trec *out, uint64_t N, uint32_t S0) {
@@ -451,24 +446,6 @@ int select_topk(QueryCtx *q, uint64_t N, uint32_t k, trec **res) {
     HIP_TRY(hipGetLastError());
     *res = in;
     return TT_OK;
-}
-
-// An integer t <= the score of any triangle whose key is >= L (so rows with hb < t can be
-// skipped): the score of key L, rounded down, lowered once more for the inexact roots.
-uint64_t score_floor(int mode, u128 L) {
-    if (L == 0) return 0;
-    double v;
-    switch (mode) {
-    case MODE_MAX:
-    case MODE_MIN: return (uint64_t)L;
-    case MODE_SUM: return (uint64_t)(L / 3);
-    case MODE_SUMSQ: v = std::sqrt((double)L / 3.0); break;
-    case MODE_PROD: v = std::cbrt((double)L); break;
-    default: v = key_as_double(L) * (1.0 - 1e-9); break;
-    }
-    if (!(v > 1.0)) return 0;
-    const uint64_t f = (uint64_t)std::floor(v);
-    return f > 0 ? f - 1 : 0;
 }
 
 // Entries to stream for a band with lower key L: every row whose bin is >= bin(score floor).
