@@ -198,7 +198,8 @@ enum { TT_BATCH_EAGER = 1 }; /* run the launch sequence directly instead of its 
 
 /*
  * out: HOST, count*k triangles; graph g's top min(k, T_g) are out[g*k ...] in local ids,
- * sorted as topk_triangles sorts them; n_out: HOST, count values.  config = -1 uses the
+ * sorted as topk_triangles sorts them, the rest of its k slots zero; n_out: HOST, count
+ * values.  config = -1 uses the
  * autotuner's choice for this (k, p) (launch shape, number of bands and of captured restart
  * rounds, timed on first use), or 0 .. batch_num_configs()-1 forces a launch shape with the
  * full number of bands.  Every choice and both launch modes return exactly the same result.

@@ -343,17 +343,18 @@ class Batch:
         return int(library().batch_num_configs())
 
     def topk(self, k: int, p: float, config: int = -1, eager: bool = False, with_stats: bool = False):
-        """Top-k of every graph.  Returns dict(i, j, l, score: [count, k] arrays, n_out: [count])."""
+        """Top-k of every graph.  Returns dict(i, j, l, score: [count, k] arrays (slots past
+        n_out[g] are zero), n_out: [count])."""
         lib = library()
         k = int(k)
-        buf = (Triangle * max(self.count * k, 1))()
-        n_out = np.zeros(max(self.count, 1), np.uint32)
+        res = np.empty(max(self.count * k, 1), TRI_DTYPE)
+        n_out = np.empty(max(self.count, 1), np.uint32)
         st = BatchStats()
-        _check(lib.batch_topk_ex(self._h, k, float(p), int(config), TT_BATCH_EAGER if eager else 0, buf,
+        _check(lib.batch_topk_ex(self._h, k, float(p), int(config), TT_BATCH_EAGER if eager else 0,
+                                 ctypes.cast(res.ctypes.data, ctypes.POINTER(Triangle)),
                                  n_out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(st)))
-        r = np.frombuffer(buf, dtype=TRI_DTYPE, count=self.count * k).copy().reshape(self.count, k)
-        r[np.arange(k)[None, :] >= n_out[: self.count, None]] = 0  # rows hold n_out[g] triangles
-        out = {"i": r["i"], "j": r["j"], "l": r["l"], "score": r["score"], "n_out": n_out[: self.count].copy()}
+        r = res[: self.count * k].reshape(self.count, k)
+        out = {"i": r["i"], "j": r["j"], "l": r["l"], "score": r["score"], "n_out": n_out[: self.count]}
         if with_stats:
             out["stats"] = st.as_dict()
         return out

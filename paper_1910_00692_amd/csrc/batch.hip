@@ -398,6 +398,7 @@ __global__ __launch_bounds__(256) void k_bselect(const trec *rec, uint32_t R, co
         const uint32_t N = (uint32_t)cnt, K = N < k ? N : k;
         if (!wave_selects(N, K)) continue;
         if (K) wave_topk(rec + (uint64_t)g * R, N, K, (uint32_t)voff[g], mode, out + (uint64_t)g * k);
+        for (uint32_t r = K + lane; r < k; r += 64) out[(uint64_t)g * k + r] = tt_triangle{0, 0, 0, 0, 0.0};
         if (lane == 0) n_out[g] = K;
     }
 }
@@ -414,6 +415,7 @@ __global__ __launch_bounds__(256) void k_bselect_big(const trec *rec, uint32_t R
         const uint32_t N = (uint32_t)cnt, K = N < k ? N : k;
         if (wave_selects(N, K)) continue;
         block_topk(rec + (uint64_t)g * R, N, K, (uint32_t)voff[g], mode, out + (uint64_t)g * k, nullptr, sh);
+        for (uint32_t r = K + threadIdx.x; r < k; r += blockDim.x) out[(uint64_t)g * k + r] = tt_triangle{0, 0, 0, 0, 0.0};
         if (threadIdx.x == 0) n_out[g] = K;
     }
 }
@@ -520,6 +522,10 @@ struct tt_batch {
     tt_triangle *dout = nullptr;
     uint32_t *dn = nullptr;
     uint8_t *redo = nullptr;
+    // pinned host staging of the results (one device-to-host pass per query)
+    uint32_t *h_n = nullptr;
+    tt_triangle *h_out = nullptr;
+    unsigned long long *h_stat = nullptr;
     unsigned long long extra[6] = {}; // counters of the host-driven restart rounds of the latest query
     hipEvent_t ev[2] = {};
     struct Plan {
@@ -545,6 +551,12 @@ void free_query_state(tt_batch *b) {
     void *ptrs[] = {b->bands, b->st, b->Eg, b->poff, b->gcount, b->rec, b->C, b->ccnt,
                     b->spart, b->dstat, b->dout, b->dn, b->redo};
     for (void *p : ptrs) dev_free(nullptr, p, 0);
+    void *pinned[] = {b->h_n, b->h_out, b->h_stat};
+    for (void *p : pinned)
+        if (p) (void)hipHostFree(p);
+    b->h_n = nullptr;
+    b->h_out = nullptr;
+    b->h_stat = nullptr;
     b->bands = nullptr; b->st = nullptr; b->Eg = nullptr; b->poff = nullptr; b->gcount = nullptr;
     b->rec = nullptr; b->C = nullptr; b->ccnt = nullptr; b->spart = b->dstat = nullptr;
     b->dout = nullptr; b->dn = nullptr; b->redo = nullptr;
@@ -583,6 +595,12 @@ int ensure_query_state(tt_batch *b, uint32_t k) {
         (rc = dev_alloc(nullptr, (void **)&b->redo, n + 1))) {
         free_query_state(b);
         return rc;
+    }
+    if (hipHostMalloc((void **)&b->h_n, (n + 1) * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_out, n * k * sizeof(tt_triangle) + 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_stat, 16 * 8, hipHostMallocDefault) != hipSuccess) {
+        free_query_state(b);
+        return fail(TT_E_NOMEM, "hipHostMalloc failed");
     }
     HIP_TRY(hipMemsetAsync(b->spart, 0, 6 * STAT_SLOTS * 8, b->stream));
     HIP_TRY(hipMemsetAsync(b->ccnt, 0, MAX_SEG * 4, b->stream));
@@ -878,10 +896,16 @@ int run_batch(tt_batch *b, uint32_t k, double p, const Choice &ch, bool eager, d
         HIP_TRY(hipGraphLaunch(it->second.exec, s));
     }
     HIP_TRY(hipEventRecord(b->ev[1], s));
-    std::vector<uint32_t> hn(b->count);
     std::memset(b->extra, 0, sizeof(b->extra));
-    HIP_TRY(hipMemcpyAsync(hn.data(), b->dn, (uint64_t)b->count * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t out_bytes = (uint64_t)b->count * k * sizeof(tt_triangle);
+    auto fetch = [&](const unsigned long long *dstat, unsigned long long *hstat) -> int {
+        HIP_TRY(hipMemcpyAsync(b->h_n, b->dn, (uint64_t)b->count * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(b->h_out, b->dout, out_bytes, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hstat, dstat, 6 * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return TT_OK;
+    };
+    if ((rc = fetch(b->dstat, b->h_stat))) return rc;
     if (ms) {
         float f = 0.f;
         (void)hipEventElapsedTime(&f, b->ev[0], b->ev[1]);
@@ -891,16 +915,13 @@ int run_batch(tt_batch *b, uint32_t k, double p, const Choice &ch, bool eager, d
     EnumArgs A = batch_args(b, *o, p, c);
     for (int round = 0; round < 64; round++) {
         bool any = false;
-        for (uint32_t g = 0; g < b->count && !any; g++) any = hn[g] == OVERFLOWED;
+        for (uint32_t g = 0; g < b->count && !any; g++) any = b->h_n[g] == OVERFLOWED;
         if (!any) return TT_OK;
         if ((rc = enqueue_restart_round(b, A, c, k, p, *o))) return rc;
         k_reduce_stats<<<6, 256, 0, s>>>(b->spart, b->dstat + 8);
         HIP_TRY(hipGetLastError());
-        unsigned long long st[6];
-        HIP_TRY(hipMemcpyAsync(hn.data(), b->dn, (uint64_t)b->count * 4, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(st, b->dstat + 8, sizeof(st), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        for (int c2 = 0; c2 < 6; c2++) b->extra[c2] += st[c2];
+        if ((rc = fetch(b->dstat + 8, b->h_stat + 8))) return rc;
+        for (int c2 = 0; c2 < 6; c2++) b->extra[c2] += b->h_stat[8 + c2];
     }
     return fail(TT_E_DEVICE, "batched query: overflow restarts did not converge");
 }
@@ -987,7 +1008,11 @@ extern "C" int batch_topk_ex(tt_batch *b, uint32_t k, double p, int config, uint
     if (k && b->count && !out) return fail(TT_E_ARG, "out is NULL");
     if (config < -1 || config >= NCONFIGS) return fail(TT_E_ARG, "config out of range");
     if (flags & ~(uint32_t)TT_BATCH_EAGER) return fail(TT_E_ARG, "unknown flags");
-    if (k == 0 || b->count == 0 || b->g->m == 0) { set_error(""); return TT_OK; }
+    if (k == 0 || b->count == 0 || b->g->m == 0) {
+        if (k && out) std::memset(out, 0, (uint64_t)b->count * k * sizeof(tt_triangle));
+        set_error("");
+        return TT_OK;
+    }
     std::lock_guard<std::mutex> lock(b->mu);
     (void)hipSetDevice(b->g->device);
     int rc = ensure_query_state(b, k);
@@ -1009,12 +1034,9 @@ extern "C" int batch_topk_ex(tt_batch *b, uint32_t k, double p, int config, uint
     const int ci = ch.ci;
     double ms = 0.0;
     if ((rc = run_batch(b, k, p, ch, (flags & TT_BATCH_EAGER) != 0, &ms))) return rc;
-    hipStream_t s = b->stream;
-    HIP_TRY(hipMemcpyAsync(n_out, b->dn, (uint64_t)b->count * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(out, b->dout, (uint64_t)b->count * k * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
-    unsigned long long st[6] = {};
-    HIP_TRY(hipMemcpyAsync(st, b->dstat, sizeof(st), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(n_out, b->h_n, (uint64_t)b->count * 4);
+    std::memcpy(out, b->h_out, (uint64_t)b->count * k * sizeof(tt_triangle));
+    const unsigned long long *st = b->h_stat;
     if (stats) {
         stats->config = (uint32_t)ci;
         stats->growth = CONFIGS[ci].growth;
