@@ -68,6 +68,8 @@ typedef struct {
     double total_ms;              /* host wall time of the call */
     double enum_kernel_ms;        /* sum over passes of the enumeration kernel's own duration */
     double sample_ms;             /* sampling only: device time of the draws (and prefix sums) */
+    uint64_t bound_order;         /* 1 if the passes streamed the entries in order of their bound
+                                     for this p (built once this p has streamed > 4m entries) */
 } tt_query_stats;
 
 /*

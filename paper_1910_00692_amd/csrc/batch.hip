@@ -65,15 +65,6 @@ __global__ __launch_bounds__(256) void k_globalize(uint32_t *src, uint32_t *dst,
     }
 }
 
-// An integer >= the score of every triangle based at entry u->v (m_p of the entry's weight
-// and the two row maxima), at most the largest of the three.
-__device__ __forceinline__ uint32_t entry_bound(int mode, double p, uint32_t a, uint32_t Wu, uint32_t Wv) {
-    const uint32_t mx = max(a, max(Wu, Wv));
-    const double sc = key_to_score(mode, score_key(mode, p, a, Wu, Wv));
-    const double up = ceil(sc * (1.0 + 1e-9));
-    return up >= (double)mx ? mx : (uint32_t)up;
-}
-
 // One block per graph: entries per coarse bound bin (bucket g*NB + NB-1-bin).
 __global__ __launch_bounds__(256) void k_ocount(const uint64_t *voff, const uint64_t *rstart, const uint32_t *rlen,
                                                 const uint32_t *col, const uint32_t *wgt, const uint32_t *maxw,

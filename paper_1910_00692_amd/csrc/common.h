@@ -45,6 +45,7 @@ struct cand {
 // Device state of one query in flight: its stream, candidate buffers and counters.  A graph
 // owns one for its synchronous calls; a server owns one per slot, so that queries on one
 // resident graph run concurrently on separate streams.
+struct BoundOrder;
 struct QueryCtx {
     hipStream_t stream = nullptr;
     bool owns_stream = false;
@@ -69,11 +70,24 @@ struct QueryCtx {
     uint64_t sub_len = 0;                  // entries in the compact stream
     bool sub_active = false;               // the passes stream the compact list
     std::vector<uint64_t> sub_hist;        // host: its entries per weight_bin(w)
+    BoundOrder *ord = nullptr;             // bound order of the running query's p (or NULL)
     hipEvent_t ev[8] = {};
     std::vector<hipEvent_t> band_ev;       // start/stop pairs of the passes of a query
 };
 void ctx_release(QueryCtx *q); // device memory and events (not the stream)
 int ensure_in_csr(tt_graph *g, hipStream_t s);
+
+// Entries in descending order of their bound m_p(w_uv, maxw(u), maxw(v)) (grouped by
+// weight_bin of an integer >= it), for one p: the entries that can be the base of a triangle
+// scoring >= t are the prefix of bins >= weight_bin(t).  Built on first use of p.
+struct BoundOrder {
+    bool valid = false;
+    uint64_t pb = 0, last_use = 0;
+    int users = 0; // queries streaming it; never replaced while > 0
+    uint32_t *src = nullptr, *col = nullptr, *wgt = nullptr, *pos = nullptr;
+    std::vector<uint64_t> hist; // host: entries per bin
+    std::vector<uint64_t> base; // host: first entry of each bin (bins descending)
+};
 
 // ----------------------------------------------------------------------------- graph
 struct tt_graph {
@@ -128,6 +142,14 @@ struct tt_graph {
     uint32_t guide_bits = 0;
     uint64_t use_clock = 0;
     std::mutex mu;
+    BoundOrder bord[8];       // for the most recent p (guarded by init_mu)
+    uint32_t max_orders = 8;
+    uint64_t order_clock = 0;
+    // entries streamed so far by queries of each recent p without a bound order: an order is
+    // built once they exceed ORDER_AFTER times m (its cost is a few passes over the entries)
+    struct StreamedAt {
+        uint64_t pb = 0, entries = 0, last_use = 0;
+    } streamed[16];
 };
 
 // ----------------------------------------------------------------------------- weight bins

@@ -537,6 +537,15 @@ __global__ void k_band_gate(const unsigned long long *count, unsigned long long 
     if (threadIdx.x == 0 && blockIdx.x == 0 && *count >= k) *skip = 1;
 }
 
+// An integer >= the score of every triangle based at entry u->v (m_p of the entry's weight
+// and the two row maxima), at most the largest of the three.
+__device__ __forceinline__ uint32_t entry_bound(int mode, double p, uint32_t a, uint32_t Wu, uint32_t Wv) {
+    const uint32_t mx = max(a, max(Wu, Wv));
+    const double sc = key_to_score(mode, score_key(mode, p, a, Wu, Wv));
+    const double up = ceil(sc * (1.0 + 1e-9));
+    return up >= (double)mx ? mx : (uint32_t)up;
+}
+
 // ----------------------------------------------------------------------------- thresholds
 // The order key of a triangle whose three weights all equal t.
 __host__ __device__ inline u128 key_of_uniform(int mode, uint32_t t) {

@@ -632,6 +632,11 @@ void release(tt_graph *g) {
         dev_free(g, t.prefix, 0);
         dev_free(g, t.guide, 0);
     }
+    for (auto &o : g->bord) {
+        void *op[] = {o.src, o.col, o.wgt, o.pos};
+        for (void *p : op) dev_free(g, p, 0);
+        o = BoundOrder();
+    }
     ctx_release(&g->q);
 }
 

@@ -329,6 +329,62 @@ __global__ __launch_bounds__(256) void k_sub_rows(const uint32_t *ids, const uin
         if (h[t]) atomicAdd(&hist[t], (unsigned long long)h[t]);
 }
 
+// ----------------------------------------------------------------------------- bound order
+constexpr int BPLACE_ITEMS = 4;
+
+// Entries per bin of their bound (an integer >= m_p(w_uv, maxw(u), maxw(v))).
+__global__ __launch_bounds__(256) void k_bound_hist(const uint32_t *osrc, const uint32_t *col, const uint32_t *wgt,
+                                                    const uint32_t *maxw, uint64_t m, int mode, double p,
+                                                    unsigned long long *hist) {
+    __shared__ uint32_t h[WBINS];
+    for (int t = threadIdx.x; t < WBINS; t += blockDim.x) h[t] = 0;
+    __syncthreads();
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[weight_bin(entry_bound(mode, p, wgt[e], maxw[osrc[e]], maxw[col[e]]))], 1u);
+    __syncthreads();
+    for (int t = threadIdx.x; t < WBINS; t += blockDim.x)
+        if (h[t]) atomicAdd(&hist[t], (unsigned long long)h[t]);
+}
+
+// Entries grouped by descending bound bin: offsets inside the block from LDS counters, one
+// global atomic per (block, non-empty bin) to reserve the block's range inside the bin.
+__global__ __launch_bounds__(256) void k_place_bound(const uint32_t *osrc, const uint32_t *col, const uint32_t *wgt,
+                                                     const uint32_t *maxw, uint64_t m, int mode, double p,
+                                                     const unsigned long long *binbase, unsigned long long *bincur,
+                                                     uint32_t *o_src, uint32_t *o_col, uint32_t *o_wgt,
+                                                     uint32_t *o_pos) {
+    __shared__ uint32_t lc[WBINS];
+    __shared__ unsigned long long lb[WBINS];
+    for (int t = threadIdx.x; t < WBINS; t += blockDim.x) lc[t] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * BPLACE_ITEMS;
+    uint32_t off[BPLACE_ITEMS], bin[BPLACE_ITEMS];
+#pragma unroll
+    for (int it = 0; it < BPLACE_ITEMS; it++) {
+        const uint64_t e = base + (uint64_t)it * blockDim.x + threadIdx.x;
+        off[it] = bin[it] = 0;
+        if (e < m) {
+            bin[it] = weight_bin(entry_bound(mode, p, wgt[e], maxw[osrc[e]], maxw[col[e]]));
+            off[it] = atomicAdd(&lc[bin[it]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < WBINS; t += blockDim.x)
+        if (lc[t]) lb[t] = binbase[t] + atomicAdd(&bincur[t], (unsigned long long)lc[t]);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < BPLACE_ITEMS; it++) {
+        const uint64_t e = base + (uint64_t)it * blockDim.x + threadIdx.x;
+        if (e < m) {
+            const uint64_t d = lb[bin[it]] + off[it];
+            o_src[d] = osrc[e];
+            o_col[d] = col[e];
+            o_wgt[d] = wgt[e];
+            o_pos[d] = (uint32_t)e;
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------- host side
 // The weight of (a lower bound of) the M-th heaviest edge, from the load-time histogram.
 uint32_t weight_at_rank(const std::vector<uint64_t> &h, uint64_t M) {
@@ -464,7 +520,10 @@ struct Stream {
 
 // The shorter of the two streams that hold every possible base entry of a band triangle:
 // rows with hb >= score floor (row order), or entries with weight >= weight floor.
-Stream pick_stream(const tt_graph *g, int mode, double p, u128 L) {
+// The shortest of the streams that hold every possible base entry of a band triangle: rows
+// with hb >= score floor (row order), entries with weight >= weight floor, and (when the
+// query has one) entries whose bound reaches the score floor.
+Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u128 L) {
     Stream r{g->osrc, g->col, g->wgt, nullptr, entries_for(g, mode, L)};
     const uint64_t z = weight_floor(mode, p, L, g->wmax);
     uint64_t E2 = g->m;
@@ -474,7 +533,119 @@ Stream pick_stream(const tt_graph *g, int mode, double p, u128 L) {
         E2 = g->wbase[b] + g->whist[b];
     }
     if (E2 < r.E) r = Stream{g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, E2};
+    if (o) {
+        const uint64_t t = score_floor(mode, L);
+        uint64_t E3 = g->m;
+        if (t > 0xFFFFFFFFull) E3 = 0;
+        else if (t > 0) {
+            const uint32_t b = weight_bin((uint32_t)t);
+            E3 = o->base[b] + o->hist[b];
+        }
+        if (E3 < r.E) r = Stream{o->src, o->col, o->wgt, o->pos, E3};
+    }
     return r;
+}
+
+constexpr uint64_t ORDER_AFTER = 4;
+
+tt_graph::StreamedAt &streamed_at(tt_graph *g, uint64_t pb) {
+    tt_graph::StreamedAt *lru = &g->streamed[0];
+    for (auto &e : g->streamed) {
+        if (e.pb == pb && e.last_use) return e;
+        if (e.last_use < lru->last_use) lru = &e;
+    }
+    *lru = tt_graph::StreamedAt();
+    lru->pb = pb;
+    return *lru;
+}
+
+// Records the entries a query of p streamed without a bound order.
+void note_streamed(tt_graph *g, double p, uint64_t entries) {
+    uint64_t pb;
+    std::memcpy(&pb, &p, 8);
+    std::lock_guard<std::mutex> lock(g->init_mu);
+    tt_graph::StreamedAt &e = streamed_at(g, pb);
+    e.entries += entries;
+    e.last_use = ++g->order_clock;
+}
+
+// The bound order of p for a query; the caller releases it.  It is built once the queries of
+// p have streamed more than ORDER_AFTER*m entries through the other orders (so one-off queries
+// do not pay for it).  Orders of other p are replaced least recently used first, never while a
+// query streams them.  NULL when there is none (the query then streams the other orders).
+int acquire_order(tt_graph *g, QueryCtx *q, double p, BoundOrder **out) {
+    *out = nullptr;
+    if (g->m == 0) return TT_OK;
+    uint64_t pb;
+    std::memcpy(&pb, &p, 8);
+    std::lock_guard<std::mutex> lock(g->init_mu);
+    g->order_clock++;
+    BoundOrder *empty = nullptr, *lru = nullptr;
+    for (uint32_t i = 0; i < g->max_orders; i++) {
+        BoundOrder &o = g->bord[i];
+        if (o.valid && o.pb == pb) {
+            o.users++;
+            o.last_use = g->order_clock;
+            *out = &o;
+            return TT_OK;
+        }
+        if (o.users) continue;
+        if (!o.valid) {
+            if (!empty) empty = &o;
+        } else if (!lru || o.last_use < lru->last_use) {
+            lru = &o;
+        }
+    }
+    BoundOrder *slot = empty ? empty : lru;
+    if (!slot) return TT_OK;
+    if (streamed_at(g, pb).entries <= ORDER_AFTER * g->m) return TT_OK;
+    slot->valid = false;
+    const uint64_t m = g->m;
+    int rc;
+    if (!slot->src && ((rc = dev_alloc(g, (void **)&slot->src, (m + 1) * 4)) ||
+                       (rc = dev_alloc(g, (void **)&slot->col, (m + 1) * 4)) ||
+                       (rc = dev_alloc(g, (void **)&slot->wgt, (m + 1) * 4)) ||
+                       (rc = dev_alloc(g, (void **)&slot->pos, (m + 1) * 4))))
+        return rc;
+    hipStream_t s = q->stream;
+    unsigned long long *dev = nullptr; // hist | base | cursors
+    if ((rc = dev_alloc(nullptr, (void **)&dev, 3 * WBINS * 8))) return rc;
+    const int mode = mode_of(p);
+    auto body = [&]() -> int {
+        HIP_TRY(hipMemsetAsync(dev, 0, 3 * WBINS * 8, s));
+        k_bound_hist<<<enum_grid(m), 256, 0, s>>>(g->osrc, g->col, g->wgt, g->maxw, m, mode, p, dev);
+        HIP_TRY(hipGetLastError());
+        slot->hist.assign(WBINS, 0);
+        HIP_TRY(hipMemcpyAsync(slot->hist.data(), dev, WBINS * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        slot->base.assign(WBINS, 0);
+        uint64_t run = 0;
+        for (int b = WBINS - 1; b >= 0; b--) { slot->base[b] = run; run += slot->hist[b]; }
+        HIP_TRY(hipMemcpyAsync(dev + WBINS, slot->base.data(), WBINS * 8, hipMemcpyHostToDevice, s));
+        const uint64_t per = 256ull * BPLACE_ITEMS;
+        k_place_bound<<<(unsigned)((m + per - 1) / per), 256, 0, s>>>(g->osrc, g->col, g->wgt, g->maxw, m, mode, p,
+                                                                     dev + WBINS, dev + 2 * WBINS, slot->src,
+                                                                     slot->col, slot->wgt, slot->pos);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+        return TT_OK;
+    };
+    rc = body();
+    (void)hipStreamSynchronize(s);
+    dev_free(nullptr, dev, 0);
+    if (rc) return rc;
+    slot->valid = true;
+    slot->pb = pb;
+    slot->users = 1;
+    slot->last_use = g->order_clock;
+    *out = slot;
+    return TT_OK;
+}
+
+void release_order(tt_graph *g, BoundOrder *o) {
+    if (!o) return;
+    std::lock_guard<std::mutex> lock(g->init_mu);
+    o->users--;
 }
 
 int ensure_band_events(QueryCtx *q, size_t pairs) {
@@ -490,7 +661,7 @@ int ensure_band_events(QueryCtx *q, size_t pairs) {
 // intersected in pieces of at most cand_cap entries.  `slot` picks its event pair.
 int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool gated, size_t slot) {
     const Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len}
-                                   : pick_stream(g, B.mode, B.p, B.L);
+                                   : pick_stream(g, q->ord, B.mode, B.p, B.L);
     EnumArgs A;
     A.rstart = g->rstart;
     A.rlen = g->rlen;
@@ -571,7 +742,9 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     hipStream_t s = q->stream;
     // thresholds: key(t, t, t) for t = weight of the k-th, 4k-th, 16k-th ... heaviest edge
     // (for a subset query: of the k-th, 4k-th ... heaviest entry of its compact stream)
-    const std::vector<uint64_t> &hist = q->sub_active ? q->sub_hist : g->whist;
+    // (for a subset query: of its compact stream; with a bound order: the k-th, 4k-th ...
+    // highest entry bound)
+    const std::vector<uint64_t> &hist = q->sub_active ? q->sub_hist : q->ord ? q->ord->hist : g->whist;
     const uint64_t total = q->sub_active ? q->sub_len : g->m;
     std::vector<u128> Ls;
     for (uint64_t M = k; M < (1ull << 62); M *= 4) {
@@ -750,7 +923,14 @@ int query_on(tt_graph *g, QueryCtx *q, uint32_t k, double p, const uint32_t *sub
             return rc;
         filter = FILTER_VERTICES;
     }
+    BoundOrder *o = nullptr;
+    if (!q->sub_active && (rc = acquire_order(g, q, p, &o))) return rc;
+    q->ord = o;
+    if (stats) stats->bound_order = o ? 1 : 0;
     rc = run_topk(g, q, k, p, filter, out, n_out, stats);
+    q->ord = nullptr;
+    release_order(g, o);
+    if (!rc && !o && !q->sub_active) note_streamed(g, p, q->hcount[4]);
     q->sub_active = false;
     return rc;
 }
@@ -834,7 +1014,14 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
     k_mark_tails<<<enum_grid(g->m / 16 + 1), 256, 0, s>>>(g->emark, g->m, g->osrc, q->vflag);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(q->ev[7], s));
+    BoundOrder *o = nullptr;
+    if ((rc = acquire_order(g, q, p, &o))) return rc;
+    q->ord = o;
+    if (stats) stats->bound_order = o ? 1 : 0;
     rc = run_topk(g, q, k, p, FILTER_EDGES, out, n_out, stats);
+    q->ord = nullptr;
+    release_order(g, o);
+    if (!rc && !o) note_streamed(g, p, q->hcount[4]);
     if (!rc && stats) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, q->ev[6], q->ev[7]) == hipSuccess) stats->sample_ms = ms;

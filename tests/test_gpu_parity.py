@@ -154,6 +154,35 @@ def test_subset_repeats_hubs_and_everything(tt, small):
         assert triples(a) == triples(b) and np.array_equal(a["score"], b["score"])
 
 
+def test_bound_order_after_repeated_queries(tt):
+    """Repeated queries of one p build its bound order once they have streamed more than 4m
+    entries; the answers must not change when the passes switch to it (every p, both query
+    kinds, and a restart above the k-th key with K_300's ties)."""
+    g = graphgen.chung_lu(20000, 200000, 2.2, 1.8, seed=13, plant=4, plant_size=4, plant_mult=1000)
+    ei = EdgeIndex(g.src, g.dst, g.w)
+    with tt.Graph(g.n, g.src, g.dst, g.w) as G:
+        for p in ALL_P:
+            want = oracle.topk(g.n, g.src, g.dst, g.w, 3000, p)
+            first, used = None, False
+            for rep in range(40):
+                r = G.topk(3000, p, with_stats=True)
+                assert_parity(r, want, p, ei, ctx=f"order p={p} rep={rep}")
+                used = used or bool(r["stats"]["bound_order"])
+                if used:
+                    break
+            assert used, p
+            es0 = oracle.sample_heavy_triangles(g.n, g.src, g.dst, g.w, 200, p, 20000, 5)
+            assert_parity(G.sample(200, p, 20000, 5), es0, p, ei, ctx=f"order es p={p}")
+    n = 300
+    s, d = (np.array(x, np.uint32) for x in zip(*itertools.combinations(range(n), 2)))
+    with tt.Graph(n, s, d, np.full(len(s), 5, np.uint32)) as G:
+        want = list(itertools.islice(itertools.combinations(range(n), 3), 100))
+        for rep in range(6):
+            r = G.topk(100, 1.0, with_stats=True)
+            assert triples(r) == want and r["stats"]["restarts"] >= 1
+        assert r["stats"]["bound_order"] == 1
+
+
 def test_validation_errors(tt):
     cases = [
         (3, [0, 1], [1, 1], [1, 1]),
