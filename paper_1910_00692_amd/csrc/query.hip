@@ -330,7 +330,6 @@ __global__ __launch_bounds__(256) void k_sub_rows(const uint32_t *ids, const uin
 }
 
 // ----------------------------------------------------------------------------- bound order
-constexpr int BPLACE_ITEMS = 4;
 
 // Entries per bin of their bound (an integer >= m_p(w_uv, maxw(u), maxw(v))).
 __global__ __launch_bounds__(256) void k_bound_hist(const uint32_t *osrc, const uint32_t *col, const uint32_t *wgt,
@@ -346,42 +345,43 @@ __global__ __launch_bounds__(256) void k_bound_hist(const uint32_t *osrc, const 
         if (h[t]) atomicAdd(&hist[t], (unsigned long long)h[t]);
 }
 
-// Entries grouped by descending bound bin: offsets inside the block from LDS counters, one
-// global atomic per (block, non-empty bin) to reserve the block's range inside the bin.
+// Entries grouped by descending bound bin.  A block places a chunk of BPLACE_CHUNK consecutive
+// entries: their bins are kept in LDS, one global atomic per (block, non-empty bin) reserves
+// the block's run inside each bin, and an LDS cursor per bin hands out slots, so the entries
+// of one bin from one block land in one contiguous run (whole cache lines, not scattered words).
+constexpr uint32_t BPLACE_CHUNK = 16384;
 __global__ __launch_bounds__(256) void k_place_bound(const uint32_t *osrc, const uint32_t *col, const uint32_t *wgt,
                                                      const uint32_t *maxw, uint64_t m, int mode, double p,
                                                      const unsigned long long *binbase, unsigned long long *bincur,
                                                      uint32_t *o_src, uint32_t *o_col, uint32_t *o_wgt,
                                                      uint32_t *o_pos) {
+    __shared__ uint16_t bins[BPLACE_CHUNK];
     __shared__ uint32_t lc[WBINS];
     __shared__ unsigned long long lb[WBINS];
     for (int t = threadIdx.x; t < WBINS; t += blockDim.x) lc[t] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * BPLACE_ITEMS;
-    uint32_t off[BPLACE_ITEMS], bin[BPLACE_ITEMS];
-#pragma unroll
-    for (int it = 0; it < BPLACE_ITEMS; it++) {
-        const uint64_t e = base + (uint64_t)it * blockDim.x + threadIdx.x;
-        off[it] = bin[it] = 0;
-        if (e < m) {
-            bin[it] = weight_bin(entry_bound(mode, p, wgt[e], maxw[osrc[e]], maxw[col[e]]));
-            off[it] = atomicAdd(&lc[bin[it]], 1u);
-        }
+    const uint64_t base = (uint64_t)blockIdx.x * BPLACE_CHUNK;
+    const uint32_t cover = (uint32_t)(m - base < BPLACE_CHUNK ? m - base : BPLACE_CHUNK);
+    for (uint32_t t = threadIdx.x; t < cover; t += blockDim.x) {
+        const uint64_t e = base + t;
+        const uint32_t b = weight_bin(entry_bound(mode, p, wgt[e], maxw[osrc[e]], maxw[col[e]]));
+        bins[t] = (uint16_t)b;
+        atomicAdd(&lc[b], 1u);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < WBINS; t += blockDim.x)
+    for (int t = threadIdx.x; t < WBINS; t += blockDim.x) {
         if (lc[t]) lb[t] = binbase[t] + atomicAdd(&bincur[t], (unsigned long long)lc[t]);
+        lc[t] = 0;
+    }
     __syncthreads();
-#pragma unroll
-    for (int it = 0; it < BPLACE_ITEMS; it++) {
-        const uint64_t e = base + (uint64_t)it * blockDim.x + threadIdx.x;
-        if (e < m) {
-            const uint64_t d = lb[bin[it]] + off[it];
-            o_src[d] = osrc[e];
-            o_col[d] = col[e];
-            o_wgt[d] = wgt[e];
-            o_pos[d] = (uint32_t)e;
-        }
+    for (uint32_t t = threadIdx.x; t < cover; t += blockDim.x) {
+        const uint64_t e = base + t;
+        const uint32_t b = bins[t];
+        const uint64_t d = lb[b] + atomicAdd(&lc[b], 1u);
+        o_src[d] = osrc[e];
+        o_col[d] = col[e];
+        o_wgt[d] = wgt[e];
+        o_pos[d] = (uint32_t)e;
     }
 }
 
@@ -547,6 +547,10 @@ Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u
 }
 
 constexpr uint64_t ORDER_AFTER = 4;
+// On a graph with at least this many entries the first query of p builds the order at once:
+// there a single pass of the other orders costs as much as the build (two passes) and the
+// threshold bands they allow are coarse enough to stream the entries several times.
+constexpr uint64_t ORDER_NOW_M = 1ull << 28;
 
 tt_graph::StreamedAt &streamed_at(tt_graph *g, uint64_t pb) {
     tt_graph::StreamedAt *lru = &g->streamed[0];
@@ -571,8 +575,9 @@ void note_streamed(tt_graph *g, double p, uint64_t entries) {
 
 // The bound order of p for a query; the caller releases it.  It is built once the queries of
 // p have streamed more than ORDER_AFTER*m entries through the other orders (so one-off queries
-// do not pay for it).  Orders of other p are replaced least recently used first, never while a
-// query streams them.  NULL when there is none (the query then streams the other orders).
+// on moderate graphs do not pay for it), or at once on graphs of at least ORDER_NOW_M entries.
+// Orders of other p are replaced least recently used first, never while a query streams them.
+// NULL when there is none (the query then streams the other orders).
 int acquire_order(tt_graph *g, QueryCtx *q, double p, BoundOrder **out) {
     *out = nullptr;
     if (g->m == 0) return TT_OK;
@@ -598,7 +603,7 @@ int acquire_order(tt_graph *g, QueryCtx *q, double p, BoundOrder **out) {
     }
     BoundOrder *slot = empty ? empty : lru;
     if (!slot) return TT_OK;
-    if (streamed_at(g, pb).entries <= ORDER_AFTER * g->m) return TT_OK;
+    if (g->m < ORDER_NOW_M && streamed_at(g, pb).entries <= ORDER_AFTER * g->m) return TT_OK;
     slot->valid = false;
     const uint64_t m = g->m;
     int rc;
@@ -622,8 +627,7 @@ int acquire_order(tt_graph *g, QueryCtx *q, double p, BoundOrder **out) {
         uint64_t run = 0;
         for (int b = WBINS - 1; b >= 0; b--) { slot->base[b] = run; run += slot->hist[b]; }
         HIP_TRY(hipMemcpyAsync(dev + WBINS, slot->base.data(), WBINS * 8, hipMemcpyHostToDevice, s));
-        const uint64_t per = 256ull * BPLACE_ITEMS;
-        k_place_bound<<<(unsigned)((m + per - 1) / per), 256, 0, s>>>(g->osrc, g->col, g->wgt, g->maxw, m, mode, p,
+        k_place_bound<<<(unsigned)((m + BPLACE_CHUNK - 1) / BPLACE_CHUNK), 256, 0, s>>>(g->osrc, g->col, g->wgt, g->maxw, m, mode, p,
                                                                      dev + WBINS, dev + 2 * WBINS, slot->src,
                                                                      slot->col, slot->wgt, slot->pos);
         HIP_TRY(hipGetLastError());
