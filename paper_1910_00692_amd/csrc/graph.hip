@@ -174,24 +174,11 @@ __device__ inline void orient(uint32_t a, uint32_t b, const uint32_t *deg, uint3
     head = a_low ? b : a;
 }
 
+// Out-degree of every tail; each edge keeps its tail and its slot inside the tail's row (the
+// value its atomic returned), so the scatter needs neither the degrees nor atomics.
 __global__ __launch_bounds__(256) void k_outdeg(const uint32_t *src, const uint32_t *dst, uint64_t m,
-                                                const uint32_t *deg, uint32_t *outdeg) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
-        const uint64_t e = base + lane;
-        const bool valid = e < m;
-        uint32_t t = 0, h = 0;
-        if (valid) orient(src[e], dst[e], deg, t, h);
-        WaveRuns r = wave_runs(t, valid);
-        if (valid && r.first == lane) atomicAdd(&outdeg[t], (uint32_t)(r.end - lane));
-    }
-}
-
-// Scatters every edge into its tail's row (rows unsorted) as one 16-byte record.
-__global__ __launch_bounds__(256) void k_scatter(const uint32_t *src, const uint32_t *dst, const uint32_t *w, uint64_t m,
-                                                 const uint32_t *deg, const uint64_t *rowp, uint32_t *cursor,
-                                                 uint4 *rec) {
+                                                const uint32_t *deg, uint32_t *outdeg, uint32_t *etail,
+                                                uint32_t *eslot) {
     const int lane = threadIdx.x & 63;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
@@ -201,9 +188,24 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *src, const uint
         if (valid) orient(src[e], dst[e], deg, t, h);
         WaveRuns r = wave_runs(t, valid);
         uint32_t slot = 0;
-        if (valid && r.first == lane) slot = atomicAdd(&cursor[t], (uint32_t)(r.end - lane));
+        if (valid && r.first == lane) slot = atomicAdd(&outdeg[t], (uint32_t)(r.end - lane));
         slot = __shfl(slot, r.first, 64) + (uint32_t)(lane - r.first);
-        if (valid) rec[rowp[t] + slot] = make_uint4(h, w[e], (uint32_t)e, t); // (head, weight, edge, tail)
+        if (valid) {
+            etail[e] = t;
+            eslot[e] = slot;
+        }
+    }
+}
+
+// Scatters every edge into its tail's row (rows unsorted) as one 16-byte record.
+__global__ __launch_bounds__(256) void k_scatter(const uint32_t *src, const uint32_t *dst, const uint32_t *w, uint64_t m,
+                                                 const uint32_t *etail, const uint32_t *eslot, const uint64_t *rowp,
+                                                 uint4 *rec) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+        const uint32_t t = etail[e];
+        const uint32_t h = src[e] ^ dst[e] ^ t; // the other endpoint
+        rec[rowp[t] + eslot[e]] = make_uint4(h, w[e], (uint32_t)e, t); // (head, weight, edge, tail)
     }
 }
 
@@ -733,7 +735,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     const uint64_t nn = (uint64_t)n + 1;
     uint64_t *rowp0 = nullptr;
     uint4 *rec0 = nullptr;
-    uint32_t *cursor = nullptr, *big = nullptr, *mid = nullptr;
+    uint32_t *big = nullptr, *mid = nullptr;
     if ((rc = dev_alloc(g, (void **)&g->deg, nn * 4)) || (rc = dev_alloc(g, (void **)&g->rstart, nn * 8)) ||
         (rc = dev_alloc(g, (void **)&g->rlen, nn * 4)) || (rc = dev_alloc(g, (void **)&g->maxw, nn * 4)) ||
         (rc = dev_alloc(g, (void **)&g->hb, nn * 4)) || (rc = dev_alloc(g, (void **)&g->col, (m + 1) * 4)) ||
@@ -741,23 +743,24 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         (rc = dev_alloc(g, (void **)&g->eid, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->opos, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->wcol, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->wwgt, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->wpos, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->in_w, (m + 1) * 4)) ||
-        (rc = S.get((void **)&cursor, nn * 4)) || (rc = S.get((void **)&big, nn * 4)) ||
+        (rc = S.get((void **)&big, nn * 4)) ||
         (rc = S.get((void **)&mid, nn * 4)) || (rc = S.get((void **)&rowp0, (nn + 1) * 8)) ||
         (rc = S.get((void **)&rec0, (m + 1) * 16)))
         return rc;
     HIP_TRY(hipMemsetAsync(g->deg, 0, nn * 4, s));
     HIP_TRY(hipMemsetAsync(g->rlen, 0, nn * 4, s));
-    HIP_TRY(hipMemsetAsync(cursor, 0, nn * 4, s));
     HIP_TRY(hipMemsetAsync(g->maxw, 0, nn * 4, s));
     if (m) {
         HIP_TRY(hipMemcpyAsync(g->in_w, w, m * 4, hipMemcpyDeviceToDevice, s));
         k_degree<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg);
-        k_outdeg<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg, g->rlen);
+        // the weight-sorted arrays are filled by the row ranking; until then they hold each
+        // edge's tail and slot
+        k_outdeg<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg, g->rlen, g->wcol, g->wwgt);
     }
     // rows in vertex order first (unsorted): rowp0[n] = m
     if ((rc = exclusive_scan_u32_to_u64(g->rlen, rowp0, nn, s, nullptr))) return rc;
     if (m) {
-        k_scatter<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, g->deg, rowp0, cursor, rec0);
+        k_scatter<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, g->wcol, g->wwgt, rowp0, rec0);
         k_row_max<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw);
     }
     HIP_TRY(hipMemcpyAsync(g->hb, g->maxw, nn * 4, hipMemcpyDeviceToDevice, s));
