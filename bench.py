@@ -58,6 +58,9 @@ def run_serve(args):
     to triangles touching 1,000 random vertices), submitted at its arrival times to the
     continuous-batching server; compared with the same requests run one at a time."""
     import threading
+    # one hardware queue per server slot, so the slots' streams do not share queues (HIP reads
+    # this when the runtime starts, i.e. before torch touches the GPU)
+    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.slots))))
     import torch
     import graphgen
     import paper_1910_00692_amd as tt
@@ -122,6 +125,7 @@ def run_serve(args):
         "config": {"workload": "served: chung-lu n=10M m~200M gamma2.1 zipf(1.8); Poisson 2000 req/s, k log-uniform "
                                "[10,1e4], p in {-inf,-1,0,1,2,+inf}, 20% subset(1000) queries",
                    "n": g.n, "m": g.m, "requests": len(reqs), "slots": args.slots, "budget_gb": args.budget_gb,
+                   "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
         "single_query_path": {"queries_per_s": len(reqs) / single_s, "p50_ms": pct(single, 50),
@@ -234,7 +238,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sampling", action="store_true", help="exact queries only")
     ap.add_argument("--requests", type=int, default=2000, help="served workload: number of requests")
-    ap.add_argument("--slots", type=int, default=4, help="served workload: server slots")
+    ap.add_argument("--slots", type=int, default=8, help="served workload: server slots")
     ap.add_argument("--budget-gb", type=int, default=16, help="served workload: scratch budget (GiB)")
     ap.add_argument("--serve-n", type=int, default=10_000_000)
     ap.add_argument("--serve-m", type=int, default=200_000_000)

@@ -129,7 +129,9 @@ int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint64_t budget
  * stream and its query scratch, so admitted requests overlap on the device.  Requests wait in
  * FIFO order and are admitted when a worker is free and their scratch bytes
  * (server_request_bytes) fit into `scratch_budget` together with the requests already
- * running; a request arriving while others run is admitted as soon as one finishes.  Every
+ * running; a request arriving while others run is admitted as soon as one finishes.  A worker
+ * keeps its scratch between requests (it grows with k), so the device memory held is at most
+ * `slots` times the largest request charged.  Every
  * result is exactly the result of topk_triangles_ex for the same arguments.  The graph must
  * outlive the server and must not be freed while it runs.  All calls are thread-safe.
  */

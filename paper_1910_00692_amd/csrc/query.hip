@@ -1108,7 +1108,8 @@ void serve_worker(tt_server *S, size_t slot) {
                           res.tri.data(), &res.n_out, &res.st);
         if (res.rc) res.err = tt_last_error();
         res.st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - r.t_submit).count();
-        ctx_release(q); // the scratch goes back to the device memory cache
+        // the slot keeps its scratch for the next request (it only grows with k); releasing it
+        // here would cost allocations, and a free of device memory waits for the whole device
         res.done = true;
         {
             std::lock_guard<std::mutex> lk(S->mu);
