@@ -619,6 +619,8 @@ EnumArgs batch_args(const tt_batch *b, const tt_batch::Order &o, double p, const
     A.wwgt = g->wwgt;
     A.wpos = g->wpos;
     A.maxw = g->maxw;
+    A.vi = g->vinfo;
+    A.cw = g->cw;
     A.s_src = o.src;
     A.s_col = o.col;
     A.s_wgt = o.wgt;

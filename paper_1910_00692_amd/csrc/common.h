@@ -45,6 +45,13 @@ struct cand {
 // Device state of one query in flight: its stream, candidate buffers and counters.  A graph
 // owns one for its synchronous calls; a server owns one per slot, so that queries on one
 // resident graph run concurrently on separate streams.
+// What an intersection needs of a vertex, in one 16-byte load.
+struct alignas(16) VInfo {
+    uint64_t rstart; // first entry of the out-row
+    uint32_t rlen;   // out-degree
+    uint32_t maxw;   // largest weight in the out-row
+};
+
 struct BoundOrder;
 struct QueryCtx {
     hipStream_t stream = nullptr;
@@ -115,6 +122,8 @@ struct tt_graph {
     uint32_t *ws_pos = nullptr; // head-sorted position of each such entry
     std::vector<uint64_t> wbase; // host: first entry of each weight bin (bins descending)
     uint32_t *maxw = nullptr;   // [n] largest weight in u's out-row (0 for an empty row)
+    VInfo *vinfo = nullptr;     // [n+1] rstart, rlen, maxw packed (the intersection's reads)
+    uint2 *cw = nullptr;        // [m] (col, wgt) interleaved: a binary-search hit holds the weight
     uint32_t *hb = nullptr;     // [n] max(maxw[u], maxw[v] over out-neighbours v): bounds every
                                 //     triangle based at u, for every p
     uint32_t *deg = nullptr;    // [n] undirected degree

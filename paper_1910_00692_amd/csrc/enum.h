@@ -146,6 +146,8 @@ enum { FL_MARK_UV = 1, FL_REQ_A = 2, FL_REQ_B = 4, FL_REQ_C = 8 };
 struct EnumArgs {
     const uint64_t *rstart;
     const uint32_t *rlen, *col, *wgt, *wcol, *wwgt, *wpos, *maxw;
+    const VInfo *vi; // rstart, rlen, maxw per vertex
+    const uint2 *cw; // (col, wgt) per entry
     // the stream of candidate entries (tail, head, weight, head-sorted position or NULL if the
     // stream is the head-sorted layout itself) and its length
     const uint32_t *s_src, *s_col, *s_wgt, *s_pos;
@@ -398,9 +400,10 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
             a = c.a;
             if (BATCH) g = c.pos;
             const Band &B = band_of<BATCH>(A, g);
-            const uint32_t Wu = A.maxw[u], Wv = A.maxw[v];
-            const uint64_t ub = A.rstart[u], vb = A.rstart[v];
-            const uint32_t ul = A.rlen[u], vl = A.rlen[v];
+            const VInfo iu = A.vi[u], iv = A.vi[v];
+            const uint32_t Wu = iu.maxw, Wv = iv.maxw;
+            const uint64_t ub = iu.rstart, vb = iv.rstart;
+            const uint32_t ul = iu.rlen, vl = iv.rlen;
             if (FILTER == FILTER_EDGES && A.emark[c.pos]) fl |= FL_MARK_UV;
             if (FILTER == FILTER_VERTICES && !A.vflag[u] && !A.vflag[v]) fl |= FL_REQ_C;
             const uint64_t zu = min_other(B, a, Wv), zv = min_other(B, a, Wu);
@@ -458,10 +461,11 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
                     uint64_t lo = oBb, hi = oBb + oBlen;
                     while (lo < hi) {
                         const uint64_t mid = (lo + hi) >> 1;
-                        if (A.col[mid] < c) lo = mid + 1; else hi = mid;
+                        if (A.cw[mid].x < c) lo = mid + 1; else hi = mid;
                     }
-                    if (lo < oBb + oBlen && A.col[lo] == c) {
-                        const uint32_t y = A.wgt[lo];
+                    const uint2 hit = lo < oBb + oBlen ? A.cw[lo] : make_uint2(~0u, 0u);
+                    if (hit.x == c) {
+                        const uint32_t y = hit.y;
                         bool adm = (uint64_t)y >= ozB;
                         if (FILTER == FILTER_EDGES) {
                             const uint8_t markB = A.emark[lo];

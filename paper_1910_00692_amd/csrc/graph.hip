@@ -628,7 +628,8 @@ void release(tt_graph *g) {
     if (!g) return;
     void *ptrs[] = {g->rstart, g->rlen,   g->col,    g->wgt,  g->osrc,    g->eid,   g->opos,
                     g->wcol,   g->wwgt,   g->wpos,   g->maxw, g->hb,      g->deg,   g->emark,
-                    g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->in_w,  g->irstart, g->itail};
+                    g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->in_w,  g->irstart, g->itail,
+                    g->vinfo,  g->cw};
     for (void *p : ptrs) dev_free(g, p, 0);
     for (auto &t : g->tables) {
         dev_free(g, t.prefix, 0);
@@ -709,6 +710,18 @@ __global__ __launch_bounds__(256) void k_in_scatter(const uint32_t *col, const u
         slot = __shfl(slot, r.first, 64) + (uint32_t)(lane - r.first);
         if (valid) itail[irstart[v] + slot] = osrc[e];
     }
+}
+
+// The intersection's per-vertex reads in one 16-byte record, and rows as (col, wgt) pairs.
+__global__ __launch_bounds__(256) void k_pack_vinfo(const uint64_t *rstart, const uint32_t *rlen, const uint32_t *maxw,
+                                                    uint64_t nn, VInfo *vi) {
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nn; v += (uint64_t)gridDim.x * blockDim.x)
+        vi[v] = VInfo{rstart[v], rlen[v], maxw[v]};
+}
+
+__global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint32_t *wgt, uint64_t m, uint2 *cw) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        cw[e] = make_uint2(col[e], wgt[e]);
 }
 
 } // namespace
@@ -848,6 +861,10 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         k_place_entries<<<(unsigned)((m + per - 1) / per), 256, 0, s>>>(g->osrc, g->col, g->wgt, m, binbase, bincur,
                                                                         g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos);
     }
+    if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo))) || (rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8)))
+        return rc;
+    k_pack_vinfo<<<grid_for(nn), 256, 0, s>>>(g->rstart, g->rlen, g->maxw, nn, g->vinfo);
+    if (m) k_pack_cw<<<grid_for(m), 256, 0, s>>>(g->col, g->wgt, m, g->cw);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
     return TT_OK;

@@ -675,6 +675,8 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
     A.wwgt = g->wwgt;
     A.wpos = g->wpos;
     A.maxw = g->maxw;
+    A.vi = g->vinfo;
+    A.cw = g->cw;
     A.skip = gated ? q->dcount + 7 : nullptr;
     A.B = B;
     A.emark = g->emark;
