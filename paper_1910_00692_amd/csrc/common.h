@@ -89,8 +89,9 @@ int ensure_in_csr(tt_graph *g, hipStream_t s);
 // scoring >= t are the prefix of bins >= weight_bin(t).  Built on first use of p.
 struct BoundOrder {
     bool valid = false;
+    bool building = false; // reserved by the query building it
     uint64_t pb = 0, last_use = 0;
-    int users = 0; // queries streaming it; never replaced while > 0
+    int users = 0; // queries streaming (or building) it; never replaced while > 0
     uint32_t *src = nullptr, *col = nullptr, *wgt = nullptr, *pos = nullptr;
     std::vector<uint64_t> hist; // host: entries per bin
     std::vector<uint64_t> base; // host: first entry of each bin (bins descending)

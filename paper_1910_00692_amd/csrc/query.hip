@@ -583,40 +583,48 @@ int acquire_order(tt_graph *g, QueryCtx *q, double p, BoundOrder **out) {
     if (g->m == 0) return TT_OK;
     uint64_t pb;
     std::memcpy(&pb, &p, 8);
-    std::lock_guard<std::mutex> lock(g->init_mu);
-    g->order_clock++;
-    BoundOrder *empty = nullptr, *lru = nullptr;
-    for (uint32_t i = 0; i < g->max_orders; i++) {
-        BoundOrder &o = g->bord[i];
-        if (o.valid && o.pb == pb) {
-            o.users++;
-            o.last_use = g->order_clock;
-            *out = &o;
-            return TT_OK;
+    BoundOrder *slot = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g->init_mu);
+        g->order_clock++;
+        BoundOrder *empty = nullptr, *lru = nullptr;
+        for (uint32_t i = 0; i < g->max_orders; i++) {
+            BoundOrder &o = g->bord[i];
+            if (o.pb == pb && (o.valid || o.building)) {
+                if (!o.valid) return TT_OK; // another query is building it
+                o.users++;
+                o.last_use = g->order_clock;
+                *out = &o;
+                return TT_OK;
+            }
+            if (o.users) continue;
+            if (!o.valid) {
+                if (!empty) empty = &o;
+            } else if (!lru || o.last_use < lru->last_use) {
+                lru = &o;
+            }
         }
-        if (o.users) continue;
-        if (!o.valid) {
-            if (!empty) empty = &o;
-        } else if (!lru || o.last_use < lru->last_use) {
-            lru = &o;
-        }
+        slot = empty ? empty : lru;
+        if (!slot) return TT_OK;
+        if (g->m < ORDER_NOW_M && streamed_at(g, pb).entries <= ORDER_AFTER * g->m) return TT_OK;
+        // reserved: built below without the lock, so queries of other p are not held up
+        slot->valid = false;
+        slot->building = true;
+        slot->pb = pb;
+        slot->users = 1;
     }
-    BoundOrder *slot = empty ? empty : lru;
-    if (!slot) return TT_OK;
-    if (g->m < ORDER_NOW_M && streamed_at(g, pb).entries <= ORDER_AFTER * g->m) return TT_OK;
-    slot->valid = false;
     const uint64_t m = g->m;
-    int rc;
-    if (!slot->src && ((rc = dev_alloc(g, (void **)&slot->src, (m + 1) * 4)) ||
-                       (rc = dev_alloc(g, (void **)&slot->col, (m + 1) * 4)) ||
-                       (rc = dev_alloc(g, (void **)&slot->wgt, (m + 1) * 4)) ||
-                       (rc = dev_alloc(g, (void **)&slot->pos, (m + 1) * 4))))
-        return rc;
     hipStream_t s = q->stream;
     unsigned long long *dev = nullptr; // hist | base | cursors
-    if ((rc = dev_alloc(nullptr, (void **)&dev, 3 * WBINS * 8))) return rc;
     const int mode = mode_of(p);
     auto body = [&]() -> int {
+        int r;
+        if (!slot->src && ((r = dev_alloc(g, (void **)&slot->src, (m + 1) * 4)) ||
+                           (r = dev_alloc(g, (void **)&slot->col, (m + 1) * 4)) ||
+                           (r = dev_alloc(g, (void **)&slot->wgt, (m + 1) * 4)) ||
+                           (r = dev_alloc(g, (void **)&slot->pos, (m + 1) * 4))))
+            return r;
+        if ((r = dev_alloc(nullptr, (void **)&dev, 3 * WBINS * 8))) return r;
         HIP_TRY(hipMemsetAsync(dev, 0, 3 * WBINS * 8, s));
         k_bound_hist<<<enum_grid(m), 256, 0, s>>>(g->osrc, g->col, g->wgt, g->maxw, m, mode, p, dev);
         HIP_TRY(hipGetLastError());
@@ -627,21 +635,24 @@ int acquire_order(tt_graph *g, QueryCtx *q, double p, BoundOrder **out) {
         uint64_t run = 0;
         for (int b = WBINS - 1; b >= 0; b--) { slot->base[b] = run; run += slot->hist[b]; }
         HIP_TRY(hipMemcpyAsync(dev + WBINS, slot->base.data(), WBINS * 8, hipMemcpyHostToDevice, s));
-        k_place_bound<<<(unsigned)((m + BPLACE_CHUNK - 1) / BPLACE_CHUNK), 256, 0, s>>>(g->osrc, g->col, g->wgt, g->maxw, m, mode, p,
-                                                                     dev + WBINS, dev + 2 * WBINS, slot->src,
-                                                                     slot->col, slot->wgt, slot->pos);
+        const unsigned grid = (unsigned)((m + BPLACE_CHUNK - 1) / BPLACE_CHUNK);
+        k_place_bound<<<grid, 256, 0, s>>>(g->osrc, g->col, g->wgt, g->maxw, m, mode, p, dev + WBINS,
+                                           dev + 2 * WBINS, slot->src, slot->col, slot->wgt, slot->pos);
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(s));
         return TT_OK;
     };
-    rc = body();
+    int rc = body();
     (void)hipStreamSynchronize(s);
     dev_free(nullptr, dev, 0);
-    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g->init_mu);
+    slot->building = false;
+    if (rc) {
+        slot->users = 0;
+        return rc;
+    }
     slot->valid = true;
-    slot->pb = pb;
-    slot->users = 1;
-    slot->last_use = g->order_clock;
+    slot->last_use = ++g->order_clock;
     *out = slot;
     return TT_OK;
 }
