@@ -235,7 +235,7 @@ def run_batch(args):
         "cpu_baseline": cpu,
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
         "autotune": {"config": tune["config"], "growth": tune["growth"], "filter_blocks": tune["filter_blocks"],
-                     "intersect_blocks": tune["intersect_blocks"], "passes": tune["passes"], "restart_rounds": tune["restart_rounds"],
+                     "intersect_blocks": tune["intersect_blocks"], "passes": tune["passes"], "restart_rounds": tune["restart_rounds"], "merge_max": tune["merge_max"],
                      "tune_ms": tune["tune_ms"]},
         "restarts": first["stats"]["restarts"], "replays_identical": bool(same), "load_ms": load_ms,
         "single_query_path": {"graphs": len(Gs), "graphs_per_s": len(Gs) / single_s},

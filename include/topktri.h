@@ -193,6 +193,8 @@ typedef struct {
     uint32_t passes;           /* score bands captured (the last one exhaustive) */
     uint32_t restart_rounds;   /* overflow restart rounds captured after the selection */
     uint32_t restarts;         /* graphs redone because their triangle region overflowed */
+    uint32_t merge_max;        /* intersection choice: rows with at most this many entries
+                                  together are merged by one lane, longer ones binary-searched */
     double launch_ms;          /* device time of the captured sequence (HIP events) */
     double tune_ms;            /* host time spent by the autotuner in this call (first use) */
     double total_ms;           /* host wall time of the call */

@@ -52,7 +52,7 @@ class BatchStats(ctypes.Structure):
                 ("triangles_emitted", ctypes.c_uint64), ("edges_streamed", ctypes.c_uint64),
                 ("config", ctypes.c_uint32), ("growth", ctypes.c_uint32), ("filter_blocks", ctypes.c_uint32),
                 ("intersect_blocks", ctypes.c_uint32), ("passes", ctypes.c_uint32),
-                ("restart_rounds", ctypes.c_uint32), ("restarts", ctypes.c_uint32),
+                ("restart_rounds", ctypes.c_uint32), ("restarts", ctypes.c_uint32), ("merge_max", ctypes.c_uint32),
                 ("launch_ms", ctypes.c_double), ("tune_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
     def as_dict(self):

@@ -460,10 +460,12 @@ struct BatchCfg {
     uint32_t growth;        // rank ratio between consecutive bands
     uint32_t filter_mul;    // filter blocks per CU
     uint32_t inter_mul;     // intersect blocks per CU
+    uint32_t merge_max;     // intersection choice: rows up to this many entries together are merged
 };
 const BatchCfg CONFIGS[] = {
-    {4, 4, 4},  {4, 4, 8},  {4, 4, 16},  {4, 16, 4},  {4, 16, 8},  {4, 16, 16},
-    {16, 4, 4}, {16, 4, 8}, {16, 4, 16}, {16, 16, 4}, {16, 16, 8}, {16, 16, 16},
+    {4, 4, 4, 0},    {4, 4, 8, 0},    {4, 16, 4, 0},    {4, 16, 8, 0},    {16, 4, 4, 0},    {16, 4, 8, 0},
+    {4, 4, 4, 64},   {4, 4, 8, 64},   {4, 16, 4, 64},   {4, 16, 8, 64},   {16, 4, 4, 64},   {16, 4, 8, 64},
+    {4, 4, 4, 256},  {4, 4, 8, 256},  {16, 4, 4, 256},  {16, 4, 8, 256},
 };
 constexpr int NCONFIGS = (int)(sizeof(CONFIGS) / sizeof(CONFIGS[0]));
 constexpr uint32_t IN_GRAPH_RESTARTS = 2; // default restart rounds inside the captured sequence
@@ -621,6 +623,7 @@ EnumArgs batch_args(const tt_batch *b, const tt_batch::Order &o, double p, const
     A.maxw = g->maxw;
     A.vi = g->vinfo;
     A.cw = g->cw;
+    A.merge_max = c.merge_max;
     A.s_src = o.src;
     A.s_col = o.col;
     A.s_wgt = o.wgt;
@@ -1037,6 +1040,7 @@ extern "C" int batch_topk_ex(tt_batch *b, uint32_t k, double p, int config, uint
         stats->intersect_blocks = (uint32_t)num_cus() * CONFIGS[ci].inter_mul;
         stats->passes = ch.passes;
         stats->restart_rounds = ch.rounds;
+        stats->merge_max = CONFIGS[ci].merge_max;
         stats->restarts = (uint32_t)(st[5] + b->extra[5]);
         stats->candidate_edges = st[0] + b->extra[0];
         stats->intersected_entries = st[1] + b->extra[1];

@@ -148,6 +148,9 @@ struct EnumArgs {
     const uint32_t *rlen, *col, *wgt, *wcol, *wwgt, *wpos, *maxw;
     const VInfo *vi; // rstart, rlen, maxw per vertex
     const uint2 *cw; // (col, wgt) per entry
+    // a candidate whose two rows hold at most this many entries together is intersected by one
+    // lane merging the two head-sorted rows; longer ones by the wave's binary searches
+    uint32_t merge_max;
     // the stream of candidate entries (tail, head, weight, head-sorted position or NULL if the
     // stream is the head-sorted layout itself) and its length
     const uint32_t *s_src, *s_col, *s_wgt, *s_pos;
@@ -342,9 +345,61 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
 // other row's head-sorted copy.
 constexpr int MAX_SEG = 4096;
 
+// The triangle (u, v, c) with weights a = w_uv, x = w_uc, y = w_vc as a record, and whether it
+// lies in its band.
+template <bool BATCH>
+__device__ __forceinline__ bool make_rec(const EnumArgs &A, uint32_t g, uint32_t a, uint32_t x, uint32_t y,
+                                         uint32_t u, uint32_t v, uint32_t c, trec &r);
+
+// Appends the records of the lanes with ok set: one ballot and one global atomic per wave (per
+// graph present among the lanes in the batched form).
+template <bool BATCH>
+__device__ __forceinline__ void wave_emit(const EnumArgs &A, bool ok, const trec &r, uint32_t og, int lane,
+                                          unsigned long long &s_emit) {
+    const uint64_t bal = __ballot(ok);
+    if (BATCH && bal) {
+        if (lane == 0) s_emit += __popcll(bal);
+        uint64_t pend = bal;
+        while (pend) {
+            const int lead = __ffsll((unsigned long long)pend) - 1;
+            const uint32_t gl = __shfl(og, lead, 64);
+            const bool mine = ok && og == gl;
+            const uint64_t grp = __ballot(mine);
+            unsigned long long b0 = 0;
+            if (lane == lead) b0 = atomicAdd(&A.gcount[gl], (unsigned long long)__popcll(grp));
+            b0 = __shfl(b0, lead, 64);
+            const uint64_t slot = b0 + __popcll(grp & ((1ull << lane) - 1ull));
+            if (mine && slot < A.R) A.out[(uint64_t)gl * A.R + slot] = r;
+            pend &= ~grp;
+        }
+    } else if (bal) {
+        const uint32_t nb = __popcll(bal);
+        unsigned long long b0 = 0;
+        if (lane == 0) b0 = atomicAdd(A.count, (unsigned long long)nb);
+        b0 = __shfl(b0, 0, 64);
+        const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
+        if (ok && b0 + rank < A.cap) A.out[b0 + rank] = r;
+        if (lane == 0) s_emit += nb;
+    }
+}
+
 template <bool BATCH> __device__ __forceinline__ const Band &band_of(const EnumArgs &A, uint32_t g) {
     if (BATCH) return A.bands[g];
     return A.B;
+}
+
+template <bool BATCH>
+__device__ __forceinline__ bool make_rec(const EnumArgs &A, uint32_t g, uint32_t a, uint32_t x, uint32_t y,
+                                         uint32_t u, uint32_t v, uint32_t c, trec &r) {
+    const u128 key = score_key(A.B.mode, A.B.p, a, x, y);
+    uint32_t i = u, j = v, l = c, tmp;
+    if (i > j) { tmp = i; i = j; j = tmp; }
+    if (j > l) { tmp = j; j = l; l = tmp; }
+    if (i > j) { tmp = i; i = j; j = tmp; }
+    r.khi = (uint64_t)(key >> 64);
+    r.klo = (uint64_t)key;
+    r.i = i; r.j = j; r.l = l; r.pad = 0;
+    return in_band(band_of<BATCH>(A, g), key, i, j, l);
 }
 
 template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void k_intersect(EnumArgs A) {
@@ -390,9 +445,9 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
         }
         const uint32_t sg = lo_s;
         const uint64_t j = ((uint64_t)(ch - pre[sg]) << 6) + (uint64_t)lane;
-        bool pass = false;
-        uint32_t a = 0, u = 0, v = 0, qA = 0, Blen = 0, fl = 0, g = 0;
-        uint64_t Ab = 0, Bb = 0, zB = 0;
+        bool pass = false, merge = false;
+        uint32_t a = 0, u = 0, v = 0, qA = 0, Blen = 0, fl = 0, g = 0, ml = 0, mvl = 0;
+        uint64_t Ab = 0, Bb = 0, zB = 0, mub = 0, mvb = 0, mzu = 0, mzv = 0;
         if (j < A.ccnt[sg]) {
             const cand c = A.C[(uint64_t)sg * seg + j];
             u = c.u;
@@ -408,6 +463,11 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
             if (FILTER == FILTER_VERTICES && !A.vflag[u] && !A.vflag[v]) fl |= FL_REQ_C;
             const uint64_t zu = min_other(B, a, Wv), zv = min_other(B, a, Wu);
             pass = zu <= Wu && zv <= Wv;
+            if (pass && ul + vl <= A.merge_max) {
+                merge = true;
+                pass = false;
+                mub = ub; ml = ul; mvb = vb; mvl = vl; mzu = zu; mzv = zv;
+            }
             if (pass) {
                 uint32_t qu, qv;
                 count_pair(A.wwgt, ub, ul, zu, vb, vl, zv, qu, qv);
@@ -472,47 +532,40 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
                             if (ofl & FL_REQ_B) adm = adm && markB;
                             adm = adm && ((ofl & FL_MARK_UV) || markA || markB);
                         }
-                        if (adm) {
-                            const u128 key = score_key(A.B.mode, A.B.p, oa, x, y);
-                            uint32_t i = ou, j = ov, l = c, tmp;
-                            if (i > j) { tmp = i; i = j; j = tmp; }
-                            if (j > l) { tmp = j; j = l; l = tmp; }
-                            if (i > j) { tmp = i; i = j; j = tmp; }
-                            ok = in_band(band_of<BATCH>(A, og), key, i, j, l);
-                            r.khi = (uint64_t)(key >> 64);
-                            r.klo = (uint64_t)key;
-                            r.i = i; r.j = j; r.l = l; r.pad = 0;
-                        }
+                        if (adm) ok = make_rec<BATCH>(A, og, oa, x, y, ou, ov, c, r);
                     }
                 }
             }
-            const uint64_t bal = __ballot(ok);
-            if (BATCH && bal) {
-                // one atomic per graph present among the emitting lanes
-                if (lane == 0) s_emit += __popcll(bal);
-                uint64_t pend = bal;
-                while (pend) {
-                    const int lead = __ffsll((unsigned long long)pend) - 1;
-                    const uint32_t gl = __shfl(og, lead, 64);
-                    const bool mine = ok && og == gl;
-                    const uint64_t grp = __ballot(mine);
-                    unsigned long long b0 = 0;
-                    if (lane == lead) b0 = atomicAdd(&A.gcount[gl], (unsigned long long)__popcll(grp));
-                    b0 = __shfl(b0, lead, 64);
-                    const uint64_t slot = b0 + __popcll(grp & ((1ull << lane) - 1ull));
-                    if (mine && slot < A.R) A.out[(uint64_t)gl * A.R + slot] = r;
-                    pend &= ~grp;
-                }
-            } else if (bal) {
-                const uint32_t nb = __popcll(bal);
-                unsigned long long b0 = 0;
-                if (lane == 0) b0 = atomicAdd(A.count, (unsigned long long)nb);
-                b0 = __shfl(b0, 0, 64);
-                const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
-                if (ok && b0 + rank < A.cap) A.out[b0 + rank] = r;
-                if (lane == 0) s_emit += nb;
-            }
+            wave_emit<BATCH>(A, ok, r, og, lane, s_emit);
         }
+        // short rows: each such lane merges the two head-sorted rows (weights below their
+        // floors skipped), one step per iteration, emitting with the whole wave
+        const uint32_t msteps = wave_max(merge ? ml + mvl : 0u);
+        uint32_t mi = 0, mj = 0;
+        for (uint32_t step = 0; step < msteps; step++) {
+            bool ok = false;
+            trec r;
+            if (merge && mi < ml && mj < mvl) {
+                const uint2 xu = A.cw[mub + mi], xv = A.cw[mvb + mj];
+                if (xu.x < xv.x) {
+                    mi++;
+                } else if (xv.x < xu.x) {
+                    mj++;
+                } else {
+                    const uint32_t c = xu.x;
+                    bool adm = (uint64_t)xu.y >= mzu && (uint64_t)xv.y >= mzv;
+                    if (FILTER == FILTER_VERTICES && (fl & FL_REQ_C)) adm = adm && A.vflag[c];
+                    if (FILTER == FILTER_EDGES)
+                        adm = adm && ((fl & FL_MARK_UV) || A.emark[mub + mi] || A.emark[mvb + mj]);
+                    if (adm) ok = make_rec<BATCH>(A, g, a, xu.y, xv.y, u, v, c, r);
+                    mi++;
+                    mj++;
+                }
+            }
+            wave_emit<BATCH>(A, ok, r, g, lane, s_emit);
+        }
+        const uint32_t consumed = wave_sum(merge ? mi + mj : 0u);
+        if (lane == 0) s_inter += consumed;
     }
     if (lane == 0) {
         stat_add(A.stats, 1, s_inter);

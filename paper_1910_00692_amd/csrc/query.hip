@@ -386,6 +386,10 @@ __global__ __launch_bounds__(256) void k_place_bound(const uint32_t *osrc, const
 }
 
 // ----------------------------------------------------------------------------- host side
+// Candidates whose two rows hold at most this many entries together are intersected by a
+// lane-local merge (sequential reads of both rows) instead of binary searches.
+constexpr uint32_t MERGE_MAX = 64;
+
 // The weight of (a lower bound of) the M-th heaviest edge, from the load-time histogram.
 uint32_t weight_at_rank(const std::vector<uint64_t> &h, uint64_t M) {
     uint64_t cum = 0;
@@ -688,6 +692,7 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
     A.maxw = g->maxw;
     A.vi = g->vinfo;
     A.cw = g->cw;
+    A.merge_max = MERGE_MAX;
     A.skip = gated ? q->dcount + 7 : nullptr;
     A.B = B;
     A.emark = g->emark;
