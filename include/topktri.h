@@ -231,8 +231,14 @@ uint64_t graph_num_edges(const tt_graph *g);
 /* Device bytes held by the graph (CSR, copies and cached scratch). */
 uint64_t graph_device_bytes(const tt_graph *g);
 
-/* Releases every resource of g.  NULL-safe. */
+/* Releases every resource of g.  NULL-safe.  Its device blocks go to a process-wide cache
+ * (per device, up to half of that device's memory) that later loads, queries and batches reuse. */
 void graph_free(tt_graph *g);
+
+/* Returns every cached device block of every device to the driver; blocks in use by live graphs,
+ * batches or servers are untouched.  Returns the bytes released.  Call it when other code in the
+ * process (e.g. a tensor allocator) needs the memory.  Thread-safe; never fails. */
+uint64_t tt_trim_cache(void);
 
 /* Message for the last error on the calling thread ("" if none).  Valid until the next call. */
 const char *tt_last_error(void);

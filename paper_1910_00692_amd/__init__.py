@@ -26,7 +26,7 @@ EXPORTED = ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles
             "sample_heavy_triangles_ex", "graph_num_vertices", "graph_num_edges", "graph_device_bytes",
             "graph_free", "tt_last_error", "server_create", "server_request_bytes", "server_submit", "server_poll",
             "server_wait", "server_info", "server_destroy", "batch_load", "batch_load_device", "batch_topk",
-            "batch_topk_ex", "batch_num_configs", "batch_num_graphs", "batch_free")
+            "batch_topk_ex", "batch_num_configs", "batch_num_graphs", "batch_free", "tt_trim_cache")
 TT_BATCH_EAGER = 1
 
 
@@ -109,6 +109,8 @@ def library():
         lib.graph_free.restype = None
         lib.tt_last_error.argtypes = []
         lib.tt_last_error.restype = ctypes.c_char_p
+        lib.tt_trim_cache.argtypes = []
+        lib.tt_trim_cache.restype = u64
         p64 = ctypes.POINTER(ctypes.c_uint64)
         pint = ctypes.POINTER(ctypes.c_int)
         lib.server_create.argtypes = [vp, u32, u64, pg]
@@ -380,3 +382,8 @@ class Batch:
 
 def load(n, src, dst, w, stream=None) -> Graph:
     return Graph(n, src, dst, w, stream=stream)
+
+
+def trim_cache() -> int:
+    """Hands every cached device block back to the driver (tt_trim_cache); returns the bytes."""
+    return int(library().tt_trim_cache())

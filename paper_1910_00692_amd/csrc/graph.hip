@@ -28,15 +28,21 @@ int fail(int code, const std::string &msg) {
 }
 extern "C" const char *tt_last_error(void) { return g_last_error.c_str(); }
 
-// Device memory comes from a process-wide cache of freed blocks (exact rounded sizes), so that
-// repeated loads and queries do not pay for hipMalloc/hipFree.  Blocks are only returned to the
-// cache after the work that used them has completed on its stream.
+// Device memory comes from a process-wide cache of freed blocks (exact rounded sizes, per
+// device), so that repeated loads and queries do not pay for hipMalloc/hipFree: returning a large
+// block to the driver and asking for it again costs far more than the work that uses it.  The
+// cache holds up to half of each device's memory; tt_trim_cache() hands it all back.  Blocks are
+// only returned to the cache after the work that used them has completed on its stream.
 namespace {
+struct Block {
+    size_t size;
+    int device;
+};
 std::mutex g_pool_mu;
-std::multimap<size_t, void *> g_pool;         // free blocks by size
-std::unordered_map<void *, size_t> g_live;    // size of every block handed out
-size_t g_pool_bytes = 0;
-constexpr size_t POOL_CAP = 16ull << 30;
+std::multimap<std::pair<int, size_t>, void *> g_pool;  // free blocks by (device, size)
+std::unordered_map<void *, Block> g_live;             // every block handed out
+std::unordered_map<int, size_t> g_pool_bytes;         // cached bytes per device
+std::unordered_map<int, size_t> g_pool_cap;           // cache limit per device
 
 size_t round_size(size_t b) {
     if (b == 0) b = 16;
@@ -47,27 +53,55 @@ size_t round_size(size_t b) {
     return (b + step - 1) / step * step;
 }
 
-void pool_release_all() {
-    for (auto &kv : g_pool) (void)hipFree(kv.second);
-    g_pool.clear();
-    g_pool_bytes = 0;
+// Caller holds g_pool_mu.  Frees every cached block (of one device, or of all when dev < 0).
+size_t pool_release(int dev) {
+    size_t freed = 0;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    for (auto it = g_pool.begin(); it != g_pool.end();) {
+        if (dev >= 0 && it->first.first != dev) { ++it; continue; }
+        (void)hipSetDevice(it->first.first);
+        (void)hipFree(it->second);
+        freed += it->first.second;
+        g_pool_bytes[it->first.first] -= it->first.second;
+        it = g_pool.erase(it);
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+    return freed;
+}
+
+size_t pool_cap(int dev) {
+    auto it = g_pool_cap.find(dev);
+    if (it != g_pool_cap.end()) return it->second;
+    size_t cap = 16ull << 30, total = 0;
+    if (hipDeviceTotalMem(&total, dev) == hipSuccess && total) cap = total / 2;
+    else (void)hipGetLastError();
+    g_pool_cap[dev] = cap;
+    return cap;
 }
 } // namespace
+
+extern "C" uint64_t tt_trim_cache(void) {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    return pool_release(-1);
+}
 
 int dev_alloc(tt_graph *g, void **p, size_t bytes) {
     *p = nullptr;
     const size_t sz = round_size(bytes);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> lock(g_pool_mu);
-    auto it = g_pool.find(sz);
+    auto it = g_pool.find({dev, sz});
     if (it != g_pool.end()) {
         *p = it->second;
         g_pool.erase(it);
-        g_pool_bytes -= sz;
+        g_pool_bytes[dev] -= sz;
     } else {
         hipError_t e = hipMalloc(p, sz);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            pool_release_all();
+            pool_release(dev);
             e = hipMalloc(p, sz);
         }
         if (e != hipSuccess) {
@@ -76,7 +110,7 @@ int dev_alloc(tt_graph *g, void **p, size_t bytes) {
             return fail(TT_E_NOMEM, "hipMalloc(" + std::to_string(sz) + " bytes) failed: " + hipGetErrorString(e));
         }
     }
-    g_live[*p] = sz;
+    g_live[*p] = {sz, dev};
     if (g) g->bytes += sz;
     return TT_OK;
 }
@@ -87,14 +121,18 @@ void dev_free(tt_graph *g, void *p, size_t) {
     std::lock_guard<std::mutex> lock(g_pool_mu);
     auto it = g_live.find(p);
     if (it == g_live.end()) return;
-    const size_t sz = it->second;
+    const Block blk = it->second;
     g_live.erase(it);
-    if (g) g->bytes -= sz;
-    if (g_pool_bytes + sz <= POOL_CAP) {
-        g_pool.insert({sz, p});
-        g_pool_bytes += sz;
+    if (g) g->bytes -= blk.size;
+    if (g_pool_bytes[blk.device] + blk.size <= pool_cap(blk.device)) {
+        g_pool.insert({{blk.device, blk.size}, p});
+        g_pool_bytes[blk.device] += blk.size;
     } else {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(blk.device);
         (void)hipFree(p);
+        if (cur >= 0) (void)hipSetDevice(cur);
     }
 }
 

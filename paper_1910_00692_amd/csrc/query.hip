@@ -143,15 +143,36 @@ template <typename T> __device__ __forceinline__ uint64_t first_above(const T *P
 // Guide table (cut points): G[j] = the edge picked by x = j * 2^(64-bits), j = 0 .. 2^bits - 1,
 // and G[2^bits] = m - 1.  The draw rule is monotone in x, so every x in bucket j picks an edge
 // in [G[j], G[j+1]]; a draw then searches only that range, with the same result.
+// Each thread fills GUIDE_RUN consecutive cut points: a full search for the first, then a
+// galloping search that starts at the previous cut point (the cut points never decrease).
+constexpr uint32_t GUIDE_RUN = 16;
+
 template <int KIND>
 __global__ __launch_bounds__(256) void k_es_guide(const void *prefix, uint64_t m, uint32_t bits, uint32_t *G) {
     typedef typename Draw<KIND>::T T;
     const T *P = (const T *)prefix;
-    const uint64_t nb = 1ull << bits;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= nb; j += (uint64_t)gridDim.x * blockDim.x) {
-        if (j == nb) { G[j] = (uint32_t)(m - 1); continue; }
-        const uint64_t x = j << (64 - bits);
-        G[j] = (uint32_t)first_above<T>(P, 0, m - 1, Draw<KIND>::r(P, m, x));
+    const uint64_t nb = 1ull << bits, runs = (nb + GUIDE_RUN - 1) / GUIDE_RUN;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= runs; t += (uint64_t)gridDim.x * blockDim.x) {
+        if (t == runs) { G[nb] = (uint32_t)(m - 1); continue; }
+        const uint64_t j0 = t * GUIDE_RUN, j1 = j0 + GUIDE_RUN < nb ? j0 + GUIDE_RUN : nb;
+        uint64_t e = first_above<T>(P, 0, m - 1, Draw<KIND>::r(P, m, j0 << (64 - bits)));
+        G[j0] = (uint32_t)e;
+        for (uint64_t j = j0 + 1; j < j1; j++) {
+            const T r = Draw<KIND>::r(P, m, j << (64 - bits));
+            if (e < m - 1 && !(P[e] > r)) {
+                // P[lo] <= r; double the step until P[hi] > r or hi reaches m - 1
+                uint64_t lo = e, hi, step = 1;
+                for (;;) {
+                    hi = lo + step;
+                    if (hi >= m - 1) { hi = m - 1; break; }
+                    if (P[hi] > r) break;
+                    lo = hi;
+                    step <<= 1;
+                }
+                e = first_above<T>(P, lo + 1, hi, r);
+            }
+            G[j] = (uint32_t)e;
+        }
     }
 }
 
@@ -974,8 +995,8 @@ int sample_table(tt_graph *g, double qexp, int kind, tt_graph::SampleTable **out
     if (!t->guide && (rc = dev_alloc(g, (void **)&t->guide, ((1ull << g->guide_bits) + 1) * 4))) return rc;
     t->q = -1.0;
     if ((rc = inclusive_weight_prefix(g, qexp, t->prefix))) return rc;
-    const uint64_t nb = (1ull << g->guide_bits) + 1;
-    const unsigned grid = (unsigned)std::min<uint64_t>((nb + 255) / 256, (uint64_t)num_cus() * 16);
+    const uint64_t runs = ((1ull << g->guide_bits) + GUIDE_RUN - 1) / GUIDE_RUN + 1;
+    const unsigned grid = (unsigned)std::min<uint64_t>((runs + 255) / 256, (uint64_t)num_cus() * 16);
     if (kind == 0) k_es_guide<0><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
     else if (kind == 1) k_es_guide<1><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
     else k_es_guide<2><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
