@@ -624,6 +624,7 @@ EnumArgs batch_args(const tt_batch *b, const tt_batch::Order &o, double p, const
     A.vi = g->vinfo;
     A.cw = g->cw;
     A.merge_max = c.merge_max;
+    A.scan_max = SCAN_MAX;
     A.s_src = o.src;
     A.s_col = o.col;
     A.s_wgt = o.wgt;
@@ -652,8 +653,14 @@ __global__ void k_goff(const uint64_t *boff, uint32_t count, uint64_t *goff) {
 int enqueue_pass(tt_batch *b, const EnumArgs &A, const BatchCfg &c) {
     hipStream_t s = b->stream;
     k_bscan<<<1, 1024, 0, s>>>(b->Eg, b->count, b->poff);
-    k_filter<FILTER_NONE, true><<<A.nseg, 256, 0, s>>>(A);
-    k_intersect<FILTER_NONE, true><<<(unsigned)num_cus() * c.inter_mul, 256, 0, s>>>(A);
+    const unsigned igrid = (unsigned)num_cus() * c.inter_mul;
+    if (A.B.mode == MODE_GEN) {
+        k_filter<FILTER_NONE, true, true><<<A.nseg, 256, 0, s>>>(A);
+        k_intersect<FILTER_NONE, true, true><<<igrid, 256, 0, s>>>(A);
+    } else {
+        k_filter<FILTER_NONE, true, false><<<A.nseg, 256, 0, s>>>(A);
+        k_intersect<FILTER_NONE, true, false><<<igrid, 256, 0, s>>>(A);
+    }
     HIP_TRY(hipGetLastError());
     return TT_OK;
 }

@@ -19,19 +19,31 @@ __device__ double gen_mean(double p, double a, double b, double c) {
     return s * exp(log1p(acc / 3.0) / p);
 }
 
-__device__ __forceinline__ u128 score_key(int mode, double p, uint32_t a, uint32_t b, uint32_t c) {
+// Order key of the integer modes (every mode but the generic p).
+__device__ __forceinline__ u128 int_key(int mode, uint32_t a, uint32_t b, uint32_t c) {
     switch (mode) {
     case MODE_MAX: return (u128)max(a, max(b, c));
     case MODE_MIN: return (u128)min(a, min(b, c));
     case MODE_SUM: return (u128)((uint64_t)a + b + c);
     case MODE_SUMSQ: return (u128)((uint64_t)a * a) + (u128)((uint64_t)b * b) + (u128)((uint64_t)c * c);
-    case MODE_PROD: {
+    default: { // MODE_PROD
         const uint64_t ab = (uint64_t)a * b;
         const uint64_t lo = ab * (uint64_t)c, hi = __umul64hi(ab, (uint64_t)c);
         return ((u128)hi << 64) | lo;
     }
-    default: return (u128)(uint64_t)__double_as_longlong(gen_mean(p, (double)a, (double)b, (double)c));
     }
+}
+
+// The kernels of a pass are compiled twice: GEN for the generic p (FP64 bits of Eq. 1) and
+// !GEN for the integer modes, which then carry none of the transcendental code (and need far
+// fewer registers).
+template <bool GEN> __device__ __forceinline__ u128 score_key_t(int mode, double p, uint32_t a, uint32_t b, uint32_t c) {
+    if (GEN) return (u128)(uint64_t)__double_as_longlong(gen_mean(p, (double)a, (double)b, (double)c));
+    return int_key(mode, a, b, c);
+}
+
+__device__ __forceinline__ u128 score_key(int mode, double p, uint32_t a, uint32_t b, uint32_t c) {
+    return mode == MODE_GEN ? score_key_t<true>(mode, p, a, b, c) : int_key(mode, a, b, c);
 }
 
 __device__ double key_to_score(int mode, u128 key) {
@@ -72,9 +84,9 @@ struct Band {
 };
 
 // key(a, Wu, Wv) >= L : no triangle on this entry can reach the band otherwise
-__device__ __forceinline__ bool bound_ok(const Band &B, uint32_t a, uint32_t Wu, uint32_t Wv) {
+template <bool GEN> __device__ __forceinline__ bool bound_ok(const Band &B, uint32_t a, uint32_t Wu, uint32_t Wv) {
     if (B.L == 0) return true;
-    if (B.mode == MODE_GEN) {
+    if (GEN) {
         // cheap upper bounds first: m_p <= max for every p, m_p <= arithmetic mean for p <= 1
         const double lim = B.theta * (1.0 - 1e-12);
         const double da = (double)a, du = (double)Wu, dv = (double)Wv;
@@ -82,7 +94,7 @@ __device__ __forceinline__ bool bound_ok(const Band &B, uint32_t a, uint32_t Wu,
         if (B.p <= 1.0 && (da + du + dv) / 3.0 < lim * (1.0 - 1e-12)) return false;
         return gen_mean(B.p, da, du, dv) >= lim;
     }
-    return score_key(B.mode, B.p, a, Wu, Wv) >= B.L;
+    return int_key(B.mode, a, Wu, Wv) >= B.L;
 }
 
 // Smallest weight x (never above the exact one) with m_p(a, x, W) >= theta, generic p.
@@ -107,8 +119,9 @@ __host__ __device__ uint64_t gen_min_other(double p, double theta, double a, dou
 }
 
 // Smallest weight x (a lower bound of it) for which key(a, x, W) can still reach L.
-__device__ __forceinline__ uint64_t min_other(const Band &B, uint32_t a, uint32_t W) {
+template <bool GEN> __device__ __forceinline__ uint64_t min_other(const Band &B, uint32_t a, uint32_t W) {
     if (B.L == 0) return 0;
+    if (GEN) return gen_min_other(B.p, B.theta, (double)a, (double)W);
     switch (B.mode) {
     case MODE_MAX: return ((u128)a >= B.L || (u128)W >= B.L) ? 0 : (uint64_t)B.L;
     case MODE_MIN: return (uint64_t)B.L;
@@ -122,14 +135,13 @@ __device__ __forceinline__ uint64_t min_other(const Band &B, uint32_t a, uint32_
         const uint64_t z = (uint64_t)sqrt(u128_to_double(B.L - aw));
         return z > 1 ? z - 1 : 0;
     }
-    case MODE_PROD: {
+    default: { // MODE_PROD
         const double q = u128_to_double(B.L) / ((double)a * (double)W);
         if (q <= 1.0) return 0;
         if (q >= 1.8e19) return ~0ull;
         const uint64_t z = (uint64_t)q;
         return z > 1 ? z - 1 : 0;
     }
-    default: return gen_min_other(B.p, B.theta, (double)a, (double)W);
     }
 }
 
@@ -142,6 +154,8 @@ __device__ __forceinline__ bool in_band(const Band &B, u128 key, uint32_t i, uin
 // ----------------------------------------------------------------------------- enumeration
 enum { FILTER_NONE = 0, FILTER_EDGES = 1, FILTER_VERTICES = 2 };
 enum { FL_MARK_UV = 1, FL_REQ_A = 2, FL_REQ_B = 4, FL_REQ_C = 8 };
+// Admissible entries of the other row scanned instead of a binary search (EnumArgs::scan_max).
+constexpr uint32_t SCAN_MAX = 32;
 
 struct EnumArgs {
     const uint64_t *rstart;
@@ -151,6 +165,10 @@ struct EnumArgs {
     // a candidate whose two rows hold at most this many entries together is intersected by one
     // lane merging the two head-sorted rows; longer ones by the wave's binary searches
     uint32_t merge_max;
+    // an entry of the iterated row is looked up in the other row by scanning that row's
+    // admissible entries (the leading ones of its weight-sorted copy) when there are at most
+    // this many, else by a binary search of its head-sorted row
+    uint32_t scan_max;
     // the stream of candidate entries (tail, head, weight, head-sorted position or NULL if the
     // stream is the head-sorted layout itself) and its length
     const uint32_t *s_src, *s_col, *s_wgt, *s_pos;
@@ -203,17 +221,38 @@ __device__ __forceinline__ uint32_t count_at_least(const uint32_t *ww, uint64_t 
 
 // Number of entries of two weight-sorted rows at or above their floors; both binary searches
 // advance together so that their loads overlap.
+// q1, q2 = the number of entries of each weight-descending row with weight >= its floor (a
+// floor of 0 counts the whole row).  Those entries lead their rows, and there are usually few,
+// so each count is found by galloping from the row's start (probes at 0, 2, 6, 14, ...) and
+// then a binary search between the last two probes: a handful of loads from the row's first
+// lines instead of a search over the whole row.  The two searches are interleaved.
 __device__ __forceinline__ void count_pair(const uint32_t *ww, uint64_t b1, uint32_t n1, uint64_t z1, uint64_t b2,
                                            uint32_t n2, uint64_t z2, uint32_t &q1, uint32_t &q2) {
-    uint32_t lo1 = z1 ? 0 : n1, hi1 = n1, lo2 = z2 ? 0 : n2, hi2 = n2;
-    while (lo1 < hi1 || lo2 < hi2) {
-        if (lo1 < hi1) {
-            const uint32_t mid = (lo1 + hi1) >> 1;
-            if ((uint64_t)ww[b1 + mid] >= z1) lo1 = mid + 1; else hi1 = mid;
+    // the count lies in [lo, up]: entries before lo reach the floor, entries from up on do not
+    uint32_t lo1 = z1 ? 0 : n1, up1 = n1, lo2 = z2 ? 0 : n2, up2 = n2, s1 = 1, s2 = 1;
+    bool g1 = lo1 < up1, g2 = lo2 < up2;
+    while (g1 || g2) {
+        if (g1) {
+            const uint32_t i = lo1 + s1 - 1;
+            if (i >= up1) g1 = false;
+            else if ((uint64_t)ww[b1 + i] >= z1) { lo1 = i + 1; s1 <<= 1; }
+            else { up1 = i; g1 = false; }
         }
-        if (lo2 < hi2) {
-            const uint32_t mid = (lo2 + hi2) >> 1;
-            if ((uint64_t)ww[b2 + mid] >= z2) lo2 = mid + 1; else hi2 = mid;
+        if (g2) {
+            const uint32_t i = lo2 + s2 - 1;
+            if (i >= up2) g2 = false;
+            else if ((uint64_t)ww[b2 + i] >= z2) { lo2 = i + 1; s2 <<= 1; }
+            else { up2 = i; g2 = false; }
+        }
+    }
+    while (lo1 < up1 || lo2 < up2) {
+        if (lo1 < up1) {
+            const uint32_t mid = (lo1 + up1) >> 1;
+            if ((uint64_t)ww[b1 + mid] >= z1) lo1 = mid + 1; else up1 = mid;
+        }
+        if (lo2 < up2) {
+            const uint32_t mid = (lo2 + up2) >> 1;
+            if ((uint64_t)ww[b2 + mid] >= z2) lo2 = mid + 1; else up2 = mid;
         }
     }
     q1 = lo1;
@@ -268,7 +307,7 @@ __device__ __forceinline__ uint32_t graph_search(const uint64_t *poff, uint32_t 
     return graph_bsearch(poff, 0, ng, e);
 }
 
-template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void k_filter(EnumArgs A) {
+template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) void k_filter(EnumArgs A) {
     __shared__ uint32_t lcount;
     if (A.skip && *A.skip) return; // written only between passes
     uint64_t E, seg;
@@ -314,8 +353,8 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
                 if (FILTER == FILTER_EDGES) pre = A.emark[pos[k]] || A.vflag[u[k]] || A.vflag[v[k]];
                 else if (FILTER == FILTER_VERTICES)
                     pre = A.vflag[u[k]] || A.vflag[v[k]] || (A.vflag2[u[k]] && A.vflag2[v[k]]);
-                if (BATCH) pass[k] = bound_ok(A.bands[pos[k]], a[k], A.maxw[u[k]], A.maxw[v[k]]);
-                else pass[k] = pre && bound_ok(A.B, a[k], A.maxw[u[k]], A.maxw[v[k]]);
+                if (BATCH) pass[k] = bound_ok<GEN>(A.bands[pos[k]], a[k], A.maxw[u[k]], A.maxw[v[k]]);
+                else pass[k] = pre && bound_ok<GEN>(A.B, a[k], A.maxw[u[k]], A.maxw[v[k]]);
             }
             const uint64_t bal = __ballot(pass[k]);
             rank[k] = n_pass + __popcll(bal & ((1ull << lane) - 1ull));
@@ -347,7 +386,7 @@ constexpr int MAX_SEG = 4096;
 
 // The triangle (u, v, c) with weights a = w_uv, x = w_uc, y = w_vc as a record, and whether it
 // lies in its band.
-template <bool BATCH>
+template <bool BATCH, bool GEN>
 __device__ __forceinline__ bool make_rec(const EnumArgs &A, uint32_t g, uint32_t a, uint32_t x, uint32_t y,
                                          uint32_t u, uint32_t v, uint32_t c, trec &r);
 
@@ -388,10 +427,10 @@ template <bool BATCH> __device__ __forceinline__ const Band &band_of(const EnumA
     return A.B;
 }
 
-template <bool BATCH>
+template <bool BATCH, bool GEN>
 __device__ __forceinline__ bool make_rec(const EnumArgs &A, uint32_t g, uint32_t a, uint32_t x, uint32_t y,
                                          uint32_t u, uint32_t v, uint32_t c, trec &r) {
-    const u128 key = score_key(A.B.mode, A.B.p, a, x, y);
+    const u128 key = score_key_t<GEN>(A.B.mode, A.B.p, a, x, y);
     uint32_t i = u, j = v, l = c, tmp;
     if (i > j) { tmp = i; i = j; j = tmp; }
     if (j > l) { tmp = j; j = l; l = tmp; }
@@ -402,7 +441,7 @@ __device__ __forceinline__ bool make_rec(const EnumArgs &A, uint32_t g, uint32_t
     return in_band(band_of<BATCH>(A, g), key, i, j, l);
 }
 
-template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void k_intersect(EnumArgs A) {
+template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) void k_intersect(EnumArgs A) {
     __shared__ uint32_t pre[MAX_SEG + 1]; // exclusive prefix of 64-candidate chunks per segment
     __shared__ uint32_t wsum[4];
     if (A.skip && *A.skip) return;
@@ -446,7 +485,7 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
         const uint32_t sg = lo_s;
         const uint64_t j = ((uint64_t)(ch - pre[sg]) << 6) + (uint64_t)lane;
         bool pass = false, merge = false;
-        uint32_t a = 0, u = 0, v = 0, qA = 0, Blen = 0, fl = 0, g = 0, ml = 0, mvl = 0;
+        uint32_t a = 0, u = 0, v = 0, qA = 0, qB = 0, Blen = 0, fl = 0, g = 0, ml = 0, mvl = 0;
         uint64_t Ab = 0, Bb = 0, zB = 0, mub = 0, mvb = 0, mzu = 0, mzv = 0;
         if (j < A.ccnt[sg]) {
             const cand c = A.C[(uint64_t)sg * seg + j];
@@ -461,7 +500,7 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
             const uint32_t ul = iu.rlen, vl = iv.rlen;
             if (FILTER == FILTER_EDGES && A.emark[c.pos]) fl |= FL_MARK_UV;
             if (FILTER == FILTER_VERTICES && !A.vflag[u] && !A.vflag[v]) fl |= FL_REQ_C;
-            const uint64_t zu = min_other(B, a, Wv), zv = min_other(B, a, Wu);
+            const uint64_t zu = min_other<GEN>(B, a, Wv), zv = min_other<GEN>(B, a, Wu);
             pass = zu <= Wu && zv <= Wv;
             if (pass && ul + vl <= A.merge_max) {
                 merge = true;
@@ -473,6 +512,7 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
                 count_pair(A.wwgt, ub, ul, zu, vb, vl, zv, qu, qv);
                 const bool uA = qu <= qv;
                 qA = uA ? qu : qv;
+                qB = uA ? qv : qu;
                 Ab = uA ? ub : vb;
                 Bb = uA ? vb : ub;
                 Blen = uA ? vl : ul;
@@ -502,8 +542,8 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
             }
             const uint32_t o_incl = __shfl(incl, s, 64), o_work = __shfl(work, s, 64);
             const uint64_t oAb = __shfl(Ab, s, 64), oBb = __shfl(Bb, s, 64), ozB = __shfl(zB, s, 64);
-            const uint32_t oBlen = __shfl(Blen, s, 64), oa = __shfl(a, s, 64), ou = __shfl(u, s, 64),
-                           ov = __shfl(v, s, 64), ofl = __shfl(fl, s, 64);
+            const uint32_t oBlen = __shfl(Blen, s, 64), oqB = __shfl(qB, s, 64), oa = __shfl(a, s, 64),
+                           ou = __shfl(u, s, 64), ov = __shfl(v, s, 64), ofl = __shfl(fl, s, 64);
             const uint32_t og = BATCH ? __shfl(g, s, 64) : 0u;
             bool ok = false;
             trec r;
@@ -517,7 +557,23 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
                     markA = A.emark[A.wpos[pa]];
                     if (ofl & FL_REQ_A) go = markA;
                 }
-                if (go) {
+                if (go && oqB <= A.scan_max) {
+                    // the other row's admissible entries are the oqB leading ones of its
+                    // weight-sorted copy: look for c among them
+                    uint32_t hit = oqB;
+                    for (uint32_t t2 = 0; t2 < oqB; t2++)
+                        if (A.wcol[oBb + t2] == c) { hit = t2; break; }
+                    if (hit < oqB) {
+                        const uint32_t y = A.wwgt[oBb + hit];
+                        bool adm = true;
+                        if (FILTER == FILTER_EDGES) {
+                            const uint8_t markB = A.emark[A.wpos[oBb + hit]];
+                            if (ofl & FL_REQ_B) adm = markB;
+                            adm = adm && ((ofl & FL_MARK_UV) || markA || markB);
+                        }
+                        if (adm) ok = make_rec<BATCH, GEN>(A, og, oa, x, y, ou, ov, c, r);
+                    }
+                } else if (go) {
                     uint64_t lo = oBb, hi = oBb + oBlen;
                     while (lo < hi) {
                         const uint64_t mid = (lo + hi) >> 1;
@@ -532,7 +588,7 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
                             if (ofl & FL_REQ_B) adm = adm && markB;
                             adm = adm && ((ofl & FL_MARK_UV) || markA || markB);
                         }
-                        if (adm) ok = make_rec<BATCH>(A, og, oa, x, y, ou, ov, c, r);
+                        if (adm) ok = make_rec<BATCH, GEN>(A, og, oa, x, y, ou, ov, c, r);
                     }
                 }
             }
@@ -557,7 +613,7 @@ template <int FILTER, bool BATCH = false> __global__ __launch_bounds__(256) void
                     if (FILTER == FILTER_VERTICES && (fl & FL_REQ_C)) adm = adm && A.vflag[c];
                     if (FILTER == FILTER_EDGES)
                         adm = adm && ((fl & FL_MARK_UV) || A.emark[mub + mi] || A.emark[mvb + mj]);
-                    if (adm) ok = make_rec<BATCH>(A, g, a, xu.y, xv.y, u, v, c, r);
+                    if (adm) ok = make_rec<BATCH, GEN>(A, g, a, xu.y, xv.y, u, v, c, r);
                     mi++;
                     mj++;
                 }

@@ -697,6 +697,21 @@ int ensure_band_events(QueryCtx *q, size_t pairs) {
     return TT_OK;
 }
 
+// The filter and intersect kernels of one stream chunk, in the instantiation of the filter
+// mode and of the kind of key (generic p or integer).
+template <bool GEN> void enqueue_pair(int filter, const EnumArgs &A, unsigned igrid, hipStream_t s) {
+    if (filter == FILTER_EDGES) {
+        k_filter<FILTER_EDGES, false, GEN><<<A.nseg, 256, 0, s>>>(A);
+        k_intersect<FILTER_EDGES, false, GEN><<<igrid, 256, 0, s>>>(A);
+    } else if (filter == FILTER_VERTICES) {
+        k_filter<FILTER_VERTICES, false, GEN><<<A.nseg, 256, 0, s>>>(A);
+        k_intersect<FILTER_VERTICES, false, GEN><<<igrid, 256, 0, s>>>(A);
+    } else {
+        k_filter<FILTER_NONE, false, GEN><<<A.nseg, 256, 0, s>>>(A);
+        k_intersect<FILTER_NONE, false, GEN><<<igrid, 256, 0, s>>>(A);
+    }
+}
+
 // Enqueues one enumeration pass (no host synchronisation): the band's stream is filtered and
 // intersected in pieces of at most cand_cap entries.  `slot` picks its event pair.
 int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool gated, size_t slot) {
@@ -714,6 +729,7 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
     A.vi = g->vinfo;
     A.cw = g->cw;
     A.merge_max = MERGE_MAX;
+    A.scan_max = SCAN_MAX;
     A.skip = gated ? q->dcount + 7 : nullptr;
     A.B = B;
     A.emark = g->emark;
@@ -737,16 +753,8 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
         A.nseg = filter_grid(E);
         A.seg = (E + A.nseg - 1) / A.nseg;
         const unsigned igrid = (unsigned)num_cus() * 8;
-        if (filter == FILTER_EDGES) {
-            k_filter<FILTER_EDGES><<<A.nseg, 256, 0, q->stream>>>(A);
-            k_intersect<FILTER_EDGES><<<igrid, 256, 0, q->stream>>>(A);
-        } else if (filter == FILTER_VERTICES) {
-            k_filter<FILTER_VERTICES><<<A.nseg, 256, 0, q->stream>>>(A);
-            k_intersect<FILTER_VERTICES><<<igrid, 256, 0, q->stream>>>(A);
-        } else {
-            k_filter<FILTER_NONE><<<A.nseg, 256, 0, q->stream>>>(A);
-            k_intersect<FILTER_NONE><<<igrid, 256, 0, q->stream>>>(A);
-        }
+        if (A.B.mode == MODE_GEN) enqueue_pair<true>(filter, A, igrid, q->stream);
+        else enqueue_pair<false>(filter, A, igrid, q->stream);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipEventRecord(q->band_ev[2 * slot + 1], q->stream));
