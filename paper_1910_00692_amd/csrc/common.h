@@ -41,6 +41,16 @@ struct cand {
     uint32_t u, v, a, pos;
 };
 
+// A candidate with many entries to intersect, handed from the wave that found it to a kernel
+// that spreads its entries over many waves (48 bytes).
+struct Heavy {
+    uint64_t Ab, Bb;           // iterated row (weight-sorted copy), other row (both copies)
+    uint32_t qA, qB, Blen, zB; // admissible entries of each row, other row's length and floor
+    uint32_t a, u, v, fl;      // base entry weight and ends, filter flags
+    uint32_t g, pad;           // graph (batched form)
+};
+constexpr uint32_t HEAVY_CAP = 4096; // heavy candidates per pass (more stay with their wave)
+
 // ----------------------------------------------------------------------------- query state
 // Device state of one query in flight: its stream, candidate buffers and counters.  A graph
 // owns one for its synchronous calls; a server owns one per slot, so that queries on one
@@ -63,6 +73,8 @@ struct QueryCtx {
     uint64_t max_cand = 1ull << 25;        // a pass streams its entries in pieces of this size
     uint64_t min_buf = 1ull << 22;         // smallest triangle buffer (records)
     uint32_t *ccnt = nullptr;              // candidates per filter block
+    struct Heavy *heavy = nullptr;         // [HEAVY_CAP] heavy candidates of the current piece
+    uint32_t *nheavy = nullptr;            // their number (reset by the piece's filter)
     unsigned long long *spart = nullptr;   // spread per-pass counters
     unsigned long long *dcount = nullptr;  // [16] counters
     unsigned long long *hcount = nullptr;  // pinned mirror

@@ -191,6 +191,11 @@ struct EnumArgs {
     uint32_t *ccnt;
     uint64_t seg;
     uint32_t nseg;
+    // candidates with more than heavy_min entries to intersect go to heavy[] (their number in
+    // *nheavy, cleared by the filter) for k_intersect_heavy; heavy == NULL keeps them in-wave
+    Heavy *heavy;
+    uint32_t *nheavy;
+    uint32_t heavy_min;
     // batched form (one disjoint union of graphs): the stream is the concatenation, over the
     // graphs, of the first E_g entries of graph g's weight-ordered segment, which starts at
     // goff[g]; poff is the exclusive prefix of E_g (ng + 1 values, poff[ng] = the length,
@@ -309,6 +314,8 @@ __device__ __forceinline__ uint32_t graph_search(const uint64_t *poff, uint32_t 
 
 template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) void k_filter(EnumArgs A) {
     __shared__ uint32_t lcount;
+    // the previous piece's intersect kernels have finished (stream order)
+    if (A.nheavy && blockIdx.x == 0 && threadIdx.x == 0) *A.nheavy = 0;
     if (A.skip && *A.skip) return; // written only between passes
     uint64_t E, seg;
     stream_extent<BATCH>(A, E, seg);
@@ -441,6 +448,83 @@ __device__ __forceinline__ bool make_rec(const EnumArgs &A, uint32_t g, uint32_t
     return in_band(band_of<BATCH>(A, g), key, i, j, l);
 }
 
+// Entry pa of a candidate's iterated row (weight-sorted copy: head c, weight x) looked up in the
+// other row: scanned among that row's qB admissible entries (the leading ones of its
+// weight-sorted copy) when there are at most scan_max, else binary-searched in its head-sorted
+// copy (Blen entries from Bb) and then held to the floor zB.  True with the triangle's record
+// when it is admissible and lies in its band.
+template <int FILTER, bool BATCH, bool GEN>
+__device__ __forceinline__ bool lookup_entry(const EnumArgs &A, uint64_t pa, uint64_t Bb, uint32_t Blen, uint32_t qB,
+                                             uint32_t zB, uint32_t a, uint32_t u, uint32_t v, uint32_t fl,
+                                             uint32_t g, trec &r) {
+    const uint32_t c = A.wcol[pa], x = A.wwgt[pa];
+    if (FILTER == FILTER_VERTICES && (fl & FL_REQ_C) && !A.vflag[c]) return false;
+    uint8_t markA = 0;
+    if (FILTER == FILTER_EDGES) {
+        markA = A.emark[A.wpos[pa]];
+        if ((fl & FL_REQ_A) && !markA) return false;
+    }
+    if (qB <= A.scan_max) {
+        uint32_t hit = qB;
+        for (uint32_t t = 0; t < qB; t++)
+            if (A.wcol[Bb + t] == c) { hit = t; break; }
+        if (hit == qB) return false;
+        if (FILTER == FILTER_EDGES) {
+            const uint8_t markB = A.emark[A.wpos[Bb + hit]];
+            if ((fl & FL_REQ_B) && !markB) return false;
+            if (!((fl & FL_MARK_UV) || markA || markB)) return false;
+        }
+        return make_rec<BATCH, GEN>(A, g, a, x, A.wwgt[Bb + hit], u, v, c, r);
+    }
+    uint64_t lo = Bb, hi = Bb + Blen;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (A.cw[mid].x < c) lo = mid + 1; else hi = mid;
+    }
+    const uint2 hit = lo < Bb + Blen ? A.cw[lo] : make_uint2(~0u, 0u);
+    if (hit.x != c || hit.y < zB) return false;
+    if (FILTER == FILTER_EDGES) {
+        const uint8_t markB = A.emark[lo];
+        if ((fl & FL_REQ_B) && !markB) return false;
+        if (!((fl & FL_MARK_UV) || markA || markB)) return false;
+    }
+    return make_rec<BATCH, GEN>(A, g, a, x, hit.y, u, v, c, r);
+}
+
+// Block-wide exclusive prefix of per-item counts: pre[i] = sum of cnt(j) for j < i, over
+// N = 256 * PER items (each thread owns PER consecutive ones); pre[N] = the total.
+template <int PER, typename F> __device__ __forceinline__ void block_prefix(uint32_t *pre, uint32_t *wsum, F cnt) {
+    const int lane = threadIdx.x & 63;
+    uint32_t loc[PER], sum = 0;
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        loc[i] = cnt(threadIdx.x * PER + i);
+        sum += loc[i];
+    }
+    const uint32_t incl = wave_incl_scan(sum);
+    if (lane == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); w++) run += wsum[w];
+#pragma unroll
+    for (int i = 0; i < PER; i++) {
+        pre[threadIdx.x * PER + i] = run;
+        run += loc[i];
+    }
+    if (threadIdx.x == 255) pre[256 * PER] = run;
+    __syncthreads();
+}
+
+// The last i with pre[i] <= x, over pre[0 .. n] (pre[0] = 0 <= x).
+__device__ __forceinline__ uint32_t prefix_owner(const uint32_t *pre, uint32_t n, uint32_t x) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) void k_intersect(EnumArgs A) {
     __shared__ uint32_t pre[MAX_SEG + 1]; // exclusive prefix of 64-candidate chunks per segment
     __shared__ uint32_t wsum[4];
@@ -448,45 +532,22 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
     uint64_t E_unused, seg;
     stream_extent<BATCH>(A, E_unused, seg);
     const int lane = threadIdx.x & 63;
-    {
-        // block scan of the per-segment chunk counts (each thread owns 16 consecutive segments)
-        constexpr int PER = (MAX_SEG + 255) / 256;
-        uint32_t loc[PER], sum = 0;
-#pragma unroll
-        for (int i = 0; i < PER; i++) {
-            const uint32_t sg = threadIdx.x * PER + i;
-            loc[i] = sg < A.nseg ? (A.ccnt[sg] + 63) >> 6 : 0;
-            sum += loc[i];
-        }
-        const uint32_t incl = wave_incl_scan(sum);
-        if (lane == 63) wsum[threadIdx.x >> 6] = incl;
-        __syncthreads();
-        uint32_t run = incl - sum;
-        for (int w = 0; w < (int)(threadIdx.x >> 6); w++) run += wsum[w];
-#pragma unroll
-        for (int i = 0; i < PER; i++) {
-            pre[threadIdx.x * PER + i] = run;
-            run += loc[i];
-        }
-        if (threadIdx.x == 255) pre[MAX_SEG] = run;
-        __syncthreads();
-    }
+    block_prefix<(MAX_SEG + 255) / 256>(pre, wsum, [&](uint32_t sg) -> uint32_t {
+        return sg < A.nseg ? (A.ccnt[sg] + 63) >> 6 : 0;
+    });
     const uint32_t nchunks = pre[MAX_SEG];
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     unsigned long long s_inter = 0, s_emit = 0;
     for (uint64_t ch = wave; ch < nchunks; ch += nwaves) {
-        // segment holding chunk ch: the last sg with pre[sg] <= ch
-        uint32_t lo_s = 0, hi_s = MAX_SEG;
-        while (hi_s - lo_s > 1) {
-            const uint32_t mid = (lo_s + hi_s) >> 1;
-            if (pre[mid] <= ch) lo_s = mid; else hi_s = mid;
-        }
-        const uint32_t sg = lo_s;
+        const uint32_t sg = prefix_owner(pre, MAX_SEG, (uint32_t)ch);
         const uint64_t j = ((uint64_t)(ch - pre[sg]) << 6) + (uint64_t)lane;
         bool pass = false, merge = false;
-        uint32_t a = 0, u = 0, v = 0, qA = 0, qB = 0, Blen = 0, fl = 0, g = 0, ml = 0, mvl = 0;
-        uint64_t Ab = 0, Bb = 0, zB = 0, mub = 0, mvb = 0, mzu = 0, mzv = 0;
+        // per lane: its candidate, and either the search plan (iterated row Ab with qA
+        // admissible entries, other row Bb) or the two rows to merge (Ab/ul with floor zA,
+        // Bb/Blen with floor zB)
+        uint32_t a = 0, u = 0, v = 0, qA = 0, qB = 0, Blen = 0, zA = 0, zB = 0, fl = 0, g = 0;
+        uint64_t Ab = 0, Bb = 0;
         if (j < A.ccnt[sg]) {
             const cand c = A.C[(uint64_t)sg * seg + j];
             u = c.u;
@@ -501,11 +562,12 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
             if (FILTER == FILTER_EDGES && A.emark[c.pos]) fl |= FL_MARK_UV;
             if (FILTER == FILTER_VERTICES && !A.vflag[u] && !A.vflag[v]) fl |= FL_REQ_C;
             const uint64_t zu = min_other<GEN>(B, a, Wv), zv = min_other<GEN>(B, a, Wu);
-            pass = zu <= Wu && zv <= Wv;
+            pass = zu <= Wu && zv <= Wv; // then both floors fit 32 bits
             if (pass && ul + vl <= A.merge_max) {
                 merge = true;
                 pass = false;
-                mub = ub; ml = ul; mvb = vb; mvl = vl; mzu = zu; mzv = zv;
+                Ab = ub; qA = ul; zA = (uint32_t)zu;
+                Bb = vb; Blen = vl; zB = (uint32_t)zv;
             }
             if (pass) {
                 uint32_t qu, qv;
@@ -516,7 +578,7 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
                 Ab = uA ? ub : vb;
                 Bb = uA ? vb : ub;
                 Blen = uA ? vl : ul;
-                zB = uA ? zv : zu;
+                zB = (uint32_t)(uA ? zv : zu);
                 if (qu == 0 || qv == 0) pass = false;
                 if (FILTER == FILTER_EDGES && !(fl & FL_MARK_UV)) {
                     // a drawn edge must be one of the other two
@@ -524,6 +586,13 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
                     if (!fa && !fb) pass = false;
                     if (!fb) fl |= FL_REQ_A; // only drawn entries of the iterated row can help
                     if (!fa) fl |= FL_REQ_B;
+                }
+                if (pass && qA > A.heavy_min && A.heavy) {
+                    const uint32_t h = atomicAdd(A.nheavy, 1u);
+                    if (h < HEAVY_CAP) {
+                        A.heavy[h] = Heavy{Ab, Bb, qA, qB, Blen, zB, a, u, v, fl, g, 0u};
+                        pass = false; // its entries are intersected by k_intersect_heavy
+                    }
                 }
             }
         }
@@ -541,78 +610,37 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
                 if (im <= tt) s += st;
             }
             const uint32_t o_incl = __shfl(incl, s, 64), o_work = __shfl(work, s, 64);
-            const uint64_t oAb = __shfl(Ab, s, 64), oBb = __shfl(Bb, s, 64), ozB = __shfl(zB, s, 64);
-            const uint32_t oBlen = __shfl(Blen, s, 64), oqB = __shfl(qB, s, 64), oa = __shfl(a, s, 64),
-                           ou = __shfl(u, s, 64), ov = __shfl(v, s, 64), ofl = __shfl(fl, s, 64);
+            const uint64_t oAb = __shfl(Ab, s, 64), oBb = __shfl(Bb, s, 64);
+            const uint32_t oBlen = __shfl(Blen, s, 64), oqB = __shfl(qB, s, 64), ozB = __shfl(zB, s, 64),
+                           oa = __shfl(a, s, 64), ou = __shfl(u, s, 64), ov = __shfl(v, s, 64),
+                           ofl = __shfl(fl, s, 64);
             const uint32_t og = BATCH ? __shfl(g, s, 64) : 0u;
             bool ok = false;
             trec r;
-            if (t < total) {
-                const uint64_t pa = oAb + (tt - (o_incl - o_work));
-                const uint32_t c = A.wcol[pa], x = A.wwgt[pa];
-                bool go = true;
-                if (FILTER == FILTER_VERTICES && (ofl & FL_REQ_C)) go = A.vflag[c];
-                uint8_t markA = 0;
-                if (FILTER == FILTER_EDGES) {
-                    markA = A.emark[A.wpos[pa]];
-                    if (ofl & FL_REQ_A) go = markA;
-                }
-                if (go && oqB <= A.scan_max) {
-                    // the other row's admissible entries are the oqB leading ones of its
-                    // weight-sorted copy: look for c among them
-                    uint32_t hit = oqB;
-                    for (uint32_t t2 = 0; t2 < oqB; t2++)
-                        if (A.wcol[oBb + t2] == c) { hit = t2; break; }
-                    if (hit < oqB) {
-                        const uint32_t y = A.wwgt[oBb + hit];
-                        bool adm = true;
-                        if (FILTER == FILTER_EDGES) {
-                            const uint8_t markB = A.emark[A.wpos[oBb + hit]];
-                            if (ofl & FL_REQ_B) adm = markB;
-                            adm = adm && ((ofl & FL_MARK_UV) || markA || markB);
-                        }
-                        if (adm) ok = make_rec<BATCH, GEN>(A, og, oa, x, y, ou, ov, c, r);
-                    }
-                } else if (go) {
-                    uint64_t lo = oBb, hi = oBb + oBlen;
-                    while (lo < hi) {
-                        const uint64_t mid = (lo + hi) >> 1;
-                        if (A.cw[mid].x < c) lo = mid + 1; else hi = mid;
-                    }
-                    const uint2 hit = lo < oBb + oBlen ? A.cw[lo] : make_uint2(~0u, 0u);
-                    if (hit.x == c) {
-                        const uint32_t y = hit.y;
-                        bool adm = (uint64_t)y >= ozB;
-                        if (FILTER == FILTER_EDGES) {
-                            const uint8_t markB = A.emark[lo];
-                            if (ofl & FL_REQ_B) adm = adm && markB;
-                            adm = adm && ((ofl & FL_MARK_UV) || markA || markB);
-                        }
-                        if (adm) ok = make_rec<BATCH, GEN>(A, og, oa, x, y, ou, ov, c, r);
-                    }
-                }
-            }
+            if (t < total)
+                ok = lookup_entry<FILTER, BATCH, GEN>(A, oAb + (tt - (o_incl - o_work)), oBb, oBlen, oqB, ozB, oa, ou,
+                                                      ov, ofl, og, r);
             wave_emit<BATCH>(A, ok, r, og, lane, s_emit);
         }
         // short rows: each such lane merges the two head-sorted rows (weights below their
         // floors skipped), one step per iteration, emitting with the whole wave
-        const uint32_t msteps = wave_max(merge ? ml + mvl : 0u);
+        const uint32_t msteps = wave_max(merge ? qA + Blen : 0u);
         uint32_t mi = 0, mj = 0;
         for (uint32_t step = 0; step < msteps; step++) {
             bool ok = false;
             trec r;
-            if (merge && mi < ml && mj < mvl) {
-                const uint2 xu = A.cw[mub + mi], xv = A.cw[mvb + mj];
+            if (merge && mi < qA && mj < Blen) {
+                const uint2 xu = A.cw[Ab + mi], xv = A.cw[Bb + mj];
                 if (xu.x < xv.x) {
                     mi++;
                 } else if (xv.x < xu.x) {
                     mj++;
                 } else {
                     const uint32_t c = xu.x;
-                    bool adm = (uint64_t)xu.y >= mzu && (uint64_t)xv.y >= mzv;
+                    bool adm = xu.y >= zA && xv.y >= zB;
                     if (FILTER == FILTER_VERTICES && (fl & FL_REQ_C)) adm = adm && A.vflag[c];
                     if (FILTER == FILTER_EDGES)
-                        adm = adm && ((fl & FL_MARK_UV) || A.emark[mub + mi] || A.emark[mvb + mj]);
+                        adm = adm && ((fl & FL_MARK_UV) || A.emark[Ab + mi] || A.emark[Bb + mj]);
                     if (adm) ok = make_rec<BATCH, GEN>(A, g, a, xu.y, xv.y, u, v, c, r);
                     mi++;
                     mj++;
@@ -622,6 +650,47 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
         }
         const uint32_t consumed = wave_sum(merge ? mi + mj : 0u);
         if (lane == 0) s_inter += consumed;
+    }
+    if (lane == 0) {
+        stat_add(A.stats, 1, s_inter);
+        stat_add(A.stats, 2, s_emit);
+    }
+}
+
+// The heavy candidates of a piece: each is cut into HEAVY_PIECE-entry pieces of its iterated
+// row, and the waves of the grid take the pieces in turn, so that one long row is intersected
+// by many waves at once instead of serialising the wave that found it.
+constexpr uint32_t HEAVY_PIECE = 256;
+
+template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) void k_intersect_heavy(EnumArgs A) {
+    __shared__ uint32_t pre[HEAVY_CAP + 1]; // exclusive prefix of pieces per heavy candidate
+    __shared__ uint32_t wsum[4];
+    if (A.skip && *A.skip) return;
+    const uint32_t nh = min(*A.nheavy, HEAVY_CAP);
+    if (nh == 0) return;
+    block_prefix<HEAVY_CAP / 256>(pre, wsum, [&](uint32_t h) -> uint32_t {
+        return h < nh ? (A.heavy[h].qA + HEAVY_PIECE - 1) / HEAVY_PIECE : 0;
+    });
+    const uint32_t npieces = pre[HEAVY_CAP];
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned long long s_inter = 0, s_emit = 0;
+    for (uint64_t pc = wave; pc < npieces; pc += nwaves) {
+        const uint32_t h = prefix_owner(pre, HEAVY_CAP, (uint32_t)pc);
+        const Heavy H = A.heavy[h];
+        const uint32_t t0 = ((uint32_t)pc - pre[h]) * HEAVY_PIECE;
+        const uint32_t t1 = min(t0 + HEAVY_PIECE, H.qA);
+        if (lane == 0) s_inter += t1 - t0;
+        for (uint32_t base = t0; base < t1; base += 64) {
+            const uint32_t t = base + (uint32_t)lane;
+            bool ok = false;
+            trec r;
+            if (t < t1)
+                ok = lookup_entry<FILTER, BATCH, GEN>(A, H.Ab + t, H.Bb, H.Blen, H.qB, H.zB, H.a, H.u, H.v, H.fl,
+                                                      H.g, r);
+            wave_emit<BATCH>(A, ok, r, H.g, lane, s_emit);
+        }
     }
     if (lane == 0) {
         stat_add(A.stats, 1, s_inter);

@@ -410,6 +410,8 @@ __global__ __launch_bounds__(256) void k_place_bound(const uint32_t *osrc, const
 // Candidates whose two rows hold at most this many entries together are intersected by a
 // lane-local merge (sequential reads of both rows) instead of binary searches.
 constexpr uint32_t MERGE_MAX = 64;
+// Candidates with more admissible entries than this are spread over many waves.
+constexpr uint32_t HEAVY_MIN = 256;
 
 // The weight of (a lower bound of) the M-th heaviest edge, from the load-time histogram.
 uint32_t weight_at_rank(const std::vector<uint64_t> &h, uint64_t M) {
@@ -447,7 +449,7 @@ uint64_t query_bytes(const tt_graph *g, const QueryCtx *q, uint32_t k, uint32_t 
     const uint64_t cap = std::max<uint64_t>(q->min_buf, 16ull * k);
     const uint64_t cand = std::min<uint64_t>(g->m + 1, q->max_cand);
     uint64_t b = 2 * cap * sizeof(trec) + cand * sizeof(cand) + (uint64_t)k * sizeof(tt_triangle) +
-                 MAX_SEG * 4 + 5 * STAT_SLOTS * 8 + 256;
+                 MAX_SEG * 4 + 5 * STAT_SLOTS * 8 + HEAVY_CAP * sizeof(Heavy) + 512;
     if (subset_n)
         b += 2 * flag_bytes(g) + 16 * sub_stream_cap(g, q) + 4 * sub_list_cap(g, q) + 17ull * (subset_n + 1) +
              WBINS * 8 + 256;
@@ -464,6 +466,8 @@ int ensure_scratch(const tt_graph *g, QueryCtx *q, uint64_t cap, uint64_t kout) 
             if (hipEventCreate(&e) != hipSuccess) return fail(TT_E_DEVICE, "hipEventCreate failed");
     }
     if (!q->ccnt && (rc = dev_alloc(nullptr, (void **)&q->ccnt, MAX_SEG * sizeof(uint32_t)))) return rc;
+    if (!q->heavy && (rc = dev_alloc(nullptr, (void **)&q->heavy, HEAVY_CAP * sizeof(Heavy)))) return rc;
+    if (!q->nheavy && (rc = dev_alloc(nullptr, (void **)&q->nheavy, 256))) return rc;
     if (!q->spart) {
         if ((rc = dev_alloc(nullptr, (void **)&q->spart, 5 * STAT_SLOTS * sizeof(unsigned long long)))) return rc;
         HIP_TRY(hipMemsetAsync(q->spart, 0, 5 * STAT_SLOTS * sizeof(unsigned long long), q->stream));
@@ -543,8 +547,6 @@ struct Stream {
     uint64_t E;
 };
 
-// The shorter of the two streams that hold every possible base entry of a band triangle:
-// rows with hb >= score floor (row order), or entries with weight >= weight floor.
 // The shortest of the streams that hold every possible base entry of a band triangle: rows
 // with hb >= score floor (row order), entries with weight >= weight floor, and (when the
 // query has one) entries whose bound reaches the score floor.
@@ -699,17 +701,16 @@ int ensure_band_events(QueryCtx *q, size_t pairs) {
 
 // The filter and intersect kernels of one stream chunk, in the instantiation of the filter
 // mode and of the kind of key (generic p or integer).
+template <int FILTER, bool GEN> void enqueue_kernels(const EnumArgs &A, unsigned igrid, hipStream_t s) {
+    k_filter<FILTER, false, GEN><<<A.nseg, 256, 0, s>>>(A);
+    k_intersect<FILTER, false, GEN><<<igrid, 256, 0, s>>>(A);
+    k_intersect_heavy<FILTER, false, GEN><<<igrid, 256, 0, s>>>(A);
+}
+
 template <bool GEN> void enqueue_pair(int filter, const EnumArgs &A, unsigned igrid, hipStream_t s) {
-    if (filter == FILTER_EDGES) {
-        k_filter<FILTER_EDGES, false, GEN><<<A.nseg, 256, 0, s>>>(A);
-        k_intersect<FILTER_EDGES, false, GEN><<<igrid, 256, 0, s>>>(A);
-    } else if (filter == FILTER_VERTICES) {
-        k_filter<FILTER_VERTICES, false, GEN><<<A.nseg, 256, 0, s>>>(A);
-        k_intersect<FILTER_VERTICES, false, GEN><<<igrid, 256, 0, s>>>(A);
-    } else {
-        k_filter<FILTER_NONE, false, GEN><<<A.nseg, 256, 0, s>>>(A);
-        k_intersect<FILTER_NONE, false, GEN><<<igrid, 256, 0, s>>>(A);
-    }
+    if (filter == FILTER_EDGES) enqueue_kernels<FILTER_EDGES, GEN>(A, igrid, s);
+    else if (filter == FILTER_VERTICES) enqueue_kernels<FILTER_VERTICES, GEN>(A, igrid, s);
+    else enqueue_kernels<FILTER_NONE, GEN>(A, igrid, s);
 }
 
 // Enqueues one enumeration pass (no host synchronisation): the band's stream is filtered and
@@ -718,6 +719,7 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
     const Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len}
                                    : pick_stream(g, q->ord, B.mode, B.p, B.L);
     EnumArgs A;
+    std::memset(&A, 0, sizeof(A));
     A.rstart = g->rstart;
     A.rlen = g->rlen;
     A.col = g->col;
@@ -741,6 +743,9 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
     A.stats = q->spart;
     A.C = q->cand;
     A.ccnt = q->ccnt;
+    A.heavy = q->heavy;
+    A.nheavy = q->nheavy;
+    A.heavy_min = HEAVY_MIN;
     HIP_TRY(hipEventRecord(q->band_ev[2 * slot], q->stream));
     for (uint64_t off = 0; off < S.E; off += q->cand_cap) {
         const uint64_t E = std::min<uint64_t>(S.E - off, q->cand_cap);
@@ -782,6 +787,16 @@ Band make_band(int mode, double p, u128 L, uint32_t Li, uint32_t Lj, uint32_t Ll
     return B;
 }
 
+// Bands are enqueued ahead of the device while they add at most this many pieces (a piece is
+// a filter + intersect launch over up to cand_cap stream entries): the late bands of a large
+// graph stream most of its entries in many pieces and are rarely needed.
+constexpr uint64_t EAGER_PIECES = 8;
+
+uint64_t band_pieces(const tt_graph *g, const QueryCtx *q, const Band &B) {
+    const uint64_t E = q->sub_active ? q->sub_len : pick_stream(g, q->ord, B.mode, B.p, B.L).E;
+    return std::max<uint64_t>(1, (E + q->cand_cap - 1) / q->cand_cap);
+}
+
 // The threshold descent: bands [L_i, L_{i-1}) until >= k triangles are held, restarts on
 // overflow, then selection.  Writes min(k, T) triangles to `out` (host).
 int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, tt_triangle *out, uint32_t *n_out,
@@ -809,19 +824,31 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     if ((rc = ensure_band_events(q, Ls.size()))) return rc;
     HIP_TRY(hipMemsetAsync(q->dcount, 0, 8 * sizeof(unsigned long long), s));
     HIP_TRY(hipEventRecord(q->ev[0], s));
-    // all bands are enqueued at once; a band finds the buffer already holding >= k triangles
-    // (the answer is complete) or overflowed, and returns at once
+    // bands are enqueued without waiting while their pieces fit EAGER_PIECES; a band that
+    // finds the buffer already holding >= k triangles (the answer is complete) or overflowed
+    // returns at once.  Past that budget the host reads the count first and stops there.
+    size_t launched = 0;
+    uint64_t pending = 0;
     for (size_t i = 0; i < Ls.size(); i++) {
+        const Band B = make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, i > 0, i > 0 ? Ls[i - 1] : 0);
+        const uint64_t np = band_pieces(g, q, B);
+        if (pending > 0 && pending + np > EAGER_PIECES) {
+            HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (q->hcount[0] >= k) break; // complete, or overflowed (the buffer holds >= 16k)
+            pending = 0;
+        }
         if (i > 0) {
             k_band_gate<<<1, 64, 0, s>>>(q->dcount, k, q->dcount + 7);
             HIP_TRY(hipGetLastError());
         }
-        rc = launch_enum(g, q, make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, i > 0, i > 0 ? Ls[i - 1] : 0), filter, true, i);
-        if (rc) return rc;
+        if ((rc = launch_enum(g, q, B, filter, true, i))) return rc;
+        pending += np;
+        launched++;
     }
     HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    add_enum_time(q, st, Ls.size());
+    add_enum_time(q, st, launched);
     uint64_t cnt = q->hcount[0];
     bool overflow = cnt > q->buf_cap;
     double sel_ms = 0.0;

@@ -118,6 +118,30 @@ def test_overflow_restart_with_ties(tt):
             assert got["stats"]["restarts"] >= 1, got["stats"]
 
 
+def test_long_rows_every_filter(tt):
+    """A dense graph (n = 320, edge probability 0.9, weights 1..3): oriented rows of up to ~290
+    entries, so at low weight floors a candidate's iterated row holds more admissible entries
+    than its wave takes on and they are spread over many waves.  Every kind of p, k from 1 to
+    5,000, subset queries and edge sampling."""
+    rng = np.random.default_rng(5)
+    n = 320
+    s, d, w = rand_graph(rng, n, 0.9, 1, 3)
+    log(f"dense n={n} m={len(s)}")
+    ei = EdgeIndex(s, d, w)
+    with tt.Graph(n, s, d, w) as G:
+        for p in (math.inf, -math.inf, 1.0, 2.0, 0.0, 0.5, -1.0):
+            for k in (1, 200, 5000):
+                check(tt, n, s, d, w, k, p, G=G, ctx="dense")
+        for sub in ([3, 77, 200], list(range(40))):
+            for p in (math.inf, 1.0, -1.0):
+                check(tt, n, s, d, w, 300, p, G=G, subset=np.array(sub, np.uint32), ctx=f"dense subset {len(sub)}")
+        for p in (1.0, math.inf, 2.0):
+            for budget in (100, 20000):
+                got = G.sample(200, p, budget, seed=budget + 3)
+                want = oracle.sample_heavy_triangles(n, s, d, w, 200, p, budget, budget + 3)
+                assert_parity(got, want, p, ei, ctx=f"dense es p={p} budget={budget}")
+
+
 def test_planted_cliques(tt):
     g = graphgen.chung_lu(20000, 200000, 2.2, 1.8, seed=3, plant=8, plant_size=4, plant_mult=1000)
     log(f"planted m={g.m}")
