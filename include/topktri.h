@@ -232,7 +232,7 @@ uint64_t graph_num_edges(const tt_graph *g);
 uint64_t graph_device_bytes(const tt_graph *g);
 
 /* Releases every resource of g.  NULL-safe.  Its device blocks go to a process-wide cache
- * (per device, up to half of that device's memory) that later loads, queries and batches reuse. */
+ * (per device, up to 3/4 of that device's memory) that later loads, queries and batches reuse. */
 void graph_free(tt_graph *g);
 
 /* Returns every cached device block of every device to the driver; blocks in use by live graphs,

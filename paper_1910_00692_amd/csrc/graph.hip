@@ -31,7 +31,7 @@ extern "C" const char *tt_last_error(void) { return g_last_error.c_str(); }
 // Device memory comes from a process-wide cache of freed blocks (exact rounded sizes, per
 // device), so that repeated loads and queries do not pay for hipMalloc/hipFree: returning a large
 // block to the driver and asking for it again costs far more than the work that uses it.  The
-// cache holds up to half of each device's memory; tt_trim_cache() hands it all back.  Blocks are
+// cache holds up to 3/4 of each device's memory; tt_trim_cache() hands it all back.  Blocks are
 // only returned to the cache after the work that used them has completed on its stream.
 namespace {
 struct Block {
@@ -74,7 +74,7 @@ size_t pool_cap(int dev) {
     auto it = g_pool_cap.find(dev);
     if (it != g_pool_cap.end()) return it->second;
     size_t cap = 16ull << 30, total = 0;
-    if (hipDeviceTotalMem(&total, dev) == hipSuccess && total) cap = total / 2;
+    if (hipDeviceTotalMem(&total, dev) == hipSuccess && total) cap = total / 4 * 3;
     else (void)hipGetLastError();
     g_pool_cap[dev] = cap;
     return cap;
@@ -437,6 +437,52 @@ __device__ __forceinline__ void put_entry(uint64_t P, uint32_t r1, uint32_t r2, 
     wpos[P + r2] = (uint32_t)(P + r1);
 }
 
+// Ascending bitonic sort of 256*R 64-bit keys held by a block of 256 threads, thread t holding
+// the keys at positions t + 256 r (r < R).  A compare-exchange at stride s pairs positions
+// i and i ^ s: for s >= 256 both are in one thread (a register swap), for 64 <= s < 256 in
+// two waves (an exchange through LDS), below 64 in one wave (a shuffle).
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int s) {
+    const uint32_t lo = __shfl_xor((uint32_t)x, s, 64), hi = __shfl_xor((uint32_t)(x >> 32), s, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int R> __device__ __forceinline__ void block_bitonic(uint64_t (&k)[R], uint64_t *xch) {
+    const uint32_t t = threadIdx.x;
+    for (uint32_t size = 2; size <= 256u * R; size <<= 1) {
+        for (uint32_t s = size >> 1; s > 0; s >>= 1) {
+            if (s >= 256) {
+                const uint32_t rs = s >> 8;
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (r & rs) continue;
+                    const bool asc = ((t + 256u * r) & size) == 0;
+                    const uint64_t x = k[r], y = k[r | rs];
+                    if ((x > y) == asc) { k[r] = y; k[r | rs] = x; }
+                }
+                continue;
+            }
+            uint64_t other[R];
+            if (s >= 64) {
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < R; r++) xch[t + 256u * r] = k[r];
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < R; r++) other[r] = xch[(t + 256u * r) ^ s];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; r++) other[r] = shfl_xor_u64(k[r], (int)s);
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const uint32_t i = t + 256u * r;
+                const bool keep_min = ((i & s) == 0) == ((i & size) == 0);
+                k[r] = keep_min ? min(k[r], other[r]) : max(k[r], other[r]);
+            }
+        }
+    }
+}
+
 // Rows of at most SMALL_MAX entries.  Window w holds the rows that START in entries
 // [64w, 64w+64) of the scatter layout; they end before 64w+128.  A wave stages that 128-entry
 // window (heads and weights) in LDS and every lane counts its entries' ranks (by head ID; by
@@ -513,38 +559,85 @@ __global__ __launch_bounds__(256) void k_list_long(const uint32_t *rlen, uint32_
     }
 }
 
-// Rows of SMALL_MAX+1 .. MID_MAX entries: one block per row; the row is staged in LDS and
-// every entry's ranks are counted there.
+// Rows of SMALL_MAX+1 .. MID_MAX entries: one block per row.  The row is staged in LDS and
+// sorted twice by the block: by (head, position) for the head-sorted layout, then by (weight
+// descending, head-sorted position) for the weight-sorted copy; both are written coalesced.
+// Equal neighbouring heads after the first sort are a repeated pair.
+template <int R>
+__device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P, uint32_t len, const uint4 *rec0,
+                                             uint32_t *sc, uint32_t *sw, uint32_t *sd, uint32_t *hc, uint32_t *hw,
+                                             uint64_t *xch, uint32_t *col, uint32_t *wgt, uint32_t *eid,
+                                             uint32_t *osrc, uint32_t *opos, uint32_t *wcol, uint32_t *wwgt,
+                                             uint32_t *wpos, bool &dup) {
+    const uint32_t t = threadIdx.x;
+    uint64_t k[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t i = t + 256u * r;
+        k[r] = ~0ull;
+        if (i < len) {
+            const uint4 x = rec0[b + i];
+            sc[i] = x.x;
+            sw[i] = x.y;
+            sd[i] = x.z;
+            k[r] = ((uint64_t)x.x << 32) | i;
+        }
+    }
+    block_bitonic<R>(k, xch);
+    __syncthreads(); // sc/sw/sd complete
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t s = t + 256u * r;
+        if (s < len) {
+            const uint32_t i = (uint32_t)k[r], c = sc[i], w = sw[i], d = sd[i];
+            col[P + s] = c;
+            wgt[P + s] = w;
+            eid[P + s] = d;
+            osrc[P + s] = u;
+            opos[d] = (uint32_t)(P + s);
+            hc[s] = c;
+            hw[s] = w;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t s = t + 256u * r;
+        dup |= s + 1 < len && hc[s + 1] == hc[s];
+        k[r] = s < len ? (((uint64_t)~hw[s] << 32) | s) : ~0ull;
+    }
+    block_bitonic<R>(k, xch);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t s = t + 256u * r;
+        if (s < len) {
+            const uint32_t h = (uint32_t)k[r];
+            wcol[P + s] = hc[h];
+            wwgt[P + s] = hw[h];
+            wpos[P + s] = (uint32_t)(P + h);
+        }
+    }
+    __syncthreads(); // LDS is reused by the block's next row
+}
+
 __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t nmid, const uint4 *rec0,
                                                   const uint64_t *rowp0, const uint64_t *rstart, const uint32_t *rlen,
                                                   uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
                                                   uint32_t *opos, uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
                                                   uint32_t *flags) {
-    __shared__ uint32_t sc[MID_MAX], sw[MID_MAX];
+    static_assert(MID_MAX == 1024, "rows are sorted as up to 4 keys per thread");
+    __shared__ uint32_t sc[MID_MAX], sw[MID_MAX], sd[MID_MAX], hc[MID_MAX], hw[MID_MAX];
+    __shared__ uint64_t xch[MID_MAX];
     bool dup = false;
     for (uint32_t bi = blockIdx.x; bi < nmid; bi += gridDim.x) {
-        const uint32_t u = mid[bi];
+        const uint32_t u = mid[bi], len = rlen[u];
         const uint64_t b = rowp0[u], P = rstart[u];
-        const uint32_t len = rlen[u];
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-            const uint4 r = rec0[b + i];
-            sc[i] = r.x;
-            sw[i] = r.y;
-        }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-            const uint32_t c = sc[i], w = sw[i];
-            uint32_t r1 = 0, r2 = 0;
-            for (uint32_t f = 0; f < len; f++) {
-                const uint32_t cf = sc[f], wf = sw[f];
-                const bool before_id = cf < c || (cf == c && f < i);
-                r1 += before_id;
-                r2 += wf > w || (wf == w && before_id);
-                dup |= cf == c && f != i;
-            }
-            put_entry(P, r1, r2, u, c, w, rec0[b + i].z, col, wgt, eid, osrc, opos, wcol, wwgt, wpos);
-        }
+        if (len <= 256)
+            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, opos, wcol, wwgt, wpos, dup);
+        else if (len <= 512)
+            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, opos, wcol, wwgt, wpos, dup);
+        else
+            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, opos, wcol, wwgt, wpos, dup);
     }
     if (__ballot(dup) && (threadIdx.x & 63) == 0) atomicOr(flags, F_DUP);
 }

@@ -824,15 +824,16 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     if ((rc = ensure_band_events(q, Ls.size()))) return rc;
     HIP_TRY(hipMemsetAsync(q->dcount, 0, 8 * sizeof(unsigned long long), s));
     HIP_TRY(hipEventRecord(q->ev[0], s));
-    // bands are enqueued without waiting while their pieces fit EAGER_PIECES; a band that
-    // finds the buffer already holding >= k triangles (the answer is complete) or overflowed
-    // returns at once.  Past that budget the host reads the count first and stops there.
+    // The first band often holds the whole answer, so the host reads the count after it.
+    // Later bands are enqueued without waiting while their pieces fit EAGER_PIECES; a band
+    // that finds the buffer already holding >= k triangles (the answer is complete) or
+    // overflowed returns at once.  Past that budget the host reads the count again first.
     size_t launched = 0;
     uint64_t pending = 0;
     for (size_t i = 0; i < Ls.size(); i++) {
         const Band B = make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, i > 0, i > 0 ? Ls[i - 1] : 0);
         const uint64_t np = band_pieces(g, q, B);
-        if (pending > 0 && pending + np > EAGER_PIECES) {
+        if (i == 1 || (pending > 0 && pending + np > EAGER_PIECES)) {
             HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             if (q->hcount[0] >= k) break; // complete, or overflowed (the buffer holds >= 16k)

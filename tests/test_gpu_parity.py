@@ -222,6 +222,30 @@ def test_validation_errors(tt):
         assert e.value.code == want, (s, d, w, e.value.code, want)
 
 
+def test_repeated_pair_in_long_rows(tt):
+    """A repeated pair is found in rows of every length class: vertex 0 has 300 neighbours S,
+    each of which also reaches 301 further vertices T, so 0 (lowest degree) is the tail of a
+    301-entry row and every T vertex of a 300-entry row; the repeat is put in one such row
+    (0 -> S[0], or T[0] -> S[7]), and in a 2-entry row (an extra edge 602 - 603) for contrast."""
+    S = np.arange(1, 301, dtype=np.uint32)
+    T = np.arange(301, 602, dtype=np.uint32)
+    s0, d0 = np.zeros(300, np.uint32), S
+    s1, d1 = np.repeat(S, len(T)), np.tile(T, len(S))
+    base_s = np.concatenate([s0, s1, [602]]).astype(np.uint32)
+    base_d = np.concatenate([d0, d1, [603]]).astype(np.uint32)
+    n = 604
+    with tt.Graph(n, base_s, base_d, np.ones(len(base_s), np.uint32)) as G:
+        assert G.m == len(base_s)
+    for a, b in ((0, 1), (301, 8), (603, 602)):
+        s = np.concatenate([base_s, [b]]).astype(np.uint32)
+        d = np.concatenate([base_d, [a]]).astype(np.uint32)
+        w = np.ones(len(s), np.uint32)
+        assert oracle.validate(n, s, d, w) == tt.TT_E_DUP_EDGE
+        with pytest.raises(tt.TopKError) as e:
+            tt.Graph(n, s, d, w)
+        assert e.value.code == tt.TT_E_DUP_EDGE, (a, b)
+
+
 def test_empty_and_degenerate(tt):
     with tt.Graph(5, [], [], []) as G:
         assert G.topk(10, 1.0)["n_out"] == 0
