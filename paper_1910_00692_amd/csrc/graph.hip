@@ -538,24 +538,47 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
     if (__ballot(dup) && lane == 0) atomicOr(flags, F_DUP);
 }
 
-// Lists the rows that need the LDS (mid) or the sorting (big) path; one atomic per wave and list.
+// Lists the rows that need the LDS (mid) or the sorting (big) path.  Each block owns a
+// contiguous range of vertices: it counts its mid and big rows, reserves its part of each list
+// with one global atomic, then writes them (a per-wave atomic on two counters serialises).
 __global__ __launch_bounds__(256) void k_list_long(const uint32_t *rlen, uint32_t n, uint32_t *mid, uint32_t *nmid,
                                                    uint32_t *big, uint32_t *nbig) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
-        const uint64_t u = base + lane;
-        const uint32_t l = u < n ? rlen[u] : 0u;
+    __shared__ uint32_t wm[4], wb[4], bm0, bb0;
+    const uint32_t lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
+    const uint64_t per = ((uint64_t)n + gridDim.x - 1) / gridDim.x;
+    const uint64_t lo = (uint64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    uint32_t cm = 0, cb = 0;
+    for (uint64_t u = lo + threadIdx.x; u < hi; u += blockDim.x) {
+        const uint32_t l = rlen[u];
+        cm += l > SMALL_MAX && l <= MID_MAX;
+        cb += l > MID_MAX;
+    }
+    cm = wave_sum(cm);
+    cb = wave_sum(cb);
+    if (lane == 0) { wm[wib] = cm; wb[wib] = cb; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tm = wm[0] + wm[1] + wm[2] + wm[3], tb = wb[0] + wb[1] + wb[2] + wb[3];
+        bm0 = tm ? atomicAdd(nmid, tm) : 0u;
+        bb0 = tb ? atomicAdd(nbig, tb) : 0u;
+    }
+    __syncthreads();
+    uint32_t run_m = bm0, run_b = bb0; // block-uniform
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (uint64_t it = lo; it < hi; it += blockDim.x) {
+        const uint64_t u = it + threadIdx.x;
+        const uint32_t l = u < hi ? rlen[u] : 0u;
         const bool isb = l > MID_MAX, ism = l > SMALL_MAX && l <= MID_MAX;
         const uint64_t bb = __ballot(isb), bm = __ballot(ism);
-        uint32_t ob = 0, om = 0;
-        if (lane == 0 && bb) ob = atomicAdd(nbig, (uint32_t)__popcll(bb));
-        if (lane == 0 && bm) om = atomicAdd(nmid, (uint32_t)__popcll(bm));
-        ob = __shfl(ob, 0, 64);
-        om = __shfl(om, 0, 64);
-        const uint64_t below = (1ull << lane) - 1ull;
-        if (isb) big[ob + __popcll(bb & below)] = (uint32_t)u;
+        __syncthreads(); // the previous iteration has read wm/wb
+        if (lane == 0) { wm[wib] = (uint32_t)__popcll(bm); wb[wib] = (uint32_t)__popcll(bb); }
+        __syncthreads();
+        uint32_t om = run_m, ob = run_b;
+        for (uint32_t w = 0; w < wib; w++) { om += wm[w]; ob += wb[w]; }
         if (ism) mid[om + __popcll(bm & below)] = (uint32_t)u;
+        if (isb) big[ob + __popcll(bb & below)] = (uint32_t)u;
+        run_m += wm[0] + wm[1] + wm[2] + wm[3];
+        run_b += wb[0] + wb[1] + wb[2] + wb[3];
     }
 }
 
@@ -934,7 +957,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     if (m) k_rank_small<<<grid_for(m), 256, 0, s>>>(rec0, rowp0, m, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
                                                     g->opos, g->wcol, g->wwgt, g->wpos, flags);
     HIP_TRY(hipMemsetAsync(flags + 1, 0, 8, s));
-    if (n) k_list_long<<<grid_for(n), 256, 0, s>>>(g->rlen, n, mid, flags + 2, big, flags + 1);
+    if (n) k_list_long<<<grid_for(n, 4096), 256, 0, s>>>(g->rlen, n, mid, flags + 2, big, flags + 1);
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const uint32_t nbig = hf[1], nmid = hf[2];

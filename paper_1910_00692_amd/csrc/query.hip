@@ -37,6 +37,9 @@ namespace {
 
 // ----------------------------------------------------------------------------- selection
 constexpr int STILE = 1024;
+// Up to this many sorted tiles are merged by ranks in one launch, more by a tree of pairwise
+// merges (one launch per level).
+constexpr uint64_t RANK_MERGE_RUNS = 32;
 
 
 // Sorts each tile of STILE records (best first) in LDS and keeps its first S0.
@@ -88,6 +91,35 @@ __global__ __launch_bounds__(256) void k_merge(const trec *in, trec *out, uint64
     }
     const uint64_t pos = (uint64_t)idx + lo;
     if (pos < So) out[rp * So + pos] = me;
+}
+
+// The tile sort's R runs (run r: the best min(S, cover_r) records of tile r, cover_r =
+// min(C, N - r*C), at in + r*S) merged in one launch: records are distinct in the full order,
+// so a record's rank in the union is its position in its run plus the number of better
+// records in every other run (a binary search each).  Ranks below K land at out[rank].
+__global__ __launch_bounds__(256) void k_rank_merge(const trec *in, trec *out, uint64_t N, uint32_t C, uint32_t S,
+                                                    uint32_t R, uint32_t K) {
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t a = (uint32_t)(gid / S), idx = (uint32_t)(gid % S);
+    if (a >= R) return;
+    auto run_len = [&](uint32_t r) -> uint32_t {
+        const uint64_t cover = N - (uint64_t)r * C;
+        return (uint32_t)(cover < S ? cover : S);
+    };
+    if (idx >= run_len(a)) return;
+    const trec me = in[(uint64_t)a * S + idx];
+    uint32_t rank = idx;
+    for (uint32_t r = 0; r < R && rank < K; r++) {
+        if (r == a) continue;
+        const trec *run = in + (uint64_t)r * S;
+        uint32_t lo = 0, hi = run_len(r);
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (better(run[mid], me)) lo = mid + 1; else hi = mid;
+        }
+        rank += lo;
+    }
+    if (rank < K) out[rank] = me;
 }
 
 __global__ void k_finalize(const trec *in, uint32_t K, int mode, tt_triangle *out) {
@@ -515,6 +547,12 @@ int select_topk(QueryCtx *q, uint64_t N, uint32_t k, trec **res) {
     trec *in = q->buf0, *out = q->buf1;
     k_tile_sort<<<(unsigned)nruns, 512, 0, s>>>(in, out, N, S0);
     std::swap(in, out);
+    if (nruns > 1 && nruns <= RANK_MERGE_RUNS) {
+        const uint64_t threads = nruns * S0;
+        k_rank_merge<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(in, out, N, STILE, S0, (uint32_t)nruns, k);
+        std::swap(in, out);
+        nruns = 1;
+    }
     uint64_t C = STILE;
     uint32_t S = S0;
     while (nruns > 1) {
@@ -830,13 +868,14 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     // overflowed returns at once.  Past that budget the host reads the count again first.
     size_t launched = 0;
     uint64_t pending = 0;
+    bool counted = false; // hcount[0] already holds the final count
     for (size_t i = 0; i < Ls.size(); i++) {
         const Band B = make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, i > 0, i > 0 ? Ls[i - 1] : 0);
         const uint64_t np = band_pieces(g, q, B);
         if (i == 1 || (pending > 0 && pending + np > EAGER_PIECES)) {
             HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (q->hcount[0] >= k) break; // complete, or overflowed (the buffer holds >= 16k)
+            if (q->hcount[0] >= k) { counted = true; break; } // complete, or overflowed (>= 16k held)
             pending = 0;
         }
         if (i > 0) {
@@ -847,8 +886,10 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
         pending += np;
         launched++;
     }
-    HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (!counted) {
+        HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     add_enum_time(q, st, launched);
     uint64_t cnt = q->hcount[0];
     bool overflow = cnt > q->buf_cap;
