@@ -37,31 +37,75 @@ namespace {
 
 // ----------------------------------------------------------------------------- selection
 constexpr int STILE = 1024;
-// Up to this many sorted tiles are merged by ranks in one launch, more by a tree of pairwise
-// merges (one launch per level).
-constexpr uint64_t RANK_MERGE_RUNS = 32;
 
 
-// Sorts each tile of STILE records (best first) in LDS and keeps its first S0.
+// Sorts each tile of STILE records (best first) in LDS and keeps its first S0.  The tile is
+// held as separate arrays of its fields, so that the lanes of a compare-exchange step touch
+// consecutive words instead of 32-byte strides.
+struct TileLds {
+    uint64_t kh[STILE], kl[STILE];
+    uint32_t ti[STILE], tj[STILE], tl[STILE];
+    __device__ __forceinline__ bool better_at(uint32_t a, uint32_t b) const {
+        if (kh[a] != kh[b]) return kh[a] > kh[b];
+        if (kl[a] != kl[b]) return kl[a] > kl[b];
+        if (ti[a] != ti[b]) return ti[a] < ti[b];
+        if (tj[a] != tj[b]) return tj[a] < tj[b];
+        return tl[a] < tl[b];
+    }
+    __device__ __forceinline__ void swap_at(uint32_t a, uint32_t b) {
+        uint64_t x = kh[a]; kh[a] = kh[b]; kh[b] = x;
+        x = kl[a]; kl[a] = kl[b]; kl[b] = x;
+        uint32_t y = ti[a]; ti[a] = ti[b]; ti[b] = y;
+        y = tj[a]; tj[a] = tj[b]; tj[b] = y;
+        y = tl[a]; tl[a] = tl[b]; tl[b] = y;
+    }
+};
+
 __global__ __launch_bounds__(512) void k_tile_sort(const trec *in, trec *out, uint64_t N, uint32_t S0) {
-    __shared__ trec sh[STILE];
+    __shared__ TileLds T;
     const uint64_t base = (uint64_t)blockIdx.x * STILE;
     const uint32_t cover = (uint32_t)((N - base) < (uint64_t)STILE ? (N - base) : (uint64_t)STILE);
-    for (uint32_t t = threadIdx.x; t < STILE; t += blockDim.x) sh[t] = t < cover ? in[base + t] : worst_rec();
+    for (uint32_t t = threadIdx.x; t < STILE; t += blockDim.x) {
+        const trec r = t < cover ? in[base + t] : worst_rec();
+        T.kh[t] = r.khi;
+        T.kl[t] = r.klo;
+        T.ti[t] = r.i;
+        T.tj[t] = r.j;
+        T.tl[t] = r.l;
+    }
     __syncthreads();
+    static_assert(STILE == 2 * 512, "one compare-exchange per thread and step");
+    // Thread t pairs i = 2t - (t mod stride) with i + stride: for stride <= 64 both lie in the
+    // 128 records [128w, 128w + 128) of the thread's wave w, so a wave only needs its own LDS
+    // writes to be complete (a wave-level fence) unless this or the next step has a longer
+    // stride, which crosses waves and takes a block barrier.
     for (uint32_t size = 2; size <= (uint32_t)STILE; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t t = threadIdx.x; t < STILE / 2; t += blockDim.x) {
-                const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
-                const bool first_best = (i & size) == 0;
-                const bool swap = first_best ? better(sh[j], sh[i]) : better(sh[i], sh[j]);
-                if (swap) { trec x = sh[i]; sh[i] = sh[j]; sh[j] = x; }
+            const uint32_t t = threadIdx.x;
+            const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
+            const bool first_best = (i & size) == 0;
+            if (first_best ? T.better_at(j, i) : T.better_at(i, j)) T.swap_at(i, j);
+            const uint32_t next = stride > 1 ? stride >> 1 : size; // the next step's stride
+            if (stride >= 128 || next >= 128) {
+                __syncthreads();
+            } else {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            __syncthreads();
         }
     }
     const uint32_t keep = cover < S0 ? cover : S0;
-    for (uint32_t t = threadIdx.x; t < keep; t += blockDim.x) out[(uint64_t)blockIdx.x * S0 + t] = sh[t];
+    for (uint32_t t = threadIdx.x; t < keep; t += blockDim.x) {
+        trec r;
+        r.khi = T.kh[t];
+        r.klo = T.kl[t];
+        r.i = T.ti[t];
+        r.j = T.tj[t];
+        r.l = T.tl[t];
+        r.pad = 0;
+        out[(uint64_t)blockIdx.x * S0 + t] = r;
+    }
 }
 
 // Merges runs 2r and 2r+1 (cover C, stride S) into run r (stride So), keeping the first So.
@@ -91,35 +135,6 @@ __global__ __launch_bounds__(256) void k_merge(const trec *in, trec *out, uint64
     }
     const uint64_t pos = (uint64_t)idx + lo;
     if (pos < So) out[rp * So + pos] = me;
-}
-
-// The tile sort's R runs (run r: the best min(S, cover_r) records of tile r, cover_r =
-// min(C, N - r*C), at in + r*S) merged in one launch: records are distinct in the full order,
-// so a record's rank in the union is its position in its run plus the number of better
-// records in every other run (a binary search each).  Ranks below K land at out[rank].
-__global__ __launch_bounds__(256) void k_rank_merge(const trec *in, trec *out, uint64_t N, uint32_t C, uint32_t S,
-                                                    uint32_t R, uint32_t K) {
-    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t a = (uint32_t)(gid / S), idx = (uint32_t)(gid % S);
-    if (a >= R) return;
-    auto run_len = [&](uint32_t r) -> uint32_t {
-        const uint64_t cover = N - (uint64_t)r * C;
-        return (uint32_t)(cover < S ? cover : S);
-    };
-    if (idx >= run_len(a)) return;
-    const trec me = in[(uint64_t)a * S + idx];
-    uint32_t rank = idx;
-    for (uint32_t r = 0; r < R && rank < K; r++) {
-        if (r == a) continue;
-        const trec *run = in + (uint64_t)r * S;
-        uint32_t lo = 0, hi = run_len(r);
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (better(run[mid], me)) lo = mid + 1; else hi = mid;
-        }
-        rank += lo;
-    }
-    if (rank < K) out[rank] = me;
 }
 
 __global__ void k_finalize(const trec *in, uint32_t K, int mode, tt_triangle *out) {
@@ -547,12 +562,6 @@ int select_topk(QueryCtx *q, uint64_t N, uint32_t k, trec **res) {
     trec *in = q->buf0, *out = q->buf1;
     k_tile_sort<<<(unsigned)nruns, 512, 0, s>>>(in, out, N, S0);
     std::swap(in, out);
-    if (nruns > 1 && nruns <= RANK_MERGE_RUNS) {
-        const uint64_t threads = nruns * S0;
-        k_rank_merge<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(in, out, N, STILE, S0, (uint32_t)nruns, k);
-        std::swap(in, out);
-        nruns = 1;
-    }
     uint64_t C = STILE;
     uint32_t S = S0;
     while (nruns > 1) {
