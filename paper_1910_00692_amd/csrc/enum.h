@@ -167,7 +167,7 @@ struct EnumArgs {
     uint32_t merge_max;
     // an entry of the iterated row is looked up in the other row by scanning that row's
     // admissible entries (the leading ones of its weight-sorted copy) when there are at most
-    // this many, else by a binary search of its head-sorted row
+    // this many and the scan takes no more steps than a binary search of the head-sorted row
     uint32_t scan_max;
     // the stream of candidate entries (tail, head, weight, head-sorted position or NULL if the
     // stream is the head-sorted layout itself) and its length
@@ -450,8 +450,9 @@ __device__ __forceinline__ bool make_rec(const EnumArgs &A, uint32_t g, uint32_t
 
 // Entry pa of a candidate's iterated row (weight-sorted copy: head c, weight x) looked up in the
 // other row: scanned among that row's qB admissible entries (the leading ones of its
-// weight-sorted copy) when there are at most scan_max, else binary-searched in its head-sorted
-// copy (Blen entries from Bb) and then held to the floor zB.  True with the triangle's record
+// weight-sorted copy) when there are at most scan_max and the scan is no longer than the
+// search, else binary-searched in its head-sorted copy (Blen entries from Bb) and then held to
+// the floor zB.  True with the triangle's record
 // when it is admissible and lies in its band.
 template <int FILTER, bool BATCH, bool GEN>
 __device__ __forceinline__ bool lookup_entry(const EnumArgs &A, uint64_t pa, uint64_t Bb, uint32_t Blen, uint32_t qB,
@@ -464,10 +465,18 @@ __device__ __forceinline__ bool lookup_entry(const EnumArgs &A, uint64_t pa, uin
         markA = A.emark[A.wpos[pa]];
         if ((fl & FL_REQ_A) && !markA) return false;
     }
-    if (qB <= A.scan_max) {
+    // the scan issues four independent loads per step; it is taken when it needs no more
+    // steps than the binary search has levels
+    if (qB <= A.scan_max && (qB + 3) / 4 <= 32u - (uint32_t)__clz(Blen)) {
         uint32_t hit = qB;
-        for (uint32_t t = 0; t < qB; t++)
-            if (A.wcol[Bb + t] == c) { hit = t; break; }
+        for (uint32_t t = 0; t < qB; t += 4) {
+            const uint32_t c0 = A.wcol[Bb + t], c1 = t + 1 < qB ? A.wcol[Bb + t + 1] : ~0u,
+                           c2 = t + 2 < qB ? A.wcol[Bb + t + 2] : ~0u, c3 = t + 3 < qB ? A.wcol[Bb + t + 3] : ~0u;
+            if (c0 == c) { hit = t; break; }
+            if (c1 == c) { hit = t + 1; break; }
+            if (c2 == c) { hit = t + 2; break; }
+            if (c3 == c) { hit = t + 3; break; }
+        }
         if (hit == qB) return false;
         if (FILTER == FILTER_EDGES) {
             const uint8_t markB = A.emark[A.wpos[Bb + hit]];
