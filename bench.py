@@ -77,8 +77,8 @@ def run_serve(args):
     continuous-batching server; compared with the same requests run one at a time."""
     import threading
     # one hardware queue per server slot, so the slots' streams do not share queues (HIP reads
-    # this when the runtime starts, i.e. before torch touches the GPU)
-    os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.slots))))
+    # this when the runtime starts, i.e. before torch touches the GPU; the default is 4)
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(4, args.slots)))
     import torch
     import graphgen
     import paper_1910_00692_amd as tt
