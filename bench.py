@@ -368,7 +368,9 @@ def main():
             G.topk(k, p)
             r = G.topk(k, p, with_stats=True)
             warm[str(p)] = {"ms": r["stats"]["total_ms"], "kernel_ms": r["stats"]["enum_kernel_ms"],
-                            "streamed": r["stats"]["edges_streamed"], "passes": r["stats"]["passes"]}
+                            "streamed": r["stats"]["edges_streamed"], "passes": r["stats"]["passes"],
+                            "heavy_candidates": r["stats"]["heavy_candidates"],
+                            "heavy_overflow": r["stats"]["heavy_overflow"]}
         G.close()
 
     cpu = None

@@ -70,6 +70,8 @@ typedef struct {
     double sample_ms;             /* sampling only: device time of the draws (and prefix sums) */
     uint64_t bound_order;         /* 1 if the passes streamed the entries in order of their bound
                                      for this p (built once this p has streamed > 4m entries) */
+    uint64_t heavy_candidates;    /* candidates whose intersection was spread over many waves */
+    uint64_t heavy_overflow;      /* heavy candidates beyond a pass's list, kept by their wave */
 } tt_query_stats;
 
 /*

@@ -41,7 +41,8 @@ class QueryStats(ctypes.Structure):
                 ("distinct_sampled", ctypes.c_uint64), ("passes", ctypes.c_uint32), ("restarts", ctypes.c_uint32),
                 ("enum_ms", ctypes.c_double), ("select_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("enum_kernel_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
-                ("bound_order", ctypes.c_uint64)]
+                ("bound_order", ctypes.c_uint64), ("heavy_candidates", ctypes.c_uint64),
+                ("heavy_overflow", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

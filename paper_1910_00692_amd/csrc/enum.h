@@ -196,6 +196,7 @@ struct EnumArgs {
     Heavy *heavy;
     uint32_t *nheavy;
     uint32_t heavy_min;
+    unsigned long long *hstat; // [0] heavy candidates spread, [1] beyond the list (or NULL)
     // batched form (one disjoint union of graphs): the stream is the concatenation, over the
     // graphs, of the first E_g entries of graph g's weight-ordered segment, which starts at
     // goff[g]; poff is the exclusive prefix of E_g (ng + 1 values, poff[ng] = the length,
@@ -675,8 +676,12 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
     __shared__ uint32_t pre[HEAVY_CAP + 1]; // exclusive prefix of pieces per heavy candidate
     __shared__ uint32_t wsum[4];
     if (A.skip && *A.skip) return;
-    const uint32_t nh = min(*A.nheavy, HEAVY_CAP);
+    const uint32_t nall = *A.nheavy, nh = min(nall, HEAVY_CAP);
     if (nh == 0) return;
+    if (A.hstat && blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(A.hstat, (unsigned long long)nh);
+        if (nall > nh) atomicAdd(A.hstat + 1, (unsigned long long)(nall - nh));
+    }
     block_prefix<HEAVY_CAP / 256>(pre, wsum, [&](uint32_t h) -> uint32_t {
         return h < nh ? (A.heavy[h].qA + HEAVY_PIECE - 1) / HEAVY_PIECE : 0;
     });

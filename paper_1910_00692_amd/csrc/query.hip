@@ -793,6 +793,7 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
     A.heavy = q->heavy;
     A.nheavy = q->nheavy;
     A.heavy_min = HEAVY_MIN;
+    A.hstat = q->dcount + 12;
     HIP_TRY(hipEventRecord(q->band_ev[2 * slot], q->stream));
     for (uint64_t off = 0; off < S.E; off += q->cand_cap) {
         const uint64_t E = std::min<uint64_t>(S.E - off, q->cand_cap);
@@ -870,6 +871,7 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     Ls.push_back(0); // exhaustive
     if ((rc = ensure_band_events(q, Ls.size()))) return rc;
     HIP_TRY(hipMemsetAsync(q->dcount, 0, 8 * sizeof(unsigned long long), s));
+    HIP_TRY(hipMemsetAsync(q->dcount + 12, 0, 2 * sizeof(unsigned long long), s));
     HIP_TRY(hipEventRecord(q->ev[0], s));
     // The first band often holds the whole answer, so the host reads the count after it.
     // Later bands are enqueued without waiting while their pieces fit EAGER_PIECES; a band
@@ -939,6 +941,7 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     k_reduce_stats<<<5, 256, 0, s>>>(q->spart, q->dcount + 1);
     if (K > 0) HIP_TRY(hipMemcpyAsync(out, q->dout, (size_t)K * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(q->hcount + 12, q->dcount + 12, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *n_out = K;
     if (st) {
@@ -952,6 +955,8 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
         st->triangles_emitted += q->hcount[3];
         st->edges_streamed += q->hcount[4];
         st->passes += (uint32_t)q->hcount[5];
+        st->heavy_candidates += q->hcount[12];
+        st->heavy_overflow += q->hcount[13];
     }
     return TT_OK;
 }

@@ -97,3 +97,27 @@ def test_batch_argument_errors(lib):
     assert lib.batch_topk_ex(None, 10, 1.0, -1, 0, None, n_out, None) == tt.TT_E_ARG
     assert lib.batch_num_graphs(None) == 0 and lib.batch_num_configs() >= 2
     lib.batch_free(None)  # NULL-safe
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's size and field offsets."""
+    import subprocess
+    mirrors = {"tt_triangle": tt.Triangle, "tt_query_stats": tt.QueryStats, "tt_batch_stats": tt.BatchStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "topktri.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'    printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    exe = tmp_path / "layout"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -132,6 +132,9 @@ def test_long_rows_every_filter(tt):
         for p in (math.inf, -math.inf, 1.0, 2.0, 0.0, 0.5, -1.0):
             for k in (1, 200, 5000):
                 check(tt, n, s, d, w, k, p, G=G, ctx="dense")
+        st = G.topk(5000, math.inf, with_stats=True)["stats"]
+        log(f"dense p=inf stats {st}")
+        assert st["heavy_candidates"] > 0 and st["heavy_overflow"] == 0  # the spread path ran
         for sub in ([3, 77, 200], list(range(40))):
             for p in (math.inf, 1.0, -1.0):
                 check(tt, n, s, d, w, 300, p, G=G, subset=np.array(sub, np.uint32), ctx=f"dense subset {len(sub)}")
