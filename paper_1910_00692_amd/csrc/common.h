@@ -80,6 +80,7 @@ struct QueryCtx {
     unsigned long long *hcount = nullptr;  // pinned mirror
     tt_triangle *dout = nullptr;
     uint64_t dout_cap = 0;
+    tt_triangle *hout = nullptr;           // pinned host staging of the results (dout_cap records)
     uint8_t *vflag = nullptr;              // [n]
     uint8_t *vflag2 = nullptr;             // [n]
     // subset queries: the entries that can be the base of a triangle touching the subset

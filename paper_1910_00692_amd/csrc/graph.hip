@@ -1126,6 +1126,8 @@ void ctx_release(QueryCtx *q) {
     q->buf_cap = q->cand_cap = q->dout_cap = 0;
     if (q->hcount) (void)hipHostFree(q->hcount);
     q->hcount = nullptr;
+    if (q->hout) (void)hipHostFree(q->hout);
+    q->hout = nullptr;
     for (auto &e : q->ev)
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
     for (auto &e : q->band_ev)

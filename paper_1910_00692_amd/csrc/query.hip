@@ -539,9 +539,15 @@ int ensure_scratch(const tt_graph *g, QueryCtx *q, uint64_t cap, uint64_t kout) 
     }
     if (q->dout_cap < kout) {
         dev_free(nullptr, q->dout, 0);
+        if (q->hout) (void)hipHostFree(q->hout);
         q->dout = nullptr;
+        q->hout = nullptr;
         q->dout_cap = 0;
         if ((rc = dev_alloc(nullptr, (void **)&q->dout, kout * sizeof(tt_triangle)))) return rc;
+        if (hipHostMalloc((void **)&q->hout, kout * sizeof(tt_triangle), hipHostMallocDefault) != hipSuccess) {
+            q->hout = nullptr;
+            return fail(TT_E_NOMEM, "hipHostMalloc failed");
+        }
         q->dout_cap = kout;
     }
     return TT_OK;
@@ -939,10 +945,12 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     }
     HIP_TRY(hipEventRecord(q->ev[2], s));
     k_reduce_stats<<<5, 256, 0, s>>>(q->spart, q->dcount + 1);
-    if (K > 0) HIP_TRY(hipMemcpyAsync(out, q->dout, (size_t)K * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(q->hcount + 12, q->dcount + 12, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    // results through pinned staging (the caller's buffer is ordinary host memory), counters in
+    // one copy
+    if (K > 0) HIP_TRY(hipMemcpyAsync(q->hout, q->dout, (size_t)K * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 16 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (K > 0) std::memcpy(out, q->hout, (size_t)K * sizeof(tt_triangle));
     *n_out = K;
     if (st) {
         float e_ms = 0.f, s_ms = 0.f;
