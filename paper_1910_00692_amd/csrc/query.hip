@@ -237,40 +237,31 @@ __global__ __launch_bounds__(256) void k_es_draw(const void *prefix, const uint3
 }
 
 // vflag[u] = 1 for every tail u with a drawn out-entry (a streaming pass over the marks).
+// Also adds the number of drawn entries (distinct sampled edges) to *count: one atomic per block.
 __global__ __launch_bounds__(256) void k_mark_tails(const uint8_t *emark, uint64_t m, const uint32_t *osrc,
-                                                    uint8_t *vflag) {
+                                                    uint8_t *vflag, unsigned long long *count) {
+    __shared__ unsigned long long part[4];
     const uint64_t nv = (m + 15) / 16;
+    unsigned long long c = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint4 x = ((const uint4 *)emark)[i];
         if ((x.x | x.y | x.z | x.w) == 0) continue;
         const uint32_t w[4] = {x.x, x.y, x.z, x.w};
         for (int k = 0; k < 16; k++) {
             const uint64_t e = i * 16 + k;
-            if (e < m && ((w[k >> 2] >> ((k & 3) * 8)) & 0xFFu)) vflag[osrc[e]] = 1;
+            if (e < m && ((w[k >> 2] >> ((k & 3) * 8)) & 0xFFu)) {
+                vflag[osrc[e]] = 1;
+                c++;
+            }
         }
     }
-}
-
-// Number of non-zero bytes in mark[0..m) (16-byte loads; the buffer is 256-byte aligned).
-__global__ __launch_bounds__(256) void k_count_marks(const uint8_t *mark, uint64_t m, unsigned long long *out) {
-    unsigned long long c = 0;
-    const uint64_t nv = m / 16;
-    const uint4 *v = (const uint4 *)mark;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = tid; i < nv; i += stride) {
-        const uint4 x = v[i];
-        const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            // one bit per non-zero byte
-            const uint32_t y = w[k] | (w[k] >> 4);
-            const uint32_t z = y | (y >> 2);
-            c += __popc((z | (z >> 1)) & 0x01010101u);
-        }
-    }
-    for (uint64_t e = nv * 16 + tid; e < m; e += stride) c += mark[e] != 0;
     c = wave_sum(c);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&out[blockIdx.x & 1023], c);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd(count, t);
+    }
 }
 
 // Sets vertex x in a byte-flag array through its 32-bit word; true for the one thread that
@@ -1148,12 +1139,13 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
     if ((rc = sample_table(g, qexp, kind, &tab))) return rc;
     HIP_TRY(hipMemsetAsync(g->emark, 0, g->m + 1, s));
     HIP_TRY(hipMemsetAsync(q->vflag, 0, (uint64_t)g->n + 1, s));
+    HIP_TRY(hipMemsetAsync(q->dcount + 14, 0, sizeof(unsigned long long), s)); // distinct draws
     const unsigned grid = (unsigned)std::min<uint64_t>((budget + 255) / 256, (uint64_t)num_cus() * 16);
     const uint32_t bits = g->guide_bits;
     if (kind == 0) k_es_draw<0><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
     else if (kind == 1) k_es_draw<1><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
     else k_es_draw<2><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
-    k_mark_tails<<<enum_grid(g->m / 16 + 1), 256, 0, s>>>(g->emark, g->m, g->osrc, q->vflag);
+    k_mark_tails<<<enum_grid(g->m / 16 + 1), 256, 0, s>>>(g->emark, g->m, g->osrc, q->vflag, q->dcount + 14);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(q->ev[7], s));
     BoundOrder *o = nullptr;
@@ -1167,12 +1159,7 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
     if (!rc && stats) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, q->ev[6], q->ev[7]) == hipSuccess) stats->sample_ms = ms;
-        // marks are counted into the spread slots of counter 0 (cleared after every query)
-        k_count_marks<<<std::min<unsigned>(enum_grid(g->m / 16 + 1), 1024u), 256, 0, s>>>(g->emark, g->m, q->spart);
-        k_reduce_stats<<<1, 256, 0, s>>>(q->spart, q->dcount + 8);
-        HIP_TRY(hipMemcpyAsync(q->hcount + 8, q->dcount + 8, 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        stats->distinct_sampled = q->hcount[8];
+        stats->distinct_sampled = q->hcount[14]; // counted by k_mark_tails, copied with the counters
         stats->total_ms = timer.ms();
     }
     if (!rc) set_error("");
