@@ -39,73 +39,63 @@ namespace {
 constexpr int STILE = 1024;
 
 
-// Sorts each tile of STILE records (best first) in LDS and keeps its first S0.  The tile is
-// held as separate arrays of its fields, so that the lanes of a compare-exchange step touch
-// consecutive words instead of 32-byte strides.
-struct TileLds {
-    uint64_t kh[STILE], kl[STILE];
-    uint32_t ti[STILE], tj[STILE], tl[STILE];
-    __device__ __forceinline__ bool better_at(uint32_t a, uint32_t b) const {
-        if (kh[a] != kh[b]) return kh[a] > kh[b];
-        if (kl[a] != kl[b]) return kl[a] > kl[b];
-        if (ti[a] != ti[b]) return ti[a] < ti[b];
-        if (tj[a] != tj[b]) return tj[a] < tj[b];
-        return tl[a] < tl[b];
-    }
-    __device__ __forceinline__ void swap_at(uint32_t a, uint32_t b) {
-        uint64_t x = kh[a]; kh[a] = kh[b]; kh[b] = x;
-        x = kl[a]; kl[a] = kl[b]; kl[b] = x;
-        uint32_t y = ti[a]; ti[a] = ti[b]; ti[b] = y;
-        y = tj[a]; tj[a] = tj[b]; tj[b] = y;
-        y = tl[a]; tl[a] = tl[b]; tl[b] = y;
-    }
-};
+// Sorts each tile of STILE records (best first) and keeps its first S0.  Thread t holds the
+// records at positions t and t + 512 in registers; a bitonic compare-exchange at stride s pairs
+// positions i and i ^ s: below 64 the partner is in the same wave (shuffles of the record's
+// seven words), from 64 to 256 in another wave (an exchange through LDS), at 512 in the same
+// thread.
+__device__ __forceinline__ trec shfl_xor_rec(const trec &r, int s) {
+    trec o;
+    o.khi = ((uint64_t)__shfl_xor((uint32_t)(r.khi >> 32), s, 64) << 32) | __shfl_xor((uint32_t)r.khi, s, 64);
+    o.klo = ((uint64_t)__shfl_xor((uint32_t)(r.klo >> 32), s, 64) << 32) | __shfl_xor((uint32_t)r.klo, s, 64);
+    o.i = __shfl_xor(r.i, s, 64);
+    o.j = __shfl_xor(r.j, s, 64);
+    o.l = __shfl_xor(r.l, s, 64);
+    o.pad = 0;
+    return o;
+}
 
 __global__ __launch_bounds__(512) void k_tile_sort(const trec *in, trec *out, uint64_t N, uint32_t S0) {
-    __shared__ TileLds T;
+    static_assert(STILE == 1024, "two records per thread of a 512-thread block");
+    __shared__ trec xch[STILE];
+    const uint32_t t = threadIdx.x;
     const uint64_t base = (uint64_t)blockIdx.x * STILE;
     const uint32_t cover = (uint32_t)((N - base) < (uint64_t)STILE ? (N - base) : (uint64_t)STILE);
-    for (uint32_t t = threadIdx.x; t < STILE; t += blockDim.x) {
-        const trec r = t < cover ? in[base + t] : worst_rec();
-        T.kh[t] = r.khi;
-        T.kl[t] = r.klo;
-        T.ti[t] = r.i;
-        T.tj[t] = r.j;
-        T.tl[t] = r.l;
-    }
-    __syncthreads();
-    static_assert(STILE == 2 * 512, "one compare-exchange per thread and step");
-    // Thread t pairs i = 2t - (t mod stride) with i + stride: for stride <= 64 both lie in the
-    // 128 records [128w, 128w + 128) of the thread's wave w, so a wave only needs its own LDS
-    // writes to be complete (a wave-level fence) unless this or the next step has a longer
-    // stride, which crosses waves and takes a block barrier.
+    trec r[2];
+    r[0] = t < cover ? in[base + t] : worst_rec();
+    r[1] = t + 512 < cover ? in[base + t + 512] : worst_rec();
+#pragma unroll
     for (uint32_t size = 2; size <= (uint32_t)STILE; size <<= 1) {
+#pragma unroll
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint32_t t = threadIdx.x;
-            const uint32_t i = 2 * t - (t & (stride - 1)), j = i + stride;
-            const bool first_best = (i & size) == 0;
-            if (first_best ? T.better_at(j, i) : T.better_at(i, j)) T.swap_at(i, j);
-            const uint32_t next = stride > 1 ? stride >> 1 : size; // the next step's stride
-            if (stride >= 128 || next >= 128) {
+            if (stride == 512) { // size 1024: the better record goes first everywhere
+                if (better(r[1], r[0])) { const trec x = r[0]; r[0] = r[1]; r[1] = x; }
+                continue;
+            }
+            trec o[2];
+            if (stride >= 64) {
                 __syncthreads();
+                xch[t] = r[0];
+                xch[t + 512] = r[1];
+                __syncthreads();
+                o[0] = xch[t ^ stride];
+                o[1] = xch[(t + 512) ^ stride];
             } else {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                o[0] = shfl_xor_rec(r[0], (int)stride);
+                o[1] = shfl_xor_rec(r[1], (int)stride);
+            }
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                const uint32_t i = t + 512u * q;
+                // the lower position of a pair takes the better record where (i & size) == 0
+                const bool keep_better = ((i & stride) == 0) == ((i & size) == 0);
+                if (better(o[q], r[q]) == keep_better) r[q] = o[q];
             }
         }
     }
     const uint32_t keep = cover < S0 ? cover : S0;
-    for (uint32_t t = threadIdx.x; t < keep; t += blockDim.x) {
-        trec r;
-        r.khi = T.kh[t];
-        r.klo = T.kl[t];
-        r.i = T.ti[t];
-        r.j = T.tj[t];
-        r.l = T.tl[t];
-        r.pad = 0;
-        out[(uint64_t)blockIdx.x * S0 + t] = r;
-    }
+    if (t < keep) out[(uint64_t)blockIdx.x * S0 + t] = r[0];
+    if (t + 512 < keep) out[(uint64_t)blockIdx.x * S0 + t + 512] = r[1];
 }
 
 // Merges runs 2r and 2r+1 (cover C, stride S) into run r (stride So), keeping the first So.
