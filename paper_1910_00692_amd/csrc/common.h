@@ -160,6 +160,7 @@ struct tt_graph {
         double q = -1.0;
         void *prefix = nullptr;   // u64 (q=1), u128 (q=2,3) or double (other q), [m]
         uint32_t *guide = nullptr; // [2^bits + 1] first candidate edge per top-bits bucket
+        void *scan_tmp = nullptr;  // block sums of the prefix scan (scan_tmp_bytes(m))
         uint64_t last_use = 0;
     } tables[2];
     uint32_t guide_bits = 0;
@@ -233,4 +234,9 @@ template <typename T> __device__ inline T wave_sum(T x) {
 }
 
 // scan helpers (scan.hip)
-int exclusive_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t s, tt_graph *g);
+// Exclusive prefix sums on stream s.  With tmp (at least scan_tmp_bytes(n) bytes, kept by the
+// caller until the stream has run the scan) nothing is allocated and the call does not wait;
+// without it the call waits for the scan.
+uint64_t scan_tmp_bytes(uint64_t n);
+int exclusive_scan_u32_to_u64(const uint32_t *in, uint64_t *out, uint64_t n, hipStream_t s, tt_graph *g,
+                              void *tmp = nullptr);

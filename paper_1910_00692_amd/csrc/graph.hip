@@ -788,6 +788,7 @@ void release(tt_graph *g) {
     for (auto &t : g->tables) {
         dev_free(g, t.prefix, 0);
         dev_free(g, t.guide, 0);
+        dev_free(g, t.scan_tmp, 0);
     }
     for (auto &o : g->bord) {
         void *op[] = {o.src, o.col, o.wgt, o.pos};
@@ -925,7 +926,10 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         k_outdeg<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg, g->rlen, g->wcol, g->wwgt);
     }
     // rows in vertex order first (unsorted): rowp0[n] = m
-    if ((rc = exclusive_scan_u32_to_u64(g->rlen, rowp0, nn, s, nullptr))) return rc;
+    void *scan_tmp = nullptr;
+    if ((rc = S.get(&scan_tmp, scan_tmp_bytes(nn))) ||
+        (rc = exclusive_scan_u32_to_u64(g->rlen, rowp0, nn, s, nullptr, scan_tmp)))
+        return rc;
     if (m) {
         k_scatter<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, g->wcol, g->wwgt, rowp0, rec0);
         k_row_max<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw);

@@ -1072,9 +1072,10 @@ int sample_table(tt_graph *g, double qexp, int kind, tt_graph::SampleTable **out
         g->guide_bits = bits;
     }
     if (!t->prefix && (rc = dev_alloc(g, &t->prefix, g->m * 16))) return rc;
+    if (!t->scan_tmp && (rc = dev_alloc(g, &t->scan_tmp, scan_tmp_bytes(g->m)))) return rc;
     if (!t->guide && (rc = dev_alloc(g, (void **)&t->guide, ((1ull << g->guide_bits) + 1) * 4))) return rc;
     t->q = -1.0;
-    if ((rc = inclusive_weight_prefix(g, qexp, t->prefix))) return rc;
+    if ((rc = inclusive_weight_prefix(g, qexp, t->prefix, t->scan_tmp))) return rc; // enqueued only
     const uint64_t runs = ((1ull << g->guide_bits) + GUIDE_RUN - 1) / GUIDE_RUN + 1;
     const unsigned grid = (unsigned)std::min<uint64_t>((runs + 255) / 256, (uint64_t)num_cus() * 16);
     if (kind == 0) k_es_guide<0><<<grid, 256, 0, g->stream>>>(t->prefix, g->m, g->guide_bits, t->guide);
