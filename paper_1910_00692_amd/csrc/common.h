@@ -49,7 +49,9 @@ struct Heavy {
     uint32_t a, u, v, fl;      // base entry weight and ends, filter flags
     uint32_t g, pad;           // graph (batched form)
 };
-constexpr uint32_t HEAVY_CAP = 4096; // heavy candidates per pass (more stay with their wave)
+constexpr uint32_t HEAVY_CAP = 16384;    // heavy candidates per piece of a pass (more stay in-wave)
+constexpr uint32_t HEAVY_PIECE = 256;    // entries of a heavy candidate's row taken by one wave
+constexpr uint32_t HEAVY_PIECES = 65536; // pieces listed per piece of a pass
 
 // ----------------------------------------------------------------------------- query state
 // Device state of one query in flight: its stream, candidate buffers and counters.  A graph
@@ -74,7 +76,8 @@ struct QueryCtx {
     uint64_t min_buf = 1ull << 22;         // smallest triangle buffer (records)
     uint32_t *ccnt = nullptr;              // candidates per filter block
     struct Heavy *heavy = nullptr;         // [HEAVY_CAP] heavy candidates of the current piece
-    uint32_t *nheavy = nullptr;            // their number (reset by the piece's filter)
+    unsigned long long *nheavy = nullptr;  // [0] heavy candidates, [1] pieces (reset by the filter)
+    uint2 *hpiece = nullptr;               // [HEAVY_PIECES] (heavy candidate, piece number)
     unsigned long long *spart = nullptr;   // spread per-pass counters
     unsigned long long *dcount = nullptr;  // [16] counters
     unsigned long long *hcount = nullptr;  // pinned mirror

@@ -191,10 +191,12 @@ struct EnumArgs {
     uint32_t *ccnt;
     uint64_t seg;
     uint32_t nseg;
-    // candidates with more than heavy_min entries to intersect go to heavy[] (their number in
-    // *nheavy, cleared by the filter) for k_intersect_heavy; heavy == NULL keeps them in-wave
+    // candidates with more than heavy_min entries to intersect go to heavy[] and their
+    // HEAVY_PIECE-entry pieces to hpiece[] (counts in nheavy[0], nheavy[1], cleared by the
+    // filter) for k_intersect_heavy; heavy == NULL keeps them in-wave
     Heavy *heavy;
-    uint32_t *nheavy;
+    unsigned long long *nheavy;
+    uint2 *hpiece;
     uint32_t heavy_min;
     unsigned long long *hstat; // [0] heavy candidates spread, [1] beyond the list (or NULL)
     // batched form (one disjoint union of graphs): the stream is the concatenation, over the
@@ -316,7 +318,7 @@ __device__ __forceinline__ uint32_t graph_search(const uint64_t *poff, uint32_t 
 template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) void k_filter(EnumArgs A) {
     __shared__ uint32_t lcount;
     // the previous piece's intersect kernels have finished (stream order)
-    if (A.nheavy && blockIdx.x == 0 && threadIdx.x == 0) *A.nheavy = 0;
+    if (A.nheavy && blockIdx.x == 0 && threadIdx.x == 0) A.nheavy[0] = A.nheavy[1] = 0;
     if (A.skip && *A.skip) return; // written only between passes
     uint64_t E, seg;
     stream_extent<BATCH>(A, E, seg);
@@ -598,11 +600,25 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
                     if (!fa) fl |= FL_REQ_B;
                 }
                 if (pass && qA > A.heavy_min && A.heavy) {
-                    const uint32_t h = atomicAdd(A.nheavy, 1u);
+                    // reserve a record and the pieces; a range reserved past the list's end is
+                    // marked empty and the candidate stays with its wave
+                    const unsigned long long h = atomicAdd(A.nheavy, 1ull);
+                    bool spread = false;
                     if (h < HEAVY_CAP) {
-                        A.heavy[h] = Heavy{Ab, Bb, qA, qB, Blen, zB, a, u, v, fl, g, 0u};
-                        pass = false; // its entries are intersected by k_intersect_heavy
+                        const uint32_t np = (qA + HEAVY_PIECE - 1) / HEAVY_PIECE;
+                        const unsigned long long p0 = atomicAdd(A.nheavy + 1, (unsigned long long)np);
+                        if (p0 + np <= HEAVY_PIECES) {
+                            A.heavy[h] = Heavy{Ab, Bb, qA, qB, Blen, zB, a, u, v, fl, g, 0u};
+                            for (uint32_t k2 = 0; k2 < np; k2++)
+                                A.hpiece[p0 + k2] = make_uint2((uint32_t)h, k2);
+                            spread = true;
+                            pass = false; // its entries are intersected by k_intersect_heavy
+                        } else {
+                            for (unsigned long long k2 = p0; k2 < HEAVY_PIECES; k2++)
+                                A.hpiece[k2] = make_uint2(~0u, 0u);
+                        }
                     }
+                    if (A.hstat) atomicAdd(A.hstat + (spread ? 0 : 1), 1ull);
                 }
             }
         }
@@ -667,33 +683,23 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
     }
 }
 
-// The heavy candidates of a piece: each is cut into HEAVY_PIECE-entry pieces of its iterated
-// row, and the waves of the grid take the pieces in turn, so that one long row is intersected
-// by many waves at once instead of serialising the wave that found it.
-constexpr uint32_t HEAVY_PIECE = 256;
-
+// The heavy candidates of a piece: each was cut into HEAVY_PIECE-entry pieces of its iterated
+// row when it was listed, and the waves of the grid take the pieces in turn, so that one long
+// row is intersected by many waves at once instead of serialising the wave that found it.
 template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) void k_intersect_heavy(EnumArgs A) {
-    __shared__ uint32_t pre[HEAVY_CAP + 1]; // exclusive prefix of pieces per heavy candidate
-    __shared__ uint32_t wsum[4];
     if (A.skip && *A.skip) return;
-    const uint32_t nall = *A.nheavy, nh = min(nall, HEAVY_CAP);
-    if (nh == 0) return;
-    if (A.hstat && blockIdx.x == 0 && threadIdx.x == 0) {
-        atomicAdd(A.hstat, (unsigned long long)nh);
-        if (nall > nh) atomicAdd(A.hstat + 1, (unsigned long long)(nall - nh));
-    }
-    block_prefix<HEAVY_CAP / 256>(pre, wsum, [&](uint32_t h) -> uint32_t {
-        return h < nh ? (A.heavy[h].qA + HEAVY_PIECE - 1) / HEAVY_PIECE : 0;
-    });
-    const uint32_t npieces = pre[HEAVY_CAP];
+    const unsigned long long np_all = A.nheavy[1];
+    const uint32_t npieces = np_all < HEAVY_PIECES ? (uint32_t)np_all : HEAVY_PIECES;
+    if (npieces == 0) return;
     const int lane = threadIdx.x & 63;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     unsigned long long s_inter = 0, s_emit = 0;
     for (uint64_t pc = wave; pc < npieces; pc += nwaves) {
-        const uint32_t h = prefix_owner(pre, HEAVY_CAP, (uint32_t)pc);
-        const Heavy H = A.heavy[h];
-        const uint32_t t0 = ((uint32_t)pc - pre[h]) * HEAVY_PIECE;
+        const uint2 pe = A.hpiece[pc];
+        if (pe.x == ~0u) continue; // reserved past the list's end, never filled
+        const Heavy H = A.heavy[pe.x];
+        const uint32_t t0 = pe.y * HEAVY_PIECE;
         const uint32_t t1 = min(t0 + HEAVY_PIECE, H.qA);
         if (lane == 0) s_inter += t1 - t0;
         for (uint32_t base = t0; base < t1; base += 64) {

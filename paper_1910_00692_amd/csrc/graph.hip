@@ -1114,13 +1114,14 @@ extern "C" uint64_t graph_device_bytes(const tt_graph *g) { return g ? g->bytes 
 void ctx_release(QueryCtx *q) {
     void *ptrs[] = {q->buf0,    q->buf1,    q->cand,    q->ccnt,    q->spart,    q->dcount, q->dout,
                     q->vflag,   q->vflag2,  q->sub_src, q->sub_col, q->sub_wgt,  q->sub_pos, q->sub_vlist,
-                    q->heavy,   q->nheavy};
+                    q->heavy,   q->nheavy,  q->hpiece};
     for (void *p : ptrs) dev_free(nullptr, p, 0);
     q->buf0 = q->buf1 = nullptr;
     q->cand = nullptr;
     q->ccnt = nullptr;
     q->heavy = nullptr;
     q->nheavy = nullptr;
+    q->hpiece = nullptr;
     q->spart = nullptr;
     q->dcount = nullptr;
     q->dout = nullptr;
