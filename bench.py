@@ -362,15 +362,25 @@ def main():
 
     warm = {}
     if W.get("cpu_edges"):
-        # warm queries on a resident CSR (the steps above build it cold every time)
+        # queries on a resident CSR (the steps above build it cold every time): the second query
+        # of each p, then the steady state once repeated queries of p have built its bound order
+        def brief(r):
+            st = r["stats"]
+            return {"ms": st["total_ms"], "kernel_ms": st["enum_kernel_ms"], "streamed": st["edges_streamed"],
+                    "passes": st["passes"], "heavy_candidates": st["heavy_candidates"],
+                    "heavy_overflow": st["heavy_overflow"], "bound_order": st["bound_order"]}
         G = tt.Graph(g.n, s_d, d_d, w_d, stream=stream)
         for p in ps:
             G.topk(k, p)
-            r = G.topk(k, p, with_stats=True)
-            warm[str(p)] = {"ms": r["stats"]["total_ms"], "kernel_ms": r["stats"]["enum_kernel_ms"],
-                            "streamed": r["stats"]["edges_streamed"], "passes": r["stats"]["passes"],
-                            "heavy_candidates": r["stats"]["heavy_candidates"],
-                            "heavy_overflow": r["stats"]["heavy_overflow"]}
+            second = brief(G.topk(k, p, with_stats=True))
+            steady, n_q = None, 2
+            while n_q < 12:
+                r = G.topk(k, p, with_stats=True)
+                n_q += 1
+                if r["stats"]["bound_order"]:
+                    steady = brief(G.topk(k, p, with_stats=True))  # the order already built
+                    break
+            warm[str(p)] = {"second_query": second, "with_bound_order": steady, "queries_until_order": n_q}
         G.close()
 
     cpu = None
