@@ -247,6 +247,140 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *src, const uint
     }
 }
 
+// ----------------------------------------------------------------------------- partitioned front half
+// Degrees, row lengths and the row-grouped records without global atomics on vertices:
+// vertices are split into buckets of 2^rb consecutive IDs; a partition block takes a contiguous
+// chunk of edges and its per-bucket counts form a bucket-major matrix M[b * nblk + blk] whose
+// exclusive scan gives each (bucket, block) its range of a bucket-ordered array.  A bucket
+// block then owns its vertices' counters in LDS.
+constexpr uint32_t PART_MAX_BUCKETS = 8192; // LDS bins of a partition block
+constexpr uint32_t PART_MAX_R = 16384;      // vertices per bucket (LDS counters of a bucket block)
+
+struct PartGeom {
+    uint32_t rb, nbk, nblk; // bucket shift, buckets, partition blocks
+    uint64_t per;           // edges per partition block
+};
+
+__global__ __launch_bounds__(256) void k_part_count_ends(const uint32_t *src, const uint32_t *dst, uint64_t m,
+                                                         PartGeom G, uint32_t *M) {
+    __shared__ uint32_t h[PART_MAX_BUCKETS];
+    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
+    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        atomicAdd(&h[src[e] >> G.rb], 1u);
+        atomicAdd(&h[dst[e] >> G.rb], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) M[(uint64_t)b * G.nblk + blockIdx.x] = h[b];
+}
+
+// Both ends of every edge into bucket order.
+__global__ __launch_bounds__(256) void k_part_ends(const uint32_t *src, const uint32_t *dst, uint64_t m, PartGeom G,
+                                                   const uint64_t *off, uint32_t *ep) {
+    __shared__ unsigned long long cur[PART_MAX_BUCKETS];
+    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) cur[b] = off[(uint64_t)b * G.nblk + blockIdx.x];
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
+    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        const uint32_t a = src[e], d = dst[e];
+        ep[atomicAdd(&cur[a >> G.rb], 1ull)] = a;
+        ep[atomicAdd(&cur[d >> G.rb], 1ull)] = d;
+    }
+}
+
+// Degrees of bucket b's vertices from its endpoints ep[off(b, 0) .. off(b + 1, 0)).
+__global__ __launch_bounds__(256) void k_bucket_degree(const uint32_t *ep, const uint64_t *off, uint64_t total,
+                                                       PartGeom G, uint32_t n, uint32_t *deg) {
+    __shared__ uint32_t c[PART_MAX_R];
+    const uint32_t b = blockIdx.x, R = 1u << G.rb;
+    const uint64_t base = (uint64_t)b << G.rb;
+    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) c[i] = 0;
+    __syncthreads();
+    const uint64_t lo = off[(uint64_t)b * G.nblk], hi = b + 1 < G.nbk ? off[(uint64_t)(b + 1) * G.nblk] : total;
+    for (uint64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) atomicAdd(&c[(uint32_t)(ep[j] - base)], 1u);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x)
+        if (base + i < n) deg[base + i] = c[i];
+}
+
+// The tail of every edge (kept in etail) and tails per (bucket, block).
+__global__ __launch_bounds__(256) void k_part_count_tails(const uint32_t *src, const uint32_t *dst, uint64_t m,
+                                                          PartGeom G, const uint32_t *deg, uint32_t *etail,
+                                                          uint32_t *M) {
+    __shared__ uint32_t h[PART_MAX_BUCKETS];
+    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
+    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        uint32_t t, hd;
+        orient(src[e], dst[e], deg, t, hd);
+        etail[e] = t;
+        atomicAdd(&h[t >> G.rb], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) M[(uint64_t)b * G.nblk + blockIdx.x] = h[b];
+}
+
+// Every edge as a 16-byte record (head, weight, edge, tail) into tail-bucket order.
+__global__ __launch_bounds__(256) void k_part_edges(const uint32_t *src, const uint32_t *dst, const uint32_t *w,
+                                                    uint64_t m, PartGeom G, const uint32_t *etail,
+                                                    const uint64_t *off, uint4 *part) {
+    __shared__ unsigned long long cur[PART_MAX_BUCKETS];
+    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) cur[b] = off[(uint64_t)b * G.nblk + blockIdx.x];
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
+    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        const uint32_t t = etail[e];
+        part[atomicAdd(&cur[t >> G.rb], 1ull)] = make_uint4(src[e] ^ dst[e] ^ t, w[e], (uint32_t)e, t);
+    }
+}
+
+// Rows of bucket b: records per tail (row lengths), their exclusive scan from the bucket's
+// first record (row starts, vertex order), then every record at its row's next slot.
+__global__ __launch_bounds__(256) void k_bucket_rows(const uint4 *part, const uint64_t *off, uint64_t m, PartGeom G,
+                                                     uint32_t n, uint32_t *rlen, uint64_t *rowp, uint4 *rec) {
+    __shared__ uint32_t c[PART_MAX_R];
+    __shared__ uint32_t wsum[4];
+    const uint32_t b = blockIdx.x, R = 1u << G.rb, lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
+    const uint64_t base = (uint64_t)b << G.rb;
+    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) c[i] = 0;
+    __syncthreads();
+    const uint64_t lo = off[(uint64_t)b * G.nblk], hi = b + 1 < G.nbk ? off[(uint64_t)(b + 1) * G.nblk] : m;
+    for (uint64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) atomicAdd(&c[(uint32_t)(part[j].w - base)], 1u);
+    __syncthreads();
+    // thread t owns counters [t*per, t*per + per)
+    const uint32_t per = (R + 255) / 256;
+    uint32_t sum = 0;
+    for (uint32_t k = 0; k < per; k++) {
+        const uint32_t i = threadIdx.x * per + k;
+        if (i < R) {
+            sum += c[i];
+            if (base + i < n) rlen[base + i] = c[i];
+        }
+    }
+    const uint32_t incl = wave_incl_scan(sum);
+    if (lane == 63) wsum[wib] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (uint32_t w = 0; w < wib; w++) run += wsum[w];
+    for (uint32_t k = 0; k < per; k++) {
+        const uint32_t i = threadIdx.x * per + k;
+        if (i < R) {
+            const uint32_t x = c[i];
+            c[i] = run;
+            if (base + i < n) rowp[base + i] = lo + run;
+            run += x;
+        }
+    }
+    if (b == G.nbk - 1 && threadIdx.x == 0) rowp[n] = m;
+    __syncthreads();
+    for (uint64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
+        const uint4 r = part[j];
+        rec[lo + atomicAdd(&c[(uint32_t)(r.w - base)], 1u)] = r;
+    }
+}
+
 constexpr int BIG_TILE = 2048;
 
 // One block per long row: bitonic sort of 2048-entry tiles in LDS, then stable merges by
@@ -882,6 +1016,25 @@ __global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint
 } // namespace
 
 // ----------------------------------------------------------------------------- build
+// Buckets of 2^rb vertices, rb in [6, 14], at least ~2,048 buckets where n allows (bucket
+// blocks fill the device); partition blocks of >= 8,192 edges, at most 1,024 of them.
+PartGeom part_geometry(uint32_t n, uint64_t m) {
+    PartGeom G;
+    uint32_t rb = 6;
+    while (rb < 14 && ((uint64_t)n >> (rb + 1)) >= 2048) rb++;
+    G.rb = rb;
+    G.nbk = (uint32_t)(((uint64_t)n + (1ull << rb) - 1) >> rb);
+    if (G.nbk == 0) G.nbk = 1;
+    uint64_t nblk = (m + 8191) / 8192;
+    if (nblk > 1024) nblk = 1024;
+    if (nblk == 0) nblk = 1;
+    G.per = (m + nblk - 1) / nblk;
+    if (G.per == 0) G.per = 1;                    // m == 0
+    G.nblk = (uint32_t)((m + G.per - 1) / G.per); // no empty trailing block
+    if (G.nblk == 0) G.nblk = 1;
+    return G;
+}
+
 static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, const uint32_t *w) {
     const uint32_t n = g->n;
     const uint64_t m = g->m;
@@ -918,22 +1071,42 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     HIP_TRY(hipMemsetAsync(g->deg, 0, nn * 4, s));
     HIP_TRY(hipMemsetAsync(g->rlen, 0, nn * 4, s));
     HIP_TRY(hipMemsetAsync(g->maxw, 0, nn * 4, s));
-    if (m) {
-        HIP_TRY(hipMemcpyAsync(g->in_w, w, m * 4, hipMemcpyDeviceToDevice, s));
-        k_degree<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg);
-        // the weight-sorted arrays are filled by the row ranking; until then they hold each
-        // edge's tail and slot
-        k_outdeg<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg, g->rlen, g->wcol, g->wwgt);
+    if (m) HIP_TRY(hipMemcpyAsync(g->in_w, w, m * 4, hipMemcpyDeviceToDevice, s));
+    // rows in vertex order first (unsorted), rowp0[n] = m
+    const PartGeom PG = part_geometry(n, m);
+    if (m && PG.nbk <= PART_MAX_BUCKETS && (1u << PG.rb) <= PART_MAX_R) {
+        // partitioned: endpoints and then records grouped by vertex bucket, counted in LDS
+        const uint64_t nm = (uint64_t)PG.nbk * PG.nblk;
+        uint32_t *M = nullptr;
+        uint64_t *off = nullptr;
+        void *scan_tmp = nullptr, *grouped = nullptr; // grouped: endpoints (8m B), then records (16m B)
+        if ((rc = S.get((void **)&M, nm * 4)) || (rc = S.get((void **)&off, nm * 8)) ||
+            (rc = S.get(&scan_tmp, scan_tmp_bytes(nm))) || (rc = S.get(&grouped, m * 16)))
+            return rc;
+        k_part_count_ends<<<PG.nblk, 256, 0, s>>>(src, dst, m, PG, M);
+        if ((rc = exclusive_scan_u32_to_u64(M, off, nm, s, nullptr, scan_tmp))) return rc;
+        k_part_ends<<<PG.nblk, 256, 0, s>>>(src, dst, m, PG, off, (uint32_t *)grouped);
+        k_bucket_degree<<<PG.nbk, 256, 0, s>>>((const uint32_t *)grouped, off, 2 * m, PG, n, g->deg);
+        // the weight-sorted head array holds each edge's tail until the row ranking fills it
+        k_part_count_tails<<<PG.nblk, 256, 0, s>>>(src, dst, m, PG, g->deg, g->wcol, M);
+        if ((rc = exclusive_scan_u32_to_u64(M, off, nm, s, nullptr, scan_tmp))) return rc;
+        k_part_edges<<<PG.nblk, 256, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
+        k_bucket_rows<<<PG.nbk, 256, 0, s>>>((const uint4 *)grouped, off, m, PG, n, g->rlen, rowp0, rec0);
+        HIP_TRY(hipGetLastError());
+    } else {
+        if (m) {
+            k_degree<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg);
+            // the weight-sorted arrays are filled by the row ranking; until then they hold each
+            // edge's tail and slot
+            k_outdeg<<<grid_for(m), 256, 0, s>>>(src, dst, m, g->deg, g->rlen, g->wcol, g->wwgt);
+        }
+        void *scan_tmp = nullptr;
+        if ((rc = S.get(&scan_tmp, scan_tmp_bytes(nn))) ||
+            (rc = exclusive_scan_u32_to_u64(g->rlen, rowp0, nn, s, nullptr, scan_tmp)))
+            return rc;
+        if (m) k_scatter<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, g->wcol, g->wwgt, rowp0, rec0);
     }
-    // rows in vertex order first (unsorted): rowp0[n] = m
-    void *scan_tmp = nullptr;
-    if ((rc = S.get(&scan_tmp, scan_tmp_bytes(nn))) ||
-        (rc = exclusive_scan_u32_to_u64(g->rlen, rowp0, nn, s, nullptr, scan_tmp)))
-        return rc;
-    if (m) {
-        k_scatter<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, g->wcol, g->wwgt, rowp0, rec0);
-        k_row_max<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw);
-    }
+    if (m) k_row_max<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw);
     HIP_TRY(hipMemcpyAsync(g->hb, g->maxw, nn * 4, hipMemcpyDeviceToDevice, s));
     if (m) k_row_bound<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw, g->hb);
     // layout by descending weight_bin(hb)
