@@ -261,7 +261,9 @@ struct PartGeom {
     uint64_t per;           // edges per partition block
 };
 
-__global__ __launch_bounds__(256) void k_part_count_ends(const uint32_t *src, const uint32_t *dst, uint64_t m,
+constexpr int PART_THREADS = 256;
+
+__global__ __launch_bounds__(PART_THREADS) void k_part_count_ends(const uint32_t *src, const uint32_t *dst, uint64_t m,
                                                          PartGeom G, uint32_t *M) {
     __shared__ uint32_t h[PART_MAX_BUCKETS];
     for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) h[b] = 0;
@@ -275,17 +277,19 @@ __global__ __launch_bounds__(256) void k_part_count_ends(const uint32_t *src, co
     for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) M[(uint64_t)b * G.nblk + blockIdx.x] = h[b];
 }
 
-// Both ends of every edge into bucket order.
-__global__ __launch_bounds__(256) void k_part_ends(const uint32_t *src, const uint32_t *dst, uint64_t m, PartGeom G,
-                                                   const uint64_t *off, uint32_t *ep) {
-    __shared__ unsigned long long cur[PART_MAX_BUCKETS];
-    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) cur[b] = off[(uint64_t)b * G.nblk + blockIdx.x];
+// Both ends of every edge into bucket order.  C: the cursor type (32-bit when the output has
+// fewer than 2^32 entries, which halves the block's LDS).
+template <typename C>
+__global__ __launch_bounds__(PART_THREADS) void k_part_ends(const uint32_t *src, const uint32_t *dst, uint64_t m,
+                                                            PartGeom G, const uint64_t *off, uint32_t *ep) {
+    __shared__ C cur[PART_MAX_BUCKETS];
+    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) cur[b] = (C)off[(uint64_t)b * G.nblk + blockIdx.x];
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
     for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
         const uint32_t a = src[e], d = dst[e];
-        ep[atomicAdd(&cur[a >> G.rb], 1ull)] = a;
-        ep[atomicAdd(&cur[d >> G.rb], 1ull)] = d;
+        ep[atomicAdd(&cur[a >> G.rb], (C)1)] = a;
+        ep[atomicAdd(&cur[d >> G.rb], (C)1)] = d;
     }
 }
 
@@ -305,7 +309,7 @@ __global__ __launch_bounds__(256) void k_bucket_degree(const uint32_t *ep, const
 }
 
 // The tail of every edge (kept in etail) and tails per (bucket, block).
-__global__ __launch_bounds__(256) void k_part_count_tails(const uint32_t *src, const uint32_t *dst, uint64_t m,
+__global__ __launch_bounds__(PART_THREADS) void k_part_count_tails(const uint32_t *src, const uint32_t *dst, uint64_t m,
                                                           PartGeom G, const uint32_t *deg, uint32_t *etail,
                                                           uint32_t *M) {
     __shared__ uint32_t h[PART_MAX_BUCKETS];
@@ -323,16 +327,17 @@ __global__ __launch_bounds__(256) void k_part_count_tails(const uint32_t *src, c
 }
 
 // Every edge as a 16-byte record (head, weight, edge, tail) into tail-bucket order.
-__global__ __launch_bounds__(256) void k_part_edges(const uint32_t *src, const uint32_t *dst, const uint32_t *w,
-                                                    uint64_t m, PartGeom G, const uint32_t *etail,
-                                                    const uint64_t *off, uint4 *part) {
-    __shared__ unsigned long long cur[PART_MAX_BUCKETS];
-    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) cur[b] = off[(uint64_t)b * G.nblk + blockIdx.x];
+template <typename C>
+__global__ __launch_bounds__(PART_THREADS) void k_part_edges(const uint32_t *src, const uint32_t *dst, const uint32_t *w,
+                                                             uint64_t m, PartGeom G, const uint32_t *etail,
+                                                             const uint64_t *off, uint4 *part) {
+    __shared__ C cur[PART_MAX_BUCKETS];
+    for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) cur[b] = (C)off[(uint64_t)b * G.nblk + blockIdx.x];
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
     for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
         const uint32_t t = etail[e];
-        part[atomicAdd(&cur[t >> G.rb], 1ull)] = make_uint4(src[e] ^ dst[e] ^ t, w[e], (uint32_t)e, t);
+        part[atomicAdd(&cur[t >> G.rb], (C)1)] = make_uint4(src[e] ^ dst[e] ^ t, w[e], (uint32_t)e, t);
     }
 }
 
@@ -1017,7 +1022,8 @@ __global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint
 
 // ----------------------------------------------------------------------------- build
 // Buckets of 2^rb vertices, rb in [6, 14], at least ~2,048 buckets where n allows (bucket
-// blocks fill the device); partition blocks of >= 8,192 edges, at most 1,024 of them.
+// blocks fill the device); partition blocks of >= 8,192 edges, at most 1,024 of them (fewer,
+// larger blocks measured slower: the passes are bound by latency, not by the run lengths).
 PartGeom part_geometry(uint32_t n, uint64_t m) {
     PartGeom G;
     uint32_t rb = 6;
@@ -1083,14 +1089,16 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         if ((rc = S.get((void **)&M, nm * 4)) || (rc = S.get((void **)&off, nm * 8)) ||
             (rc = S.get(&scan_tmp, scan_tmp_bytes(nm))) || (rc = S.get(&grouped, m * 16)))
             return rc;
-        k_part_count_ends<<<PG.nblk, 256, 0, s>>>(src, dst, m, PG, M);
+        k_part_count_ends<<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, M);
         if ((rc = exclusive_scan_u32_to_u64(M, off, nm, s, nullptr, scan_tmp))) return rc;
-        k_part_ends<<<PG.nblk, 256, 0, s>>>(src, dst, m, PG, off, (uint32_t *)grouped);
+        if (2 * m < (1ull << 32)) k_part_ends<uint32_t><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, off, (uint32_t *)grouped);
+        else k_part_ends<unsigned long long><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, off, (uint32_t *)grouped);
         k_bucket_degree<<<PG.nbk, 256, 0, s>>>((const uint32_t *)grouped, off, 2 * m, PG, n, g->deg);
         // the weight-sorted head array holds each edge's tail until the row ranking fills it
-        k_part_count_tails<<<PG.nblk, 256, 0, s>>>(src, dst, m, PG, g->deg, g->wcol, M);
+        k_part_count_tails<<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, g->deg, g->wcol, M);
         if ((rc = exclusive_scan_u32_to_u64(M, off, nm, s, nullptr, scan_tmp))) return rc;
-        k_part_edges<<<PG.nblk, 256, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
+        if (m < (1ull << 32)) k_part_edges<uint32_t><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
+        else k_part_edges<unsigned long long><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
         k_bucket_rows<<<PG.nbk, 256, 0, s>>>((const uint4 *)grouped, off, m, PG, n, g->rlen, rowp0, rec0);
         HIP_TRY(hipGetLastError());
     } else {
