@@ -145,6 +145,19 @@ def test_long_rows_every_filter(tt):
                 assert_parity(got, want, p, ei, ctx=f"dense es p={p} budget={budget}")
 
 
+def test_huge_id_space(tt):
+    """3,000 vertices spread over IDs in [0, 150M): more vertex buckets than the partitioned build
+    takes, so the build counts degrees and places rows with global atomics instead."""
+    g = graphgen.chung_lu(3000, 30000, 2.3, 1.8, seed=11)
+    rng = np.random.default_rng(4)
+    ids = np.sort(rng.choice(150_000_000, size=3000, replace=False)).astype(np.uint32)
+    n, s, d, w = 150_000_000, ids[g.src], ids[g.dst], g.w
+    log(f"huge id space m={len(s)}")
+    with tt.Graph(n, s, d, w) as G:
+        for p in (1.0, math.inf, 2.0, -1.0):
+            check(tt, n, s, d, w, 100, p, G=G, ctx="huge ids")
+
+
 def test_planted_cliques(tt):
     g = graphgen.chung_lu(20000, 200000, 2.2, 1.8, seed=3, plant=8, plant_size=4, plant_mult=1000)
     log(f"planted m={g.m}")
