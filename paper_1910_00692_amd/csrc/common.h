@@ -99,6 +99,7 @@ struct QueryCtx {
 };
 void ctx_release(QueryCtx *q); // device memory and events (not the stream)
 int ensure_in_csr(tt_graph *g, hipStream_t s);
+int ensure_opos(tt_graph *g, hipStream_t s);
 
 // Entries in descending order of their bound m_p(w_uv, maxw(u), maxw(v)) (grouped by
 // weight_bin of an integer >= it), for one p: the entries that can be the base of a triangle
@@ -129,7 +130,7 @@ struct tt_graph {
     uint32_t *wgt = nullptr;    // [m] edge weight
     uint32_t *osrc = nullptr;   // [m] tail vertex u of each entry
     uint32_t *eid = nullptr;    // [m] input edge index of each entry
-    uint32_t *opos = nullptr;   // [m] entry position of each input edge
+    uint32_t *opos = nullptr;   // [m] entry position of each input edge (built by the first sampling query)
     uint32_t *wcol = nullptr;   // [m] the same rows sorted by weight descending (then head ID)
     uint32_t *wwgt = nullptr;   // [m]
     uint32_t *wpos = nullptr;   // [m] position of each weight-sorted entry in the head-sorted row

@@ -247,6 +247,12 @@ __global__ __launch_bounds__(256) void k_scatter(const uint32_t *src, const uint
     }
 }
 
+// opos[eid[p]] = p: the entry position of every input edge (needed by edge sampling only).
+__global__ __launch_bounds__(256) void k_make_opos(const uint32_t *eid, uint64_t m, uint32_t *opos) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += stride) opos[eid[p]] = (uint32_t)p;
+}
+
 // ----------------------------------------------------------------------------- partitioned front half
 // Degrees, row lengths and the row-grouped records without global atomics on vertices:
 // vertices are split into buckets of 2^rb consecutive IDs; a partition block takes a contiguous
@@ -561,16 +567,14 @@ constexpr uint32_t MID_MAX = 1024;   // rows ordered by a block in LDS
 constexpr int RANK_ITEMS = 2;        // window of RANK_ITEMS * 64 entries per wave
 
 // Writes one entry of a row (tail t, head c, weight w, input edge d) to both copies of the
-// final layout: head order at rank r1, weight order at rank r2; records its tail and the
-// position of its input edge.
+// final layout: head order at rank r1, weight order at rank r2; records its tail and input edge.
 __device__ __forceinline__ void put_entry(uint64_t P, uint32_t r1, uint32_t r2, uint32_t t, uint32_t c, uint32_t w,
                                           uint32_t d, uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
-                                          uint32_t *opos, uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos) {
+                                          uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos) {
     col[P + r1] = c;
     wgt[P + r1] = w;
     eid[P + r1] = d;
     osrc[P + r1] = t;
-    opos[d] = (uint32_t)(P + r1);
     wcol[P + r2] = c;
     wwgt[P + r2] = w;
     wpos[P + r2] = (uint32_t)(P + r1);
@@ -628,7 +632,7 @@ template <int R> __device__ __forceinline__ void block_bitonic(uint64_t (&k)[R],
 // weight desc, then head ID) over its own row only.  Equal heads in one row are a repeated pair.
 __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uint64_t *rowp0, uint64_t m,
                                                     const uint64_t *rstart, const uint32_t *rlen, uint32_t *col,
-                                                    uint32_t *wgt, uint32_t *eid, uint32_t *osrc, uint32_t *opos,
+                                                    uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
                                                     uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos, uint32_t *flags) {
     __shared__ uint32_t sc[4][RANK_ITEMS * 64], sw[4][RANK_ITEMS * 64];
     const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
@@ -670,7 +674,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
                 r2 += wf > wt[k] || (wf == wt[k] && before_id);
                 dup |= cf == c[k] && f != me;
             }
-            put_entry(rstart[t[k]], r1, r2, t[k], c[k], wt[k], d[k], col, wgt, eid, osrc, opos, wcol, wwgt, wpos);
+            put_entry(rstart[t[k]], r1, r2, t[k], c[k], wt[k], d[k], col, wgt, eid, osrc, wcol, wwgt, wpos);
         }
         __syncthreads();
     }
@@ -729,7 +733,7 @@ template <int R>
 __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P, uint32_t len, const uint4 *rec0,
                                              uint32_t *sc, uint32_t *sw, uint32_t *sd, uint32_t *hc, uint32_t *hw,
                                              uint64_t *xch, uint32_t *col, uint32_t *wgt, uint32_t *eid,
-                                             uint32_t *osrc, uint32_t *opos, uint32_t *wcol, uint32_t *wwgt,
+                                             uint32_t *osrc, uint32_t *wcol, uint32_t *wwgt,
                                              uint32_t *wpos, bool &dup) {
     const uint32_t t = threadIdx.x;
     uint64_t k[R];
@@ -756,7 +760,6 @@ __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P,
             wgt[P + s] = w;
             eid[P + s] = d;
             osrc[P + s] = u;
-            opos[d] = (uint32_t)(P + s);
             hc[s] = c;
             hw[s] = w;
         }
@@ -785,7 +788,7 @@ __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P,
 __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t nmid, const uint4 *rec0,
                                                   const uint64_t *rowp0, const uint64_t *rstart, const uint32_t *rlen,
                                                   uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
-                                                  uint32_t *opos, uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
+                                                  uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
                                                   uint32_t *flags) {
     static_assert(MID_MAX == 1024, "rows are sorted as up to 4 keys per thread");
     __shared__ uint32_t sc[MID_MAX], sw[MID_MAX], sd[MID_MAX], hc[MID_MAX], hw[MID_MAX];
@@ -795,11 +798,11 @@ __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t 
         const uint32_t u = mid[bi], len = rlen[u];
         const uint64_t b = rowp0[u], P = rstart[u];
         if (len <= 256)
-            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, opos, wcol, wwgt, wpos, dup);
+            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, dup);
         else if (len <= 512)
-            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, opos, wcol, wwgt, wpos, dup);
+            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, dup);
         else
-            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, opos, wcol, wwgt, wpos, dup);
+            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, dup);
     }
     if (__ballot(dup) && (threadIdx.x & 63) == 0) atomicOr(flags, F_DUP);
 }
@@ -821,12 +824,11 @@ __global__ __launch_bounds__(256) void k_move_big(const uint32_t *big, uint32_t 
     }
 }
 
-// After the head-ID sort of the long rows: positions of their input edges, the duplicate
-// check, and the keys of their weight-sorted copy.
+// After the head-ID sort of the long rows: the duplicate check and the keys of their
+// weight-sorted copy.
 __global__ __launch_bounds__(256) void k_post_big(const uint32_t *big, uint32_t nbig, const uint64_t *rstart,
                                                   const uint32_t *rlen, const uint32_t *col, const uint32_t *wgt,
-                                                  const uint32_t *eid, uint32_t *opos, uint64_t *wkey, uint32_t *wpos,
-                                                  uint32_t *flags) {
+                                                  uint64_t *wkey, uint32_t *wpos, uint32_t *flags) {
     bool dup = false;
     for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
         const uint32_t u = big[bi];
@@ -834,7 +836,6 @@ __global__ __launch_bounds__(256) void k_post_big(const uint32_t *big, uint32_t 
         for (uint32_t t = threadIdx.x; t < rlen[u]; t += blockDim.x) {
             const uint32_t c = col[b + t];
             if (t > 0 && col[b + t - 1] == c) dup = true;
-            opos[eid[b + t]] = (uint32_t)(b + t);
             wkey[b + t] = ((uint64_t)(~wgt[b + t]) << 32) | c; // ascending = weight desc, then ID
             wpos[b + t] = (uint32_t)(b + t);
         }
@@ -1067,7 +1068,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         (rc = dev_alloc(g, (void **)&g->rlen, nn * 4)) || (rc = dev_alloc(g, (void **)&g->maxw, nn * 4)) ||
         (rc = dev_alloc(g, (void **)&g->hb, nn * 4)) || (rc = dev_alloc(g, (void **)&g->col, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->wgt, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->osrc, (m + 1) * 4)) ||
-        (rc = dev_alloc(g, (void **)&g->eid, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->opos, (m + 1) * 4)) ||
+        (rc = dev_alloc(g, (void **)&g->eid, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->wcol, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->wwgt, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->wpos, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->in_w, (m + 1) * 4)) ||
         (rc = S.get((void **)&big, nn * 4)) ||
@@ -1140,7 +1141,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     }
     // both row orders: counted ranks for rows up to MID_MAX entries, sorts for longer ones
     if (m) k_rank_small<<<grid_for(m), 256, 0, s>>>(rec0, rowp0, m, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                                    g->opos, g->wcol, g->wwgt, g->wpos, flags);
+                                                    g->wcol, g->wwgt, g->wpos, flags);
     HIP_TRY(hipMemsetAsync(flags + 1, 0, 8, s));
     if (n) k_list_long<<<grid_for(n, 4096), 256, 0, s>>>(g->rlen, n, mid, flags + 2, big, flags + 1);
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
@@ -1149,7 +1150,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     if (nmid) {
         const unsigned gm = nmid < 8192u ? nmid : 8192u;
         k_rank_mid<<<gm, 256, 0, s>>>(mid, nmid, rec0, rowp0, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                      g->opos, g->wcol, g->wwgt, g->wpos, flags);
+                                      g->wcol, g->wwgt, g->wpos, flags);
     }
     if (nbig) {
         const unsigned gb = nbig < 4096u ? nbig : 4096u;
@@ -1157,7 +1158,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         if ((rc = sort_big<uint32_t>(g, S, g->rstart, g->rlen, big, nbig, g->col, g->wgt, g->eid))) return rc;
         uint64_t *wkey = nullptr;
         if ((rc = S.get((void **)&wkey, (m + 1) * 8))) return rc;
-        k_post_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->opos, wkey, g->wpos, flags);
+        k_post_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, g->col, g->wgt, wkey, g->wpos, flags);
         if ((rc = sort_big<uint64_t>(g, S, g->rstart, g->rlen, big, nbig, wkey, g->wpos, nullptr))) return rc;
         k_split_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, wkey, g->wcol, g->wwgt);
         S.drop(wkey);
@@ -1206,6 +1207,19 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     if (m) k_pack_cw<<<grid_for(m), 256, 0, s>>>(g->col, g->wgt, m, g->cw);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
+    return TT_OK;
+}
+
+// The entry position of every input edge (built once, on the first sampling query).
+int ensure_opos(tt_graph *g, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g->init_mu);
+    if (g->opos) return TT_OK;
+    uint32_t *opos = nullptr;
+    int rc = dev_alloc(g, (void **)&opos, (g->m + 1) * 4);
+    if (rc) return rc;
+    if (g->m) k_make_opos<<<grid_for(g->m), 256, 0, s>>>(g->eid, g->m, opos);
+    HIP_TRY(hipGetLastError());
+    g->opos = opos; // the caller's later work on s is ordered after the kernel
     return TT_OK;
 }
 

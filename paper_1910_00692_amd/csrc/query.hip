@@ -1121,6 +1121,7 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
     QueryCtx *q = &g->q;
     if ((rc = ensure_flags(g, q)) || (rc = ensure_scratch(g, q, 1, 1))) return rc;
     if (!g->emark && (rc = dev_alloc(g, (void **)&g->emark, g->m + 1))) return rc;
+    if ((rc = ensure_opos(g, q->stream))) return rc;
     const double qexp = (std::isfinite(p) && p > 0.0) ? p : 1.0;
     const int kind = qexp == 1.0 ? 0 : (qexp == 2.0 || qexp == 3.0) ? 1 : 2;
     hipStream_t s = q->stream;

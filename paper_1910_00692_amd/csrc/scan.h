@@ -2,7 +2,7 @@
 #pragma once
 #include "common.h"
 
-// Inclusive prefix sums of w_e^q over input edges e = 0..m-1 (weights read through opos).
+// Inclusive prefix sums of w_e^q over input edges e = 0..m-1 (weights in input order, in_w).
 // q = 1: uint64_t[m]; q = 2 or 3: u128[m]; any other q: double[m].  With tmp (at least
 // scan_tmp_bytes(m) bytes, kept by the caller until the stream has run the scan) nothing is
 // allocated and the call does not wait; without it the call waits for the scan.
