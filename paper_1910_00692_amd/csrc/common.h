@@ -100,6 +100,7 @@ struct QueryCtx {
 void ctx_release(QueryCtx *q); // device memory and events (not the stream)
 int ensure_in_csr(tt_graph *g, hipStream_t s);
 int ensure_opos(tt_graph *g, hipStream_t s);
+int ensure_weight_stream(tt_graph *g, hipStream_t s);
 
 // Entries in descending order of their bound m_p(w_uv, maxw(u), maxw(v)) (grouped by
 // weight_bin of an integer >= it), for one p: the entries that can be the base of a triangle

@@ -1191,16 +1191,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         uint64_t run = 0;
         for (int b = WBINS - 1; b >= 0; b--) { g->wbase[b] = run; run += g->whist[b]; }
     }
-    if ((rc = dev_alloc(g, (void **)&g->ws_src, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->ws_col, (m + 1) * 4)) ||
-        (rc = dev_alloc(g, (void **)&g->ws_wgt, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->ws_pos, (m + 1) * 4)))
-        return rc;
-    HIP_TRY(hipMemcpyAsync(binbase, g->wbase.data(), WBINS * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(bincur, 0, WBINS * 8, s));
-    if (m) {
-        const uint64_t per = 256ull * PLACE_ITEMS;
-        k_place_entries<<<(unsigned)((m + per - 1) / per), 256, 0, s>>>(g->osrc, g->col, g->wgt, m, binbase, bincur,
-                                                                        g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos);
-    }
+    // (the stream itself is placed by the first query that streams it: ensure_weight_stream)
     if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo))) || (rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8)))
         return rc;
     k_pack_vinfo<<<grid_for(nn), 256, 0, s>>>(g->rstart, g->rlen, g->maxw, nn, g->vinfo);
@@ -1219,7 +1210,44 @@ int ensure_opos(tt_graph *g, hipStream_t s) {
     if (rc) return rc;
     if (g->m) k_make_opos<<<grid_for(g->m), 256, 0, s>>>(g->eid, g->m, opos);
     HIP_TRY(hipGetLastError());
-    g->opos = opos; // the caller's later work on s is ordered after the kernel
+    HIP_TRY(hipStreamSynchronize(s)); // complete before other streams may see it
+    g->opos = opos;
+    return TT_OK;
+}
+
+// The entries in order of descending weight bin (built once, by the first query whose band
+// streams a prefix of it).
+int ensure_weight_stream(tt_graph *g, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g->init_mu);
+    if (g->ws_src) return TT_OK;
+    const uint64_t m = g->m;
+    int rc;
+    Scratch S;
+    S.stream = s;
+    uint32_t *ws[4] = {};
+    unsigned long long *binbase = nullptr, *bincur = nullptr;
+    for (auto &a : ws)
+        if ((rc = dev_alloc(g, (void **)&a, (m + 1) * 4))) {
+            for (auto &b : ws) dev_free(g, b, 0);
+            return rc;
+        }
+    if ((rc = S.get((void **)&binbase, WBINS * 8)) || (rc = S.get((void **)&bincur, WBINS * 8))) {
+        for (auto &b : ws) dev_free(g, b, 0);
+        return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(binbase, g->wbase.data(), WBINS * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(bincur, 0, WBINS * 8, s));
+    if (m) {
+        const uint64_t per = 256ull * PLACE_ITEMS;
+        k_place_entries<<<(unsigned)((m + per - 1) / per), 256, 0, s>>>(g->osrc, g->col, g->wgt, m, binbase, bincur,
+                                                                        ws[0], ws[1], ws[2], ws[3]);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s)); // complete before other streams may see it
+    g->ws_src = ws[0];
+    g->ws_col = ws[1];
+    g->ws_wgt = ws[2];
+    g->ws_pos = ws[3];
     return TT_OK;
 }
 

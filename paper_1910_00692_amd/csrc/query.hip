@@ -748,8 +748,15 @@ template <bool GEN> void enqueue_pair(int filter, const EnumArgs &A, unsigned ig
 // Enqueues one enumeration pass (no host synchronisation): the band's stream is filtered and
 // intersected in pieces of at most cand_cap entries.  `slot` picks its event pair.
 int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool gated, size_t slot) {
-    const Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len}
-                                   : pick_stream(g, q->ord, B.mode, B.p, B.L);
+    Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len}
+                             : pick_stream(g, q->ord, B.mode, B.p, B.L);
+    if (!q->sub_active && !S.src) {
+        // the weight-ordered stream is chosen but not placed yet (lazily built graph state,
+        // guarded by the graph's init lock)
+        int rc = ensure_weight_stream(const_cast<tt_graph *>(g), q->stream);
+        if (rc) return rc;
+        S = pick_stream(g, q->ord, B.mode, B.p, B.L);
+    }
     EnumArgs A;
     std::memset(&A, 0, sizeof(A));
     A.rstart = g->rstart;
