@@ -352,7 +352,8 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
                 u[k] = A.s_src[x];
                 v[k] = A.s_col[x];
                 a[k] = A.s_wgt[x];
-                if (!BATCH) pos[k] = A.s_pos ? A.s_pos[e] : (uint32_t)(e + A.pos_off);
+                // the entry position is needed only by the drawn-entry marks
+                if (!BATCH && FILTER == FILTER_EDGES) pos[k] = A.s_pos ? A.s_pos[e] : (uint32_t)(e + A.pos_off);
             }
         }
         uint32_t n_pass = 0, rank[FILTER_UNROLL];
@@ -733,10 +734,14 @@ __global__ void k_reduce_stats(unsigned long long *stats, unsigned long long *ou
     if (threadIdx.x == 0) out[c] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-// Between two passes: the later bands are skipped once the buffer holds >= k triangles (the
-// answer is complete) or has overflowed (the host restarts).
-__global__ void k_band_gate(const unsigned long long *count, unsigned long long k, unsigned long long *skip) {
-    if (threadIdx.x == 0 && blockIdx.x == 0 && *count >= k) *skip = 1;
+// Between two passes enqueued without a count read: the later bands are skipped once the
+// buffer holds any triangle (the host then reads the count and picks the next threshold from
+// it); *last records the last band allowed to run.
+__global__ void k_band_gate(const unsigned long long *count, unsigned long long *skip, unsigned long long band,
+                            unsigned long long *last) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || *skip) return;
+    if (*count > 0) *skip = 1;
+    else *last = band;
 }
 
 // An integer >= the score of every triangle based at entry u->v (m_p of the entry's weight

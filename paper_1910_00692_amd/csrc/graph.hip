@@ -347,6 +347,65 @@ __global__ __launch_bounds__(PART_THREADS) void k_part_edges(const uint32_t *src
     }
 }
 
+// Second level of the endpoint grouping.  With many buckets a partition block keeps too many
+// partly written lines open at once (one per bucket) for L2 to combine them, so the first level
+// groups the endpoints by coarse buckets of 2^s2 buckets (cs = rb + s2) and this level refines
+// each coarse group.  The input is grouped by coarse bucket, so a block's chunk [lo, hi)
+// touches only the buckets of its first to last coarse bucket: a window [fb0, fb1) of at most
+// nbk buckets.
+struct SegGeom {
+    uint32_t rb, cs, s2, nbk, nblk; // bucket shift, coarse shift, cs - rb, buckets, blocks
+    uint64_t per;                   // endpoints per block
+};
+
+__device__ __forceinline__ bool seg_window(const uint32_t *in, uint64_t total, const SegGeom &G, uint64_t &lo,
+                                           uint64_t &hi, uint32_t &fb0, uint32_t &fb1) {
+    lo = (uint64_t)blockIdx.x * G.per;
+    hi = lo + G.per < total ? lo + G.per : total;
+    if (lo >= hi) return false;
+    const uint32_t first = in[lo] >> G.cs, last = in[hi - 1] >> G.cs;
+    fb0 = first << G.s2;
+    const uint64_t e = (uint64_t)(last + 1) << G.s2;
+    fb1 = e < G.nbk ? (uint32_t)e : G.nbk;
+    return fb0 < fb1;
+}
+
+// Endpoints per (bucket, block); entries outside the block's window stay zero (cleared before).
+__global__ __launch_bounds__(PART_THREADS) void k_seg_count(const uint32_t *in, uint64_t total, SegGeom G,
+                                                            uint32_t *M) {
+    __shared__ uint32_t h[PART_MAX_BUCKETS];
+    uint64_t lo, hi;
+    uint32_t fb0, fb1;
+    if (!seg_window(in, total, G, lo, hi, fb0, fb1)) return;
+    const uint32_t W = fb1 - fb0;
+    for (uint32_t b = threadIdx.x; b < W; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        const uint32_t b = (in[e] >> G.rb) - fb0;
+        if (b < W) atomicAdd(&h[b], 1u);
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < W; b += blockDim.x) M[(uint64_t)(fb0 + b) * G.nblk + blockIdx.x] = h[b];
+}
+
+// C: the cursor type, as in k_part_ends.
+template <typename C>
+__global__ __launch_bounds__(PART_THREADS) void k_seg_scatter(const uint32_t *in, uint64_t total, SegGeom G,
+                                                              const uint64_t *off, uint32_t *out) {
+    __shared__ C cur[PART_MAX_BUCKETS];
+    uint64_t lo, hi;
+    uint32_t fb0, fb1;
+    if (!seg_window(in, total, G, lo, hi, fb0, fb1)) return;
+    const uint32_t W = fb1 - fb0;
+    for (uint32_t b = threadIdx.x; b < W; b += blockDim.x) cur[b] = (C)off[(uint64_t)(fb0 + b) * G.nblk + blockIdx.x];
+    __syncthreads();
+    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+        const uint32_t x = in[e];
+        const uint32_t b = (x >> G.rb) - fb0;
+        if (b < W) out[atomicAdd(&cur[b], (C)1)] = x;
+    }
+}
+
 // Rows of bucket b: records per tail (row lengths), their exclusive scan from the bucket's
 // first record (row starts, vertex order), then every record at its row's next slot.
 __global__ __launch_bounds__(256) void k_bucket_rows(const uint4 *part, const uint64_t *off, uint64_t m, PartGeom G,
@@ -1042,6 +1101,25 @@ PartGeom part_geometry(uint32_t n, uint64_t m) {
     return G;
 }
 
+// Blocks of the second partition level over `total` items (same block sizing as the first).
+SegGeom seg_geometry(const PartGeom &P, uint32_t s2, uint64_t total) {
+    SegGeom G;
+    G.rb = P.rb;
+    G.s2 = s2;
+    G.cs = P.rb + s2;
+    G.nbk = P.nbk;
+    uint64_t nblk = (total + 8191) / 8192;
+    if (nblk > 1024) nblk = 1024;
+    if (nblk == 0) nblk = 1;
+    G.per = (total + nblk - 1) / nblk;
+    if (G.per == 0) G.per = 1;
+    G.nblk = (uint32_t)((total + G.per - 1) / G.per);
+    if (G.nblk == 0) G.nblk = 1;
+    return G;
+}
+
+constexpr uint32_t PART_COARSE = 128; // at most this many buckets open per block and level
+
 static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, const uint32_t *w) {
     const uint32_t n = g->n;
     const uint64_t m = g->m;
@@ -1082,22 +1160,48 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     // rows in vertex order first (unsorted), rowp0[n] = m
     const PartGeom PG = part_geometry(n, m);
     if (m && PG.nbk <= PART_MAX_BUCKETS && (1u << PG.rb) <= PART_MAX_R) {
-        // partitioned: endpoints and then records grouped by vertex bucket, counted in LDS
-        const uint64_t nm = (uint64_t)PG.nbk * PG.nblk;
+        // partitioned: endpoints and then records grouped by vertex bucket, counted in LDS.  With
+        // more than PART_COARSE buckets the endpoints are grouped in two levels: coarse buckets
+        // of 2^s2 buckets, then each coarse group refined (k_seg_count / k_seg_scatter).
+        uint32_t s2 = 0;
+        while ((PG.nbk >> s2) > PART_COARSE) s2++;
+        PartGeom P1 = PG; // first level of the endpoint grouping: coarse buckets
+        P1.rb = PG.rb + s2;
+        P1.nbk = (uint32_t)(((uint64_t)n + (1ull << P1.rb) - 1) >> P1.rb);
+        const SegGeom E2 = seg_geometry(PG, s2, 2 * m);
+        PartGeom PE = PG; // bucket geometry of the final grouping of the endpoints
+        if (s2) {
+            PE.nblk = E2.nblk;
+            PE.per = E2.per;
+        }
+        const uint64_t nm = std::max(std::max((uint64_t)P1.nbk * P1.nblk, (uint64_t)PE.nbk * PE.nblk),
+                                     (uint64_t)PG.nbk * PG.nblk);
         uint32_t *M = nullptr;
         uint64_t *off = nullptr;
         void *scan_tmp = nullptr, *grouped = nullptr; // grouped: endpoints (8m B), then records (16m B)
         if ((rc = S.get((void **)&M, nm * 4)) || (rc = S.get((void **)&off, nm * 8)) ||
             (rc = S.get(&scan_tmp, scan_tmp_bytes(nm))) || (rc = S.get(&grouped, m * 16)))
             return rc;
-        k_part_count_ends<<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, M);
-        if ((rc = exclusive_scan_u32_to_u64(M, off, nm, s, nullptr, scan_tmp))) return rc;
-        if (2 * m < (1ull << 32)) k_part_ends<uint32_t><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, off, (uint32_t *)grouped);
-        else k_part_ends<unsigned long long><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, off, (uint32_t *)grouped);
-        k_bucket_degree<<<PG.nbk, 256, 0, s>>>((const uint32_t *)grouped, off, 2 * m, PG, n, g->deg);
-        // the weight-sorted head array holds each edge's tail until the row ranking fills it
+        // first level into rec0 when a second follows (rec0 is written only by k_bucket_rows)
+        uint32_t *ep1 = s2 ? (uint32_t *)rec0 : (uint32_t *)grouped;
+        const bool ends32 = 2 * m < (1ull << 32);
+        k_part_count_ends<<<P1.nblk, PART_THREADS, 0, s>>>(src, dst, m, P1, M);
+        if ((rc = exclusive_scan_u32_to_u64(M, off, (uint64_t)P1.nbk * P1.nblk, s, nullptr, scan_tmp))) return rc;
+        if (ends32) k_part_ends<uint32_t><<<P1.nblk, PART_THREADS, 0, s>>>(src, dst, m, P1, off, ep1);
+        else k_part_ends<unsigned long long><<<P1.nblk, PART_THREADS, 0, s>>>(src, dst, m, P1, off, ep1);
+        if (s2) {
+            const uint64_t nme = (uint64_t)PE.nbk * PE.nblk;
+            HIP_TRY(hipMemsetAsync(M, 0, nme * 4, s));
+            k_seg_count<<<E2.nblk, PART_THREADS, 0, s>>>(ep1, 2 * m, E2, M);
+            if ((rc = exclusive_scan_u32_to_u64(M, off, nme, s, nullptr, scan_tmp))) return rc;
+            if (ends32) k_seg_scatter<uint32_t><<<E2.nblk, PART_THREADS, 0, s>>>(ep1, 2 * m, E2, off, (uint32_t *)grouped);
+            else k_seg_scatter<unsigned long long><<<E2.nblk, PART_THREADS, 0, s>>>(ep1, 2 * m, E2, off, (uint32_t *)grouped);
+        }
+        k_bucket_degree<<<PE.nbk, 256, 0, s>>>((const uint32_t *)grouped, off, 2 * m, PE, n, g->deg);
+        // records in one level (a second level measured no faster for the 16-byte records).
+        // The weight-sorted head array holds each edge's tail until the row ranking fills it.
         k_part_count_tails<<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, g->deg, g->wcol, M);
-        if ((rc = exclusive_scan_u32_to_u64(M, off, nm, s, nullptr, scan_tmp))) return rc;
+        if ((rc = exclusive_scan_u32_to_u64(M, off, (uint64_t)PG.nbk * PG.nblk, s, nullptr, scan_tmp))) return rc;
         if (m < (1ull << 32)) k_part_edges<uint32_t><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
         else k_part_edges<unsigned long long><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
         k_bucket_rows<<<PG.nbk, 256, 0, s>>>((const uint4 *)grouped, off, m, PG, n, g->rlen, rowp0, rec0);

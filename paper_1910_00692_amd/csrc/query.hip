@@ -436,8 +436,10 @@ __global__ __launch_bounds__(256) void k_place_bound(const uint32_t *osrc, const
 
 // ----------------------------------------------------------------------------- host side
 // Candidates whose two rows hold at most this many entries together are intersected by a
-// lane-local merge (sequential reads of both rows) instead of binary searches.
-constexpr uint32_t MERGE_MAX = 64;
+// lane-local merge (sequential reads of both rows) instead of the flattened lookups.  Off on
+// this path: with the weight floors cutting each row to its admissible prefix, the lookups
+// measured faster at every threshold tried (32, 64, 128); the batched form still tunes it.
+constexpr uint32_t MERGE_MAX = 0;
 // Candidates with more admissible entries than this are spread over many waves.
 constexpr uint32_t HEAVY_MIN = 256;
 
@@ -847,52 +849,107 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     int rc = ensure_scratch(g, q, cap, k);
     if (rc) return rc;
     hipStream_t s = q->stream;
-    // thresholds: key(t, t, t) for t = weight of the k-th, 4k-th, 16k-th ... heaviest edge
-    // (for a subset query: of the k-th, 4k-th ... heaviest entry of its compact stream)
-    // (for a subset query: of its compact stream; with a bound order: the k-th, 4k-th ...
-    // highest entry bound)
+    // Thresholds: L = key(t, t, t) for t = the weight of the M-th heaviest edge (of a subset
+    // query's compact stream; with a bound order, the M-th highest entry bound), M = k, 4k,
+    // 16k ... while no triangle is found.  Once some are (c < k of them), the next rank is
+    // chosen from c: the count above a threshold grows roughly as the cube of the rank on these
+    // graphs, so M grows by (2k / c)^(1/3), between 1.25 and 4, one band at a time.  The last
+    // band (L = 0) is exhaustive.
     const std::vector<uint64_t> &hist = q->sub_active ? q->sub_hist : q->ord ? q->ord->hist : g->whist;
     const uint64_t total = q->sub_active ? q->sub_len : g->m;
-    std::vector<u128> Ls;
-    for (uint64_t M = k; M < (1ull << 62); M *= 4) {
-        if (M > total) break;
-        const uint32_t t = weight_at_rank(hist, M);
-        if (t <= 1) break;
-        const u128 L = key_of_uniform(mode, t);
-        if (Ls.empty() || L < Ls.back()) Ls.push_back(L);
-    }
-    Ls.push_back(0); // exhaustive
-    if ((rc = ensure_band_events(q, Ls.size()))) return rc;
+    // The first rank at or after M (growing by f) whose threshold lies below `below`.  Weights
+    // tie in large groups (small integers above all), so the group holding rank M can reach far
+    // past it; then the weight bin just above the group is taken when it still lies below
+    // `below` (a smaller step than asked for, instead of a much larger one).
+    auto next_band = [&](double M, double f, bool has_below, u128 below, double &Mout) -> u128 {
+        for (;;) {
+            if (M > (double)total) { Mout = (double)total; return 0; }
+            uint64_t cum = 0, above = 0; // entries in bins >= b, and in the bins above b
+            int b = WBINS - 1, b_up = -1;
+            for (; b >= 0; b--) {
+                if (hist[b] && cum + hist[b] >= (uint64_t)M) break;
+                if (hist[b]) b_up = b;
+                cum += hist[b];
+            }
+            if (b < 0) { Mout = M; return 0; }
+            above = cum;
+            cum += hist[b];
+            if (b_up >= 0 && (double)cum > 2.0 * M) {
+                const u128 Lu = key_of_uniform(mode, weight_bin_low((uint32_t)b_up));
+                if (!has_below || Lu < below) { Mout = (double)above; return Lu; }
+            }
+            const uint32_t t = weight_bin_low((uint32_t)b);
+            if (t <= 1) { Mout = M; return 0; }
+            const u128 L = key_of_uniform(mode, t);
+            if (!has_below || L < below) { Mout = M; return L; }
+            M *= f;
+        }
+    };
     HIP_TRY(hipMemsetAsync(q->dcount, 0, 8 * sizeof(unsigned long long), s));
     HIP_TRY(hipMemsetAsync(q->dcount + 12, 0, 2 * sizeof(unsigned long long), s));
     HIP_TRY(hipEventRecord(q->ev[0], s));
-    // The first band often holds the whole answer, so the host reads the count after it.
-    // Later bands are enqueued without waiting while their pieces fit EAGER_PIECES; a band
-    // that finds the buffer already holding >= k triangles (the answer is complete) or
-    // overflowed returns at once.  Past that budget the host reads the count again first.
-    size_t launched = 0;
-    uint64_t pending = 0;
-    bool counted = false; // hcount[0] already holds the final count
-    for (size_t i = 0; i < Ls.size(); i++) {
-        const Band B = make_band(mode, p, Ls[i], ~0u, ~0u, ~0u, i > 0, i > 0 ? Ls[i - 1] : 0);
-        const uint64_t np = band_pieces(g, q, B);
-        if (i == 1 || (pending > 0 && pending + np > EAGER_PIECES)) {
-            HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (q->hcount[0] >= k) { counted = true; break; } // complete, or overflowed (>= 16k held)
-            pending = 0;
-        }
-        if (i > 0) {
-            k_band_gate<<<1, 64, 0, s>>>(q->dcount, k, q->dcount + 7);
+    std::vector<u128> Ls;     // thresholds of the bands enqueued, in order
+    std::vector<double> Ms;   // their ranks
+    size_t launched = 0;      // bands whose events are recorded
+    auto enqueue = [&](u128 L, double M, bool gated) -> int {
+        const size_t i = Ls.size();
+        int r = ensure_band_events(q, launched + 1);
+        if (r) return r;
+        if (gated) {
+            k_band_gate<<<1, 64, 0, s>>>(q->dcount, q->dcount + 7, (unsigned long long)i, q->dcount + 6);
             HIP_TRY(hipGetLastError());
         }
-        if ((rc = launch_enum(g, q, B, filter, true, i))) return rc;
-        pending += np;
+        const Band B = make_band(mode, p, L, ~0u, ~0u, ~0u, i > 0, i > 0 ? Ls.back() : 0);
+        if ((r = launch_enum(g, q, B, filter, gated, launched))) return r;
+        Ls.push_back(L);
+        Ms.push_back(M);
         launched++;
-    }
-    if (!counted) {
-        HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8, hipMemcpyDeviceToHost, s));
+        return TT_OK;
+    };
+    auto read_count = [&]() -> int {
+        HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        return TT_OK;
+    };
+    {
+        double M0;
+        const u128 L0 = next_band((double)k, 4.0, false, 0, M0);
+        if ((rc = enqueue(L0, M0, false)) || (rc = read_count())) return rc;
+    }
+    // The first band often holds the whole answer, so the host reads the count after it.
+    // While the count is zero, later bands (x4 in rank) are enqueued without waiting while
+    // their pieces fit EAGER_PIECES; the gate before each stops the rest once the buffer holds
+    // any triangle (or the answer is complete) and records the last band that ran.
+    size_t last = 0; // index of the last band that ran
+    while (q->hcount[0] < k && Ls.back() != 0) {
+        const uint64_t c = q->hcount[0];
+        if (c == 0) {
+            uint64_t pending = 0;
+            double M = Ms[last] * 4.0;
+            while (Ls.back() != 0) {
+                double Mn;
+                const u128 L = next_band(M, 4.0, true, Ls.back(), Mn);
+                const Band B = make_band(mode, p, L, ~0u, ~0u, ~0u, true, Ls.back());
+                const uint64_t np = band_pieces(g, q, B);
+                if (pending > 0 && pending + np > EAGER_PIECES) break;
+                if ((rc = enqueue(L, Mn, true))) return rc;
+                pending += np;
+                M = Mn * 4.0;
+            }
+            if ((rc = read_count())) return rc;
+            last = q->hcount[7] ? (size_t)q->hcount[6] : Ls.size() - 1;
+            if (q->hcount[0] >= k) break;
+            // paused after the first band with triangles: drop the bands that did not run (the
+            // bands from here on are not gated, so the skip flag stays as it is)
+            Ls.resize(last + 1);
+            Ms.resize(last + 1);
+        } else {
+            const double f = std::min(4.0, std::max(1.25, std::cbrt(2.0 * (double)k / (double)c)));
+            double Mn;
+            const u128 L = next_band(Ms[last] * f, f, true, Ls.back(), Mn);
+            if ((rc = enqueue(L, Mn, false)) || (rc = read_count())) return rc;
+            last = Ls.size() - 1;
+        }
     }
     add_enum_time(q, st, launched);
     uint64_t cnt = q->hcount[0];
