@@ -139,10 +139,13 @@ struct tt_graph {
     // of a qualifying triangle must weigh >= z, the entries that can be its base are a prefix.
     uint32_t *ws_src = nullptr, *ws_col = nullptr, *ws_wgt = nullptr;
     uint32_t *ws_pos = nullptr; // head-sorted position of each such entry
+    uint32_t *ws_hmx = nullptr; // row maximum of each such entry's head
     std::vector<uint64_t> wbase; // host: first entry of each weight bin (bins descending)
     uint32_t *maxw = nullptr;   // [n] largest weight in u's out-row (0 for an empty row)
     VInfo *vinfo = nullptr;     // [n+1] rstart, rlen, maxw packed (the intersection's reads)
     uint2 *cw = nullptr;        // [m] (col, wgt) interleaved: a binary-search hit holds the weight
+    uint32_t *hmx = nullptr;    // [m] maxw of each entry's head: the filter's bound test streams it
+                                //     instead of gathering maxw[v] at random
     uint32_t *hb = nullptr;     // [n] max(maxw[u], maxw[v] over out-neighbours v): bounds every
                                 //     triangle based at u, for every p
     uint32_t *deg = nullptr;    // [n] undirected degree

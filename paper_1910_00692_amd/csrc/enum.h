@@ -172,6 +172,7 @@ struct EnumArgs {
     // the stream of candidate entries (tail, head, weight, head-sorted position or NULL if the
     // stream is the head-sorted layout itself) and its length
     const uint32_t *s_src, *s_col, *s_wgt, *s_pos;
+    const uint32_t *s_hmx; // maxw of each stream entry's head (single-graph streams), else NULL
     uint64_t E;
     uint64_t pos_off; // head-sorted position of stream entry 0 when s_pos is NULL
     const unsigned long long *skip; // set (between passes) once the answer is complete
@@ -335,13 +336,13 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
     uint32_t gcur = 0; // batched form: graph of this lane's latest entry
     if (BATCH && lo < hi) gcur = graph_search(A.poff, A.ng, lo);
     for (uint64_t base = lo + (threadIdx.x >> 6) * 64 * FILTER_UNROLL; base < hi; base += blockDim.x * FILTER_UNROLL) {
-        uint32_t u[FILTER_UNROLL], v[FILTER_UNROLL], a[FILTER_UNROLL], pos[FILTER_UNROLL];
+        uint32_t u[FILTER_UNROLL], v[FILTER_UNROLL], a[FILTER_UNROLL], pos[FILTER_UNROLL], mv[FILTER_UNROLL];
         bool pass[FILTER_UNROLL];
 #pragma unroll
         for (int k = 0; k < FILTER_UNROLL; k++) {
             const uint64_t e = base + (uint64_t)k * 64 + lane;
             pass[k] = e < hi;
-            u[k] = v[k] = a[k] = pos[k] = 0;
+            u[k] = v[k] = a[k] = pos[k] = mv[k] = 0;
             if (pass[k]) {
                 uint64_t x = e;
                 if (BATCH) {
@@ -352,6 +353,7 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
                 u[k] = A.s_src[x];
                 v[k] = A.s_col[x];
                 a[k] = A.s_wgt[x];
+                if (!BATCH && A.s_hmx) mv[k] = A.s_hmx[x];
                 // the entry position is needed only by the drawn-entry marks
                 if (!BATCH && FILTER == FILTER_EDGES) pos[k] = A.s_pos ? A.s_pos[e] : (uint32_t)(e + A.pos_off);
             }
@@ -365,7 +367,7 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
                 else if (FILTER == FILTER_VERTICES)
                     pre = A.vflag[u[k]] || A.vflag[v[k]] || (A.vflag2[u[k]] && A.vflag2[v[k]]);
                 if (BATCH) pass[k] = bound_ok<GEN>(A.bands[pos[k]], a[k], A.maxw[u[k]], A.maxw[v[k]]);
-                else pass[k] = pre && bound_ok<GEN>(A.B, a[k], A.maxw[u[k]], A.maxw[v[k]]);
+                else pass[k] = pre && bound_ok<GEN>(A.B, a[k], A.maxw[u[k]], A.s_hmx ? mv[k] : A.maxw[v[k]]);
             }
             const uint64_t bal = __ballot(pass[k]);
             rank[k] = n_pass + __popcll(bal & ((1ull << lane) - 1ull));

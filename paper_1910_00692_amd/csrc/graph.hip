@@ -593,6 +593,8 @@ __global__ __launch_bounds__(256) void k_bin_entries(const uint32_t *hb, const u
 }
 
 constexpr int PLACE_ITEMS = 16;
+// Graphs with at least this many vertices (row maxima of >= 64 MB) keep maxw of each entry's head.
+constexpr uint32_t HMX_MIN_N = 1u << 24;
 
 // Row starts grouped by bin: offsets inside the block come from LDS atomics, then one global
 // atomic per (block, non-empty bin) reserves the block's range inside the bin.
@@ -920,8 +922,9 @@ __global__ __launch_bounds__(256) void k_split_big(const uint32_t *big, uint32_t
 // atomic per (block, non-empty bin) to reserve the block's range inside the bin.
 __global__ __launch_bounds__(256) void k_place_entries(const uint32_t *osrc, const uint32_t *col, const uint32_t *wgt,
                                                        uint64_t m, const unsigned long long *binbase,
-                                                       unsigned long long *bincur, uint32_t *ws_src, uint32_t *ws_col,
-                                                       uint32_t *ws_wgt, uint32_t *ws_pos) {
+                                                       unsigned long long *bincur, const uint32_t *hmx, uint32_t *ws_src,
+                                                       uint32_t *ws_col, uint32_t *ws_wgt, uint32_t *ws_pos,
+                                                       uint32_t *ws_hmx) {
     __shared__ uint32_t lc[WBINS];
     __shared__ unsigned long long lb[WBINS];
     for (int t = threadIdx.x; t < WBINS; t += blockDim.x) lc[t] = 0;
@@ -948,6 +951,7 @@ __global__ __launch_bounds__(256) void k_place_entries(const uint32_t *osrc, con
             ws_col[d] = col[e];
             ws_wgt[d] = w;
             ws_pos[d] = (uint32_t)e;
+            if (hmx) ws_hmx[d] = hmx[e];
         }
     }
 }
@@ -982,7 +986,7 @@ void release(tt_graph *g) {
     void *ptrs[] = {g->rstart, g->rlen,   g->col,    g->wgt,  g->osrc,    g->eid,   g->opos,
                     g->wcol,   g->wwgt,   g->wpos,   g->maxw, g->hb,      g->deg,   g->emark,
                     g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->in_w,  g->irstart, g->itail,
-                    g->vinfo,  g->cw};
+                    g->vinfo,  g->cw,     g->hmx,    g->ws_hmx};
     for (void *p : ptrs) dev_free(g, p, 0);
     for (auto &t : g->tables) {
         dev_free(g, t.prefix, 0);
@@ -1073,9 +1077,13 @@ __global__ __launch_bounds__(256) void k_pack_vinfo(const uint64_t *rstart, cons
         vi[v] = VInfo{rstart[v], rlen[v], maxw[v]};
 }
 
-__global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint32_t *wgt, uint64_t m, uint2 *cw) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
-        cw[e] = make_uint2(col[e], wgt[e]);
+__global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint32_t *wgt, const uint32_t *maxw,
+                                                 uint64_t m, uint2 *cw, uint32_t *hmx) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = col[e];
+        cw[e] = make_uint2(v, wgt[e]);
+        if (hmx) hmx[e] = maxw[v];
+    }
 }
 
 } // namespace
@@ -1296,10 +1304,13 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         for (int b = WBINS - 1; b >= 0; b--) { g->wbase[b] = run; run += g->whist[b]; }
     }
     // (the stream itself is placed by the first query that streams it: ensure_weight_stream)
-    if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo))) || (rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8)))
+    // The per-entry head maxima pay only where the row maxima no longer stay in the caches
+    // (then the filter's gather of maxw[v] misses to HBM for nearly every streamed entry).
+    if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo))) || (rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8)) ||
+        (n >= HMX_MIN_N && (rc = dev_alloc(g, (void **)&g->hmx, (m + 1) * 4))))
         return rc;
     k_pack_vinfo<<<grid_for(nn), 256, 0, s>>>(g->rstart, g->rlen, g->maxw, nn, g->vinfo);
-    if (m) k_pack_cw<<<grid_for(m), 256, 0, s>>>(g->col, g->wgt, m, g->cw);
+    if (m) k_pack_cw<<<grid_for(m), 256, 0, s>>>(g->col, g->wgt, g->maxw, m, g->cw, g->hmx);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
     return TT_OK;
@@ -1328,10 +1339,10 @@ int ensure_weight_stream(tt_graph *g, hipStream_t s) {
     int rc;
     Scratch S;
     S.stream = s;
-    uint32_t *ws[4] = {};
+    uint32_t *ws[5] = {};
     unsigned long long *binbase = nullptr, *bincur = nullptr;
-    for (auto &a : ws)
-        if ((rc = dev_alloc(g, (void **)&a, (m + 1) * 4))) {
+    for (int i = 0; i < (g->hmx ? 5 : 4); i++)
+        if ((rc = dev_alloc(g, (void **)&ws[i], (m + 1) * 4))) {
             for (auto &b : ws) dev_free(g, b, 0);
             return rc;
         }
@@ -1344,14 +1355,15 @@ int ensure_weight_stream(tt_graph *g, hipStream_t s) {
     if (m) {
         const uint64_t per = 256ull * PLACE_ITEMS;
         k_place_entries<<<(unsigned)((m + per - 1) / per), 256, 0, s>>>(g->osrc, g->col, g->wgt, m, binbase, bincur,
-                                                                        ws[0], ws[1], ws[2], ws[3]);
+                                                                        g->hmx, ws[0], ws[1], ws[2], ws[3], ws[4]);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s)); // complete before other streams may see it
-    g->ws_src = ws[0];
+    g->ws_hmx = ws[4];
     g->ws_col = ws[1];
     g->ws_wgt = ws[2];
     g->ws_pos = ws[3];
+    g->ws_src = ws[0]; // last: its presence announces the stream
     return TT_OK;
 }
 

@@ -582,13 +582,14 @@ uint64_t entries_for(const tt_graph *g, int mode, u128 L) {
 struct Stream {
     const uint32_t *src, *col, *wgt, *pos;
     uint64_t E;
+    const uint32_t *hmx; // row maximum of each entry's head, or NULL (then gathered)
 };
 
 // The shortest of the streams that hold every possible base entry of a band triangle: rows
 // with hb >= score floor (row order), entries with weight >= weight floor, and (when the
 // query has one) entries whose bound reaches the score floor.
 Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u128 L) {
-    Stream r{g->osrc, g->col, g->wgt, nullptr, entries_for(g, mode, L)};
+    Stream r{g->osrc, g->col, g->wgt, nullptr, entries_for(g, mode, L), g->hmx};
     const uint64_t z = weight_floor(mode, p, L, g->wmax);
     uint64_t E2 = g->m;
     if (z > 0xFFFFFFFFull) E2 = 0;
@@ -596,7 +597,7 @@ Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u
         const uint32_t b = weight_bin((uint32_t)z);
         E2 = g->wbase[b] + g->whist[b];
     }
-    if (E2 < r.E) r = Stream{g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, E2};
+    if (E2 < r.E) r = Stream{g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, E2, g->ws_hmx};
     if (o) {
         const uint64_t t = score_floor(mode, L);
         uint64_t E3 = g->m;
@@ -605,7 +606,7 @@ Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u
             const uint32_t b = weight_bin((uint32_t)t);
             E3 = o->base[b] + o->hist[b];
         }
-        if (E3 < r.E) r = Stream{o->src, o->col, o->wgt, o->pos, E3};
+        if (E3 < r.E) r = Stream{o->src, o->col, o->wgt, o->pos, E3, nullptr};
     }
     return r;
 }
@@ -750,7 +751,7 @@ template <bool GEN> void enqueue_pair(int filter, const EnumArgs &A, unsigned ig
 // Enqueues one enumeration pass (no host synchronisation): the band's stream is filtered and
 // intersected in pieces of at most cand_cap entries.  `slot` picks its event pair.
 int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool gated, size_t slot) {
-    Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len}
+    Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len, nullptr}
                              : pick_stream(g, q->ord, B.mode, B.p, B.L);
     if (!q->sub_active && !S.src) {
         // the weight-ordered stream is chosen but not placed yet (lazily built graph state,
@@ -796,6 +797,7 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
         A.s_col = S.col + off;
         A.s_wgt = S.wgt + off;
         A.s_pos = S.pos ? S.pos + off : nullptr;
+        A.s_hmx = S.hmx ? S.hmx + off : nullptr;
         A.pos_off = off;
         A.E = E;
         A.nseg = filter_grid(E);

@@ -158,6 +158,25 @@ def test_huge_id_space(tt):
             check(tt, n, s, d, w, 100, p, G=G, ctx="huge ids")
 
 
+def test_head_maxima_id_space(tt):
+    """20,000 vertices spread over IDs in [0, 20M): the partitioned build, and enough vertex IDs
+    (>= 2^24) that every entry keeps its head's row maximum for the filter, in the head-sorted
+    stream and in the weight-ordered one (p = -inf streams the latter), exact and sampled."""
+    g = graphgen.chung_lu(20000, 200000, 2.2, 1.8, seed=12)
+    rng = np.random.default_rng(6)
+    ids = np.sort(rng.choice(20_000_000, size=20000, replace=False)).astype(np.uint32)
+    n, s, d, w = 20_000_000, ids[g.src], ids[g.dst], g.w
+    log(f"head maxima id space m={len(s)}")
+    ei = EdgeIndex(s, d, w)
+    with tt.Graph(n, s, d, w) as G:
+        for p in (-math.inf, 1.0, 2.0, math.inf, -1.0):
+            check(tt, n, s, d, w, 100, p, G=G, ctx="head maxima")
+        for p in (1.0, -math.inf):
+            got = G.sample(100, p, 20000, 5)
+            want = oracle.sample_heavy_triangles(n, s, d, w, 100, p, 20000, 5)
+            assert_parity(got, want, p, ei, ctx=f"head maxima es p={p}")
+
+
 def test_planted_cliques(tt):
     g = graphgen.chung_lu(20000, 200000, 2.2, 1.8, seed=3, plant=8, plant_size=4, plant_mult=1000)
     log(f"planted m={g.m}")
