@@ -56,7 +56,7 @@ def recorded_traffic(workload):
     """HBM bytes per enumeration pass from the counter runs summarised in profiles/, or None if
     they were taken on another workload or the enumeration sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_enum_medium_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"k_enum_{workload}_traffic.md")
     try:
         fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
     except OSError:
@@ -255,6 +255,8 @@ def main():
     ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS) + ["serve", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sampling", action="store_true", help="exact queries only")
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the resident-graph queries after the timed steps (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device 3 times (a kernel of known traffic for counter runs)")
     ap.add_argument("--requests", type=int, default=2000, help="served workload: number of requests")
@@ -361,7 +363,7 @@ def main():
                 "bytes_per_launch": alg_bytes / launches, "mean_launch_ms": mean_launch_ms, "launches": launches}
 
     warm = {}
-    if W.get("cpu_edges"):
+    if W.get("cpu_edges") and not args.no_warm:
         # queries on a resident CSR (the steps above build it cold every time): the second query
         # of each p, then the steady state once repeated queries of p have built its bound order
         def brief(r):
