@@ -737,8 +737,8 @@ __global__ void k_reduce_stats(unsigned long long *stats, unsigned long long *ou
 }
 
 // Between two passes enqueued without a count read: the later bands are skipped once the
-// buffer holds `need` triangles (1: the host then picks the next threshold from the count; k:
-// the answer is complete, or the buffer overflowed); *last records the last band allowed to run.
+// buffer holds `need` triangles (the host then reads the count: the answer is complete, or the
+// next threshold follows from it); *last records the last band allowed to run.
 __global__ void k_band_gate(const unsigned long long *count, unsigned long long need, unsigned long long *skip,
                             unsigned long long band, unsigned long long *last) {
     if (threadIdx.x != 0 || blockIdx.x != 0 || *skip) return;
