@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 #include <mutex>
+#include <atomic>
 #include <algorithm>
 #include <new>
 
@@ -100,7 +101,7 @@ struct QueryCtx {
 void ctx_release(QueryCtx *q); // device memory and events (not the stream)
 int ensure_in_csr(tt_graph *g, hipStream_t s);
 int ensure_opos(tt_graph *g, hipStream_t s);
-int ensure_weight_stream(tt_graph *g, hipStream_t s);
+int ensure_weight_stream(tt_graph *g, hipStream_t s, uint32_t bin);
 
 // Entries in descending order of their bound m_p(w_uv, maxw(u), maxw(v)) (grouped by
 // weight_bin of an integer >= it), for one p: the entries that can be the base of a triangle
@@ -140,6 +141,8 @@ struct tt_graph {
     uint32_t *ws_src = nullptr, *ws_col = nullptr, *ws_wgt = nullptr;
     uint32_t *ws_pos = nullptr; // head-sorted position of each such entry
     uint32_t *ws_hmx = nullptr; // row maximum of each such entry's head
+    unsigned long long *ws_base = nullptr; // [WBINS] device copy of wbase
+    std::atomic<uint32_t> ws_low{2048u}; // bins >= ws_low are in place (set after they are); 2048 = WBINS
     std::vector<uint64_t> wbase; // host: first entry of each weight bin (bins descending)
     uint32_t *maxw = nullptr;   // [n] largest weight in u's out-row (0 for an empty row)
     VInfo *vinfo = nullptr;     // [n+1] rstart, rlen, maxw packed (the intersection's reads)
@@ -187,6 +190,7 @@ struct tt_graph {
 // ----------------------------------------------------------------------------- weight bins
 // 2048 log-spaced bins: w < 64 exact; otherwise 64 bins per octave.
 constexpr int WBINS = 2048;
+static_assert(WBINS == 2048, "tt_graph::ws_low starts at WBINS");
 __host__ __device__ inline uint32_t weight_bin(uint32_t w) {
     if (w < 64) return w;
     uint32_t e = 31u - (uint32_t)__builtin_clz(w);          // 6..31

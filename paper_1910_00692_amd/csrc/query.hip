@@ -583,21 +583,22 @@ struct Stream {
     const uint32_t *src, *col, *wgt, *pos;
     uint64_t E;
     const uint32_t *hmx; // row maximum of each entry's head, or NULL (then gathered)
+    uint32_t wbin;       // the weight-ordered stream: the lowest bin it reads; else WBINS
 };
 
 // The shortest of the streams that hold every possible base entry of a band triangle: rows
 // with hb >= score floor (row order), entries with weight >= weight floor, and (when the
 // query has one) entries whose bound reaches the score floor.
 Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u128 L) {
-    Stream r{g->osrc, g->col, g->wgt, nullptr, entries_for(g, mode, L), g->hmx};
+    Stream r{g->osrc, g->col, g->wgt, nullptr, entries_for(g, mode, L), g->hmx, (uint32_t)WBINS};
     const uint64_t z = weight_floor(mode, p, L, g->wmax);
-    uint64_t E2 = g->m;
-    if (z > 0xFFFFFFFFull) E2 = 0;
-    else if (z > 0) {
+    if (z > 0xFFFFFFFFull) {
+        r.E = 0; // no edge is heavy enough
+    } else if (z > 0) {
         const uint32_t b = weight_bin((uint32_t)z);
-        E2 = g->wbase[b] + g->whist[b];
+        const uint64_t E2 = g->wbase[b] + g->whist[b];
+        if (E2 < r.E) r = Stream{g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, E2, g->ws_hmx, b};
     }
-    if (E2 < r.E) r = Stream{g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, E2, g->ws_hmx};
     if (o) {
         const uint64_t t = score_floor(mode, L);
         uint64_t E3 = g->m;
@@ -606,7 +607,7 @@ Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u
             const uint32_t b = weight_bin((uint32_t)t);
             E3 = o->base[b] + o->hist[b];
         }
-        if (E3 < r.E) r = Stream{o->src, o->col, o->wgt, o->pos, E3, nullptr};
+        if (E3 < r.E) r = Stream{o->src, o->col, o->wgt, o->pos, E3, nullptr, (uint32_t)WBINS};
     }
     return r;
 }
@@ -751,12 +752,12 @@ template <bool GEN> void enqueue_pair(int filter, const EnumArgs &A, unsigned ig
 // Enqueues one enumeration pass (no host synchronisation): the band's stream is filtered and
 // intersected in pieces of at most cand_cap entries.  `slot` picks its event pair.
 int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool gated, size_t slot) {
-    Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len, nullptr}
+    Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len, nullptr, (uint32_t)WBINS}
                              : pick_stream(g, q->ord, B.mode, B.p, B.L);
-    if (!q->sub_active && !S.src) {
-        // the weight-ordered stream is chosen but not placed yet (lazily built graph state,
-        // guarded by the graph's init lock)
-        int rc = ensure_weight_stream(const_cast<tt_graph *>(g), q->stream);
+    if (!q->sub_active && S.wbin < (uint32_t)WBINS && g->ws_low.load(std::memory_order_acquire) > S.wbin) {
+        // the weight-ordered stream is chosen but its bins down to S.wbin are not placed yet
+        // (lazily built graph state, guarded by the graph's init lock)
+        int rc = ensure_weight_stream(const_cast<tt_graph *>(g), q->stream, S.wbin);
         if (rc) return rc;
         S = pick_stream(g, q->ord, B.mode, B.p, B.L);
     }

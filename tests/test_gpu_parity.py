@@ -177,6 +177,25 @@ def test_head_maxima_id_space(tt):
             assert_parity(got, want, p, ei, ctx=f"head maxima es p={p}")
 
 
+def test_weight_stream_placed_in_parts(tt, monkeypatch):
+    """The weight-ordered stream placed bin range by bin range, as on graphs of more than 2^27
+    entries (forced here on a small graph): p = -inf descends through several bands that stream
+    ever longer prefixes of it, exact and sampled, each against the oracle; then p = 1 and a
+    second graph whose first query needs the whole stream at once."""
+    monkeypatch.setenv("TT_WS_ALL_AT_ONCE", "0")
+    g = graphgen.chung_lu(30000, 300000, 2.1, 1.8, seed=13)
+    log(f"weight stream in parts m={g.m}")
+    ei = EdgeIndex(g.src, g.dst, g.w)
+    with tt.Graph(g.n, g.src, g.dst, g.w) as G:
+        for p in (-math.inf, 1.0, 2.0, math.inf):
+            check(tt, g.n, g.src, g.dst, g.w, 300, p, G=G, ctx="ws parts")
+        got = G.sample(300, -math.inf, 50000, 9)
+        want = oracle.sample_heavy_triangles(g.n, g.src, g.dst, g.w, 300, -math.inf, 50000, 9)
+        assert_parity(got, want, -math.inf, ei, ctx="ws parts es")
+    with tt.Graph(g.n, g.src, g.dst, g.w) as G:
+        check(tt, g.n, g.src, g.dst, g.w, 30000, -math.inf, G=G, ctx="ws parts big k")
+
+
 def test_planted_cliques(tt):
     g = graphgen.chung_lu(20000, 200000, 2.2, 1.8, seed=3, plant=8, plant_size=4, plant_mult=1000)
     log(f"planted m={g.m}")
