@@ -754,13 +754,17 @@ template <bool GEN> void enqueue_pair(int filter, const EnumArgs &A, unsigned ig
 int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool gated, size_t slot) {
     Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len, nullptr, (uint32_t)WBINS}
                              : pick_stream(g, q->ord, B.mode, B.p, B.L);
-    if (!q->sub_active && S.wbin < (uint32_t)WBINS && g->ws_low.load(std::memory_order_acquire) > S.wbin) {
-        // the weight-ordered stream is chosen but its bins down to S.wbin are not placed yet
-        // (lazily built graph state, guarded by the graph's init lock)
-        int rc = ensure_weight_stream(const_cast<tt_graph *>(g), q->stream, S.wbin);
-        if (rc) return rc;
+    if (!q->sub_active && S.wbin < (uint32_t)WBINS) {
+        // the weight-ordered stream: its bins down to S.wbin are placed on first need (lazily
+        // built graph state, guarded by the graph's init lock); the stream's arrays are read
+        // again after the acquire of ws_low that shows them placed
+        if (g->ws_low.load(std::memory_order_acquire) > S.wbin) {
+            int rc = ensure_weight_stream(const_cast<tt_graph *>(g), q->stream, S.wbin);
+            if (rc) return rc;
+        }
         S = pick_stream(g, q->ord, B.mode, B.p, B.L);
     }
+    if (S.E && !S.src) return fail(TT_E_DEVICE, "internal: a stream with entries has no arrays");
     EnumArgs A;
     std::memset(&A, 0, sizeof(A));
     A.rstart = g->rstart;

@@ -70,6 +70,25 @@ def test_served_equals_single(tt, graph):
     assert info["max_running"] >= 2  # requests overlapped on the device
 
 
+def test_served_with_stream_placed_in_parts(tt, graph, monkeypatch):
+    """A fresh graph whose weight-ordered stream is placed bin range by bin range (as on graphs
+    of more than 2^27 entries), first needed by requests running concurrently: each served
+    result equals the single-query result of the graph that placed the stream at once."""
+    g, G = graph
+    reqs = [r for r in requests(g.n, 64, 19) if r[2] is None][:32]
+    singles = [G.topk(k, p) for k, p, _ in reqs]
+    monkeypatch.setenv("TT_WS_ALL_AT_ONCE", "0")
+    with tt.Graph(g.n, g.src, g.dst, g.w) as H:
+        with tt.Server(H, slots=4, scratch_budget=8 << 30) as S:
+            tickets = [S.submit(k, p, None) for k, p, _ in reqs]
+            served = [S.wait(t) for t in tickets]
+            info = S.info()
+    log(f"server info {info}")
+    for (k, p, _), a, b in zip(reqs, singles, served):
+        assert same(a, b), (k, p)
+    assert info["max_running"] >= 2
+
+
 def test_served_against_oracle(tt, graph):
     g, G = graph
     ei = EdgeIndex(g.src, g.dst, g.w)
