@@ -1048,6 +1048,8 @@ int check_subset(const tt_graph *g, const uint32_t *subset, uint32_t subset_n) {
 // the compact stream of the entries that can be the base of a triangle touching the subset.
 // If the stream or the list would not fit (huge subsets), the passes stream every entry with
 // the vertex pre-tests instead.
+constexpr uint64_t SUB_SCAN_MUL = 8;
+
 int prepare_subset(tt_graph *g, QueryCtx *q, const uint32_t *subset, uint32_t cnt) {
     int rc;
     q->sub_active = false;
@@ -1087,8 +1089,12 @@ int prepare_subset(tt_graph *g, QueryCtx *q, const uint32_t *subset, uint32_t cn
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(q->hcount + 8, cnt8, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        // The rows to scan bound the compact stream; most of their entries are usually dropped
+        // (a subset vertex of high in-degree lists many in-neighbours whose rows lead elsewhere),
+        // so rows up to SUB_SCAN_MUL times the capacity are scanned, and the stream is used if
+        // the entries kept fit.  Otherwise: the full stream with vertex pre-tests.
         const uint64_t nv = q->hcount[8], bound = q->hcount[9];
-        if (nv > vcap || bound > scap) return TT_OK; // the full stream with vertex pre-tests
+        if (nv > vcap || bound > SUB_SCAN_MUL * scap) return TT_OK;
         k_sub_rows<<<num_cus() * 8, 256, 0, s>>>(ids, own, cnt, q->sub_vlist, (uint32_t)nv, g->rstart, g->rlen,
                                                  g->col, g->wgt, q->vflag, q->vflag2, q->sub_src, q->sub_col,
                                                  q->sub_wgt, q->sub_pos, scap, cnt8, hist);
@@ -1098,7 +1104,7 @@ int prepare_subset(tt_graph *g, QueryCtx *q, const uint32_t *subset, uint32_t cn
         HIP_TRY(hipMemcpyAsync(q->hcount + 10, cnt8 + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         q->sub_len = q->hcount[10];
-        q->sub_active = true;
+        q->sub_active = q->sub_len <= scap; // else some kept entries did not fit: full stream
         return TT_OK;
     };
     rc = body();

@@ -62,6 +62,24 @@ def test_medium_sampling(medium, p):
     assert_parity(got, want, p, ei, ctx=f"medium es p={p}")
 
 
+def test_medium_subset_with_hubs(medium):
+    """A subset holding the 50 highest-degree vertices: their in-neighbours' rows hold far more
+    entries than the compact stream, most of which are dropped, so the stream is built from a
+    scan of those rows (and used if what is kept fits).  Against the oracle."""
+    g, G, ei = medium
+    deg = np.bincount(g.src, minlength=g.n) + np.bincount(g.dst, minlength=g.n)
+    hubs = np.argsort(deg)[-50:]
+    rng = np.random.default_rng(77)
+    sub = np.unique(np.concatenate([hubs, rng.choice(g.n, size=950, replace=False)])).astype(np.uint32)
+    for p in (1.0, -math.inf):
+        got = G.topk(500, p, subset=sub, with_stats=True)
+        log(f"  hubs p={p} stats {got['stats']}")
+        vm = np.zeros(g.n, np.uint8)
+        vm[sub.astype(np.int64)] = 1
+        want = oracle.topk(g.n, g.src, g.dst, g.w, 500, p, vertex_mark=vm)
+        assert_parity(got, want, p, ei, ctx=f"medium subset with hubs p={p}")
+
+
 @pytest.mark.parametrize("size,p", [(1000, 1.0), (1000, 0.0), (300_000, 2.0)])
 def test_medium_subset(medium, size, p):
     """A 1,000-vertex subset takes the compact stream of its possible base entries; a
