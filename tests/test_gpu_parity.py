@@ -118,6 +118,23 @@ def test_overflow_restart_with_ties(tt):
             assert got["stats"]["restarts"] >= 1, got["stats"]
 
 
+def test_descent_through_weight_ties(tt):
+    """Weights that tie in large groups (1 and 2 for most edges, a few heavy ones): the rank a
+    band asks for falls inside a tie group far larger than itself, so the descent takes the bin
+    above the group first, and the count it finds picks the next step.  k on both sides of the
+    group boundaries, every kind of p, against the oracle."""
+    g = graphgen.chung_lu(20000, 200000, 2.2, 1.8, seed=21)
+    rng = np.random.default_rng(21)
+    w = np.where(rng.random(g.m) < 0.7, 1, 2).astype(np.uint32)
+    heavy = rng.choice(g.m, size=300, replace=False)
+    w[heavy] = rng.integers(3, 50, size=300).astype(np.uint32)
+    log(f"weight ties m={g.m}")
+    with tt.Graph(g.n, g.src, g.dst, w) as G:
+        for k in (10, 300, 5000):
+            for p in (1.0, -math.inf, math.inf, 0.0, -1.0):
+                check(tt, g.n, g.src, g.dst, w, k, p, G=G, ctx="weight ties")
+
+
 def test_long_rows_every_filter(tt):
     """A dense graph (n = 320, edge probability 0.9, weights 1..3): oriented rows of up to ~290
     entries, so at low weight floors a candidate's iterated row holds more admissible entries
