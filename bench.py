@@ -271,8 +271,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this library runs on one GPU; a multi-GPU run is not part of this build "
-              "(DESIGN.md describes how the path would shard).", file=sys.stderr)
+        print("bench.py: this library runs on one GPU; there is no multi-GPU path to measure "
+              "(the replicated-graph sharding it would use is described with the design notes).",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "serve":
