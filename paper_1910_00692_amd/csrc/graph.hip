@@ -567,7 +567,10 @@ __global__ __launch_bounds__(256) void k_row_max(const uint4 *rec, uint64_t m, u
     }
 }
 
-__global__ __launch_bounds__(256) void k_row_bound(const uint4 *rec, uint64_t m, const uint32_t *maxw, uint32_t *hb) {
+// hb[u] = the largest row maximum among u's heads; hm0[j] (when kept) = the row maximum of
+// record j's head, which the row ranking then places with the entry.
+__global__ __launch_bounds__(256) void k_row_bound(const uint4 *rec, uint64_t m, const uint32_t *maxw, uint32_t *hb,
+                                                   uint32_t *hm0) {
     const int lane = threadIdx.x & 63;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += stride) {
@@ -575,7 +578,9 @@ __global__ __launch_bounds__(256) void k_row_bound(const uint4 *rec, uint64_t m,
         const bool valid = e < m;
         const uint4 x = valid ? rec[e] : make_uint4(0u, 0u, 0u, 0u);
         const WaveRuns r = wave_runs(x.w, valid);
-        const uint32_t v = seg_max(valid ? maxw[x.x] : 0u, r);
+        const uint32_t mh = valid ? maxw[x.x] : 0u;
+        if (hm0 && valid) hm0[e] = mh;
+        const uint32_t v = seg_max(mh, r);
         if (valid && r.first == lane) atomicMax(&hb[x.w], v);
     }
 }
@@ -631,9 +636,11 @@ constexpr int RANK_ITEMS = 2;        // window of RANK_ITEMS * 64 entries per wa
 // Writes one entry of a row (tail t, head c, weight w, input edge d) to both copies of the
 // final layout: head order at rank r1, weight order at rank r2; records its tail and input edge.
 __device__ __forceinline__ void put_entry(uint64_t P, uint32_t r1, uint32_t r2, uint32_t t, uint32_t c, uint32_t w,
-                                          uint32_t d, uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
-                                          uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos) {
+                                          uint32_t d, uint32_t hm, uint32_t *col, uint32_t *wgt, uint32_t *eid,
+                                          uint32_t *osrc, uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
+                                          uint32_t *hmx) {
     col[P + r1] = c;
+    if (hmx) hmx[P + r1] = hm;
     wgt[P + r1] = w;
     eid[P + r1] = d;
     osrc[P + r1] = t;
@@ -695,7 +702,8 @@ template <int R> __device__ __forceinline__ void block_bitonic(uint64_t (&k)[R],
 __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uint64_t *rowp0, uint64_t m,
                                                     const uint64_t *rstart, const uint32_t *rlen, uint32_t *col,
                                                     uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
-                                                    uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos, uint32_t *flags) {
+                                                    uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos, uint32_t *flags,
+                                                    const uint32_t *hm0, uint32_t *hmx) {
     __shared__ uint32_t sc[4][RANK_ITEMS * 64], sw[4][RANK_ITEMS * 64];
     const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
     const uint64_t nw = (m + 63) / 64;
@@ -704,16 +712,17 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
     for (uint64_t blk = (uint64_t)blockIdx.x * 4; blk < nw; blk += (uint64_t)gridDim.x * 4) {
         const uint64_t w0 = blk + wib;
         const uint64_t base = w0 * 64;
-        uint32_t c[RANK_ITEMS], wt[RANK_ITEMS], d[RANK_ITEMS], t[RANK_ITEMS], rb[RANK_ITEMS], len[RANK_ITEMS];
+        uint32_t c[RANK_ITEMS], wt[RANK_ITEMS], d[RANK_ITEMS], t[RANK_ITEMS], rb[RANK_ITEMS], len[RANK_ITEMS], hv[RANK_ITEMS];
         bool mine[RANK_ITEMS];
 #pragma unroll
         for (int k = 0; k < RANK_ITEMS; k++) {
             const uint64_t e = base + (uint64_t)k * 64 + lane;
             uint4 r = make_uint4(0u, 0u, 0u, 0u);
             mine[k] = false;
-            rb[k] = len[k] = 0;
+            rb[k] = len[k] = hv[k] = 0;
             if (w0 < nw && e < m) {
                 r = rec0[e];
+                if (hm0) hv[k] = hm0[e];
                 const uint64_t b = rowp0[r.w];
                 len[k] = rlen[r.w];
                 mine[k] = b >= base && b < base + 64 && len[k] <= SMALL_MAX;
@@ -736,7 +745,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
                 r2 += wf > wt[k] || (wf == wt[k] && before_id);
                 dup |= cf == c[k] && f != me;
             }
-            put_entry(rstart[t[k]], r1, r2, t[k], c[k], wt[k], d[k], col, wgt, eid, osrc, wcol, wwgt, wpos);
+            put_entry(rstart[t[k]], r1, r2, t[k], c[k], wt[k], d[k], hv[k], col, wgt, eid, osrc, wcol, wwgt, wpos, hmx);
         }
         __syncthreads();
     }
@@ -796,7 +805,7 @@ __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P,
                                              uint32_t *sc, uint32_t *sw, uint32_t *sd, uint32_t *hc, uint32_t *hw,
                                              uint64_t *xch, uint32_t *col, uint32_t *wgt, uint32_t *eid,
                                              uint32_t *osrc, uint32_t *wcol, uint32_t *wwgt,
-                                             uint32_t *wpos, bool &dup) {
+                                             uint32_t *wpos, const uint32_t *hm0, uint32_t *hmx, bool &dup) {
     const uint32_t t = threadIdx.x;
     uint64_t k[R];
 #pragma unroll
@@ -822,6 +831,7 @@ __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P,
             wgt[P + s] = w;
             eid[P + s] = d;
             osrc[P + s] = u;
+            if (hmx) hmx[P + s] = hm0[b + i];
             hc[s] = c;
             hw[s] = w;
         }
@@ -851,7 +861,7 @@ __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t 
                                                   const uint64_t *rowp0, const uint64_t *rstart, const uint32_t *rlen,
                                                   uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
                                                   uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
-                                                  uint32_t *flags) {
+                                                  uint32_t *flags, const uint32_t *hm0, uint32_t *hmx) {
     static_assert(MID_MAX == 1024, "rows are sorted as up to 4 keys per thread");
     __shared__ uint32_t sc[MID_MAX], sw[MID_MAX], sd[MID_MAX], hc[MID_MAX], hw[MID_MAX];
     __shared__ uint64_t xch[MID_MAX];
@@ -860,11 +870,11 @@ __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t 
         const uint32_t u = mid[bi], len = rlen[u];
         const uint64_t b = rowp0[u], P = rstart[u];
         if (len <= 256)
-            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, dup);
+            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
         else if (len <= 512)
-            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, dup);
+            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
         else
-            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, dup);
+            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
     }
     if (__ballot(dup) && (threadIdx.x & 63) == 0) atomicOr(flags, F_DUP);
 }
@@ -890,7 +900,8 @@ __global__ __launch_bounds__(256) void k_move_big(const uint32_t *big, uint32_t 
 // weight-sorted copy.
 __global__ __launch_bounds__(256) void k_post_big(const uint32_t *big, uint32_t nbig, const uint64_t *rstart,
                                                   const uint32_t *rlen, const uint32_t *col, const uint32_t *wgt,
-                                                  uint64_t *wkey, uint32_t *wpos, uint32_t *flags) {
+                                                  uint64_t *wkey, uint32_t *wpos, uint32_t *flags,
+                                                  const uint32_t *maxw, uint32_t *hmx) {
     bool dup = false;
     for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
         const uint32_t u = big[bi];
@@ -900,6 +911,7 @@ __global__ __launch_bounds__(256) void k_post_big(const uint32_t *big, uint32_t 
             if (t > 0 && col[b + t - 1] == c) dup = true;
             wkey[b + t] = ((uint64_t)(~wgt[b + t]) << 32) | c; // ascending = weight desc, then ID
             wpos[b + t] = (uint32_t)(b + t);
+            if (hmx) hmx[b + t] = maxw[c];
         }
     }
     if (__ballot(dup) && (threadIdx.x & 63) == 0) atomicOr(flags, F_DUP);
@@ -1084,13 +1096,9 @@ __global__ __launch_bounds__(256) void k_pack_vinfo(const uint64_t *rstart, cons
         vi[v] = VInfo{rstart[v], rlen[v], maxw[v]};
 }
 
-__global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint32_t *wgt, const uint32_t *maxw,
-                                                 uint64_t m, uint2 *cw, uint32_t *hmx) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t v = col[e];
-        cw[e] = make_uint2(v, wgt[e]);
-        if (hmx) hmx[e] = maxw[v];
-    }
+__global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint32_t *wgt, uint64_t m, uint2 *cw) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        cw[e] = make_uint2(col[e], wgt[e]);
 }
 
 } // namespace
@@ -1236,7 +1244,14 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     }
     if (m) k_row_max<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw);
     HIP_TRY(hipMemcpyAsync(g->hb, g->maxw, nn * 4, hipMemcpyDeviceToDevice, s));
-    if (m) k_row_bound<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw, g->hb);
+    // The per-entry head maxima pay only where the row maxima no longer stay in the caches
+    // (then the filter's gather of maxw[v] misses to HBM for nearly every streamed entry).  They
+    // are gathered once, in record order, and placed by the row ranking with their entries.
+    uint32_t *hm0 = nullptr;
+    if (n >= HMX_MIN_N &&
+        ((rc = dev_alloc(g, (void **)&g->hmx, (m + 1) * 4)) || (rc = S.get((void **)&hm0, (m + 1) * 4))))
+        return rc;
+    if (m) k_row_bound<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw, g->hb, hm0);
     // layout by descending weight_bin(hb)
     unsigned long long *ecnt = nullptr, *bincur = nullptr, *binbase = nullptr;
     if ((rc = S.get((void **)&ecnt, WBINS * 8)) || (rc = S.get((void **)&bincur, WBINS * 8)) ||
@@ -1260,7 +1275,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     }
     // both row orders: counted ranks for rows up to MID_MAX entries, sorts for longer ones
     if (m) k_rank_small<<<grid_for(m), 256, 0, s>>>(rec0, rowp0, m, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                                    g->wcol, g->wwgt, g->wpos, flags);
+                                                    g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
     HIP_TRY(hipMemsetAsync(flags + 1, 0, 8, s));
     if (n) k_list_long<<<grid_for(n, 4096), 256, 0, s>>>(g->rlen, n, mid, flags + 2, big, flags + 1);
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
@@ -1269,7 +1284,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     if (nmid) {
         const unsigned gm = nmid < 8192u ? nmid : 8192u;
         k_rank_mid<<<gm, 256, 0, s>>>(mid, nmid, rec0, rowp0, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                      g->wcol, g->wwgt, g->wpos, flags);
+                                      g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
     }
     if (nbig) {
         const unsigned gb = nbig < 4096u ? nbig : 4096u;
@@ -1277,7 +1292,8 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         if ((rc = sort_big<uint32_t>(g, S, g->rstart, g->rlen, big, nbig, g->col, g->wgt, g->eid))) return rc;
         uint64_t *wkey = nullptr;
         if ((rc = S.get((void **)&wkey, (m + 1) * 8))) return rc;
-        k_post_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, g->col, g->wgt, wkey, g->wpos, flags);
+        k_post_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, g->col, g->wgt, wkey, g->wpos, flags, g->maxw,
+                                      g->hmx);
         if ((rc = sort_big<uint64_t>(g, S, g->rstart, g->rlen, big, nbig, wkey, g->wpos, nullptr))) return rc;
         k_split_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, wkey, g->wcol, g->wwgt);
         S.drop(wkey);
@@ -1311,13 +1327,10 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         for (int b = WBINS - 1; b >= 0; b--) { g->wbase[b] = run; run += g->whist[b]; }
     }
     // (the stream itself is placed by the first query that streams it: ensure_weight_stream)
-    // The per-entry head maxima pay only where the row maxima no longer stay in the caches
-    // (then the filter's gather of maxw[v] misses to HBM for nearly every streamed entry).
-    if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo))) || (rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8)) ||
-        (n >= HMX_MIN_N && (rc = dev_alloc(g, (void **)&g->hmx, (m + 1) * 4))))
+    if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo))) || (rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8)))
         return rc;
     k_pack_vinfo<<<grid_for(nn), 256, 0, s>>>(g->rstart, g->rlen, g->maxw, nn, g->vinfo);
-    if (m) k_pack_cw<<<grid_for(m), 256, 0, s>>>(g->col, g->wgt, g->maxw, m, g->cw, g->hmx);
+    if (m) k_pack_cw<<<grid_for(m), 256, 0, s>>>(g->col, g->wgt, m, g->cw);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
     return TT_OK;
