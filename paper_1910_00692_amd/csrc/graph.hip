@@ -975,12 +975,24 @@ __global__ __launch_bounds__(256) void k_place_entries(const uint32_t *osrc, con
     }
 }
 
+// Four weights per thread in flight (a few blocks per CU run this, so that each bin's global
+// counter takes few atomics; their loads would otherwise wait one at a time).
 __global__ __launch_bounds__(256) void k_weight_hist(const uint32_t *wgt, uint64_t m, unsigned long long *hist) {
     __shared__ uint32_t h[WBINS];
     for (int t = threadIdx.x; t < WBINS; t += blockDim.x) h[t] = 0;
     __syncthreads();
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
-        atomicAdd(&h[weight_bin(wgt[e])], 1u);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < m; e0 += 4 * stride) {
+        uint32_t w[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint64_t e = e0 + (uint64_t)i * stride;
+            w[i] = e < m ? wgt[e] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            if (e0 + (uint64_t)i * stride < m) atomicAdd(&h[weight_bin(w[i])], 1u);
+    }
     __syncthreads();
     for (int t = threadIdx.x; t < WBINS; t += blockDim.x)
         if (h[t]) atomicAdd(&hist[t], (unsigned long long)h[t]);
@@ -1259,7 +1271,8 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         return rc;
     HIP_TRY(hipMemsetAsync(ecnt, 0, WBINS * 8, s));
     HIP_TRY(hipMemsetAsync(bincur, 0, WBINS * 8, s));
-    if (n) k_bin_entries<<<grid_for(n), 256, 0, s>>>(g->hb, g->rlen, n, ecnt);
+    // (histograms: a few blocks per CU, so that each bin's global counter takes few atomics)
+    if (n) k_bin_entries<<<std::min<unsigned>(grid_for(n), (unsigned)num_cus() * 4), 256, 0, s>>>(g->hb, g->rlen, n, ecnt);
     g->ebin.assign(WBINS, 0);
     g->ebase.assign(WBINS, 0);
     HIP_TRY(hipMemcpyAsync(g->ebin.data(), ecnt, WBINS * 8, hipMemcpyDeviceToHost, s));
@@ -1303,7 +1316,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     unsigned long long *hist = nullptr;
     if ((rc = S.get((void **)&hist, WBINS * 8))) return rc;
     HIP_TRY(hipMemsetAsync(hist, 0, WBINS * 8, s));
-    if (m) k_weight_hist<<<grid_for(m), 256, 0, s>>>(g->wgt, m, hist);
+    if (m) k_weight_hist<<<std::min<unsigned>(grid_for(m), (unsigned)num_cus() * 4), 256, 0, s>>>(g->wgt, m, hist);
     g->whist.assign(WBINS, 0);
     HIP_TRY(hipMemcpyAsync(g->whist.data(), hist, WBINS * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
