@@ -269,6 +269,9 @@ struct PartGeom {
 };
 
 constexpr int PART_THREADS = 256;
+// Items per thread and loop trip in the partition passes: their loads are issued together
+// (one at a time, each trip waited on its load before the LDS atomic could start).
+constexpr int PART_UNROLL = 4;
 
 __global__ __launch_bounds__(PART_THREADS) void k_part_count_ends(const uint32_t *src, const uint32_t *dst, uint64_t m,
                                                          PartGeom G, uint32_t *M) {
@@ -276,9 +279,19 @@ __global__ __launch_bounds__(PART_THREADS) void k_part_count_ends(const uint32_t
     for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) h[b] = 0;
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
-    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        atomicAdd(&h[src[e] >> G.rb], 1u);
-        atomicAdd(&h[dst[e] >> G.rb], 1u);
+    for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += PART_UNROLL * blockDim.x) {
+        uint32_t a[PART_UNROLL], d[PART_UNROLL];
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t e = e0 + (uint64_t)i * blockDim.x;
+            if (e < hi) { a[i] = src[e]; d[i] = dst[e]; }
+        }
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++)
+            if (e0 + (uint64_t)i * blockDim.x < hi) {
+                atomicAdd(&h[a[i] >> G.rb], 1u);
+                atomicAdd(&h[d[i] >> G.rb], 1u);
+            }
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) M[(uint64_t)b * G.nblk + blockIdx.x] = h[b];
@@ -293,10 +306,19 @@ __global__ __launch_bounds__(PART_THREADS) void k_part_ends(const uint32_t *src,
     for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) cur[b] = (C)off[(uint64_t)b * G.nblk + blockIdx.x];
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
-    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        const uint32_t a = src[e], d = dst[e];
-        ep[atomicAdd(&cur[a >> G.rb], (C)1)] = a;
-        ep[atomicAdd(&cur[d >> G.rb], (C)1)] = d;
+    for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += PART_UNROLL * blockDim.x) {
+        uint32_t a[PART_UNROLL], d[PART_UNROLL];
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t e = e0 + (uint64_t)i * blockDim.x;
+            if (e < hi) { a[i] = src[e]; d[i] = dst[e]; }
+        }
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++)
+            if (e0 + (uint64_t)i * blockDim.x < hi) {
+                ep[atomicAdd(&cur[a[i] >> G.rb], (C)1)] = a[i];
+                ep[atomicAdd(&cur[d[i] >> G.rb], (C)1)] = d[i];
+            }
     }
 }
 
@@ -309,7 +331,17 @@ __global__ __launch_bounds__(256) void k_bucket_degree(const uint32_t *ep, const
     for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) c[i] = 0;
     __syncthreads();
     const uint64_t lo = off[(uint64_t)b * G.nblk], hi = b + 1 < G.nbk ? off[(uint64_t)(b + 1) * G.nblk] : total;
-    for (uint64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) atomicAdd(&c[(uint32_t)(ep[j] - base)], 1u);
+    for (uint64_t j0 = lo + threadIdx.x; j0 < hi; j0 += PART_UNROLL * blockDim.x) {
+        uint32_t x[PART_UNROLL];
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t j = j0 + (uint64_t)i * blockDim.x;
+            if (j < hi) x[i] = ep[j];
+        }
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++)
+            if (j0 + (uint64_t)i * blockDim.x < hi) atomicAdd(&c[(uint32_t)(x[i] - base)], 1u);
+    }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < R; i += blockDim.x)
         if (base + i < n) deg[base + i] = c[i];
@@ -323,11 +355,23 @@ __global__ __launch_bounds__(PART_THREADS) void k_part_count_tails(const uint32_
     for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) h[b] = 0;
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
-    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        uint32_t t, hd;
-        orient(src[e], dst[e], deg, t, hd);
-        etail[e] = t;
-        atomicAdd(&h[t >> G.rb], 1u);
+    for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += PART_UNROLL * blockDim.x) {
+        uint32_t a[PART_UNROLL], d[PART_UNROLL];
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t e = e0 + (uint64_t)i * blockDim.x;
+            if (e < hi) { a[i] = src[e]; d[i] = dst[e]; }
+        }
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t e = e0 + (uint64_t)i * blockDim.x;
+            if (e < hi) {
+                uint32_t t, hd;
+                orient(a[i], d[i], deg, t, hd);
+                etail[e] = t;
+                atomicAdd(&h[t >> G.rb], 1u);
+            }
+        }
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) M[(uint64_t)b * G.nblk + blockIdx.x] = h[b];
@@ -342,9 +386,19 @@ __global__ __launch_bounds__(PART_THREADS) void k_part_edges(const uint32_t *src
     for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) cur[b] = (C)off[(uint64_t)b * G.nblk + blockIdx.x];
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * G.per, hi = lo + G.per < m ? lo + G.per : m;
-    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        const uint32_t t = etail[e];
-        part[atomicAdd(&cur[t >> G.rb], (C)1)] = make_uint4(src[e] ^ dst[e] ^ t, w[e], (uint32_t)e, t);
+    for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += PART_UNROLL * blockDim.x) {
+        uint4 r[PART_UNROLL];
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t e = e0 + (uint64_t)i * blockDim.x;
+            if (e < hi) {
+                const uint32_t t = etail[e];
+                r[i] = make_uint4(src[e] ^ dst[e] ^ t, w[e], (uint32_t)e, t);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++)
+            if (e0 + (uint64_t)i * blockDim.x < hi) part[atomicAdd(&cur[r[i].w >> G.rb], (C)1)] = r[i];
     }
 }
 
@@ -381,9 +435,19 @@ __global__ __launch_bounds__(PART_THREADS) void k_seg_count(const uint32_t *in, 
     const uint32_t W = fb1 - fb0;
     for (uint32_t b = threadIdx.x; b < W; b += blockDim.x) h[b] = 0;
     __syncthreads();
-    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        const uint32_t b = (in[e] >> G.rb) - fb0;
-        if (b < W) atomicAdd(&h[b], 1u);
+    for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += PART_UNROLL * blockDim.x) {
+        uint32_t x[PART_UNROLL];
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t e = e0 + (uint64_t)i * blockDim.x;
+            if (e < hi) x[i] = in[e];
+        }
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++)
+            if (e0 + (uint64_t)i * blockDim.x < hi) {
+                const uint32_t b = (x[i] >> G.rb) - fb0;
+                if (b < W) atomicAdd(&h[b], 1u);
+            }
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < W; b += blockDim.x) M[(uint64_t)(fb0 + b) * G.nblk + blockIdx.x] = h[b];
@@ -400,10 +464,19 @@ __global__ __launch_bounds__(PART_THREADS) void k_seg_scatter(const uint32_t *in
     const uint32_t W = fb1 - fb0;
     for (uint32_t b = threadIdx.x; b < W; b += blockDim.x) cur[b] = (C)off[(uint64_t)(fb0 + b) * G.nblk + blockIdx.x];
     __syncthreads();
-    for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-        const uint32_t x = in[e];
-        const uint32_t b = (x >> G.rb) - fb0;
-        if (b < W) out[atomicAdd(&cur[b], (C)1)] = x;
+    for (uint64_t e0 = lo + threadIdx.x; e0 < hi; e0 += PART_UNROLL * blockDim.x) {
+        uint32_t x[PART_UNROLL];
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t e = e0 + (uint64_t)i * blockDim.x;
+            if (e < hi) x[i] = in[e];
+        }
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++)
+            if (e0 + (uint64_t)i * blockDim.x < hi) {
+                const uint32_t b = (x[i] >> G.rb) - fb0;
+                if (b < W) out[atomicAdd(&cur[b], (C)1)] = x[i];
+            }
     }
 }
 
@@ -418,7 +491,17 @@ __global__ __launch_bounds__(256) void k_bucket_rows(const uint4 *part, const ui
     for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) c[i] = 0;
     __syncthreads();
     const uint64_t lo = off[(uint64_t)b * G.nblk], hi = b + 1 < G.nbk ? off[(uint64_t)(b + 1) * G.nblk] : m;
-    for (uint64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) atomicAdd(&c[(uint32_t)(part[j].w - base)], 1u);
+    for (uint64_t j0 = lo + threadIdx.x; j0 < hi; j0 += PART_UNROLL * blockDim.x) {
+        uint32_t x[PART_UNROLL];
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t j = j0 + (uint64_t)i * blockDim.x;
+            if (j < hi) x[i] = part[j].w;
+        }
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++)
+            if (j0 + (uint64_t)i * blockDim.x < hi) atomicAdd(&c[(uint32_t)(x[i] - base)], 1u);
+    }
     __syncthreads();
     // thread t owns counters [t*per, t*per + per)
     const uint32_t per = (R + 255) / 256;
@@ -446,9 +529,16 @@ __global__ __launch_bounds__(256) void k_bucket_rows(const uint4 *part, const ui
     }
     if (b == G.nbk - 1 && threadIdx.x == 0) rowp[n] = m;
     __syncthreads();
-    for (uint64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
-        const uint4 r = part[j];
-        rec[lo + atomicAdd(&c[(uint32_t)(r.w - base)], 1u)] = r;
+    for (uint64_t j0 = lo + threadIdx.x; j0 < hi; j0 += PART_UNROLL * blockDim.x) {
+        uint4 r[PART_UNROLL];
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++) {
+            const uint64_t j = j0 + (uint64_t)i * blockDim.x;
+            if (j < hi) r[i] = part[j];
+        }
+#pragma unroll
+        for (int i = 0; i < PART_UNROLL; i++)
+            if (j0 + (uint64_t)i * blockDim.x < hi) rec[lo + atomicAdd(&c[(uint32_t)(r[i].w - base)], 1u)] = r[i];
     }
 }
 
