@@ -803,6 +803,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
         const uint64_t w0 = blk + wib;
         const uint64_t base = w0 * 64;
         uint32_t c[RANK_ITEMS], wt[RANK_ITEMS], d[RANK_ITEMS], t[RANK_ITEMS], rb[RANK_ITEMS], len[RANK_ITEMS], hv[RANK_ITEMS];
+        uint64_t P[RANK_ITEMS]; // final row start, loaded before the ranking so that it is not waited on after
         bool mine[RANK_ITEMS];
 #pragma unroll
         for (int k = 0; k < RANK_ITEMS; k++) {
@@ -810,6 +811,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
             uint4 r = make_uint4(0u, 0u, 0u, 0u);
             mine[k] = false;
             rb[k] = len[k] = hv[k] = 0;
+            P[k] = 0;
             if (w0 < nw && e < m) {
                 r = rec0[e];
                 if (hm0) hv[k] = hm0[e];
@@ -817,6 +819,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
                 len[k] = rlen[r.w];
                 mine[k] = b >= base && b < base + 64 && len[k] <= SMALL_MAX;
                 rb[k] = (uint32_t)(b - base); // window-relative row start (valid when mine)
+                if (mine[k]) P[k] = rstart[r.w];
             }
             c[k] = r.x; wt[k] = r.y; d[k] = r.z; t[k] = r.w;
             sc[wib][k * 64 + lane] = r.x;
@@ -835,7 +838,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
                 r2 += wf > wt[k] || (wf == wt[k] && before_id);
                 dup |= cf == c[k] && f != me;
             }
-            put_entry(rstart[t[k]], r1, r2, t[k], c[k], wt[k], d[k], hv[k], col, wgt, eid, osrc, wcol, wwgt, wpos, hmx);
+            put_entry(P[k], r1, r2, t[k], c[k], wt[k], d[k], hv[k], col, wgt, eid, osrc, wcol, wwgt, wpos, hmx);
         }
         __syncthreads();
     }
