@@ -62,8 +62,15 @@ def _load():
         lib.orc_topk.restype = i32
         lib.orc_list.argtypes = [u64, u64, p32, p32, p32, u64, p32, p32, p32, p32, p64]
         lib.orc_list.restype = i32
+        lib.orc_topk_marked.argtypes = [u64, u64, p32, p32, p32, u64, dbl, i32, p8, p8, p32, p32, p32, pd, p64,
+                                        p64, p64, p64]
+        lib.orc_topk_marked.restype = i32
         lib.orc_es_draw.argtypes = [u64, p32, dbl, u64, u64, p8, p64]
         lib.orc_es_draw.restype = i32
+        lib.orc_es_draw_q.argtypes = [u64, p32, dbl, u64, u64, p8, p64]
+        lib.orc_es_draw_q.restype = i32
+        lib.orc_es_prefix_f64.argtypes = [u64, p32, dbl, pd]
+        lib.orc_es_prefix_f64.restype = i32
         lib.orc_sample_exponent.argtypes = [dbl]
         lib.orc_sample_exponent.restype = dbl
         lib.orc_splitmix64_at.argtypes = [u64, u64]
@@ -108,26 +115,30 @@ class OracleError(RuntimeError):
 
 
 def topk(n, src, dst, w, k: int, p: float, nthreads: int = 0, edge_mark=None, vertex_mark=None):
-    """Top-k triangles.  Returns dict(i, j, l, score, key, n_out, total)."""
+    """Top-k triangles.  Returns dict(i, j, l, score, key, n_out, total).  With edge_mark (per
+    input edge) only triangles with a marked edge are admitted, with vertex_mark (per vertex)
+    only triangles with a marked vertex; with both, triangles that satisfy both."""
     s, d, ww = _edges(src, dst, w)
     m = s.shape[0]
-    filt, mark = FILTER_NONE, None
+    em = vm = None
     if edge_mark is not None:
-        filt, mark = FILTER_EDGE_MARK, _arr(edge_mark, np.uint8)
-        assert mark.shape[0] == m
-    elif vertex_mark is not None:
-        filt, mark = FILTER_VERTEX_MARK, _arr(vertex_mark, np.uint8)
-        assert mark.shape[0] == n
+        em = _arr(edge_mark, np.uint8)
+        assert em.shape[0] == m
+    if vertex_mark is not None:
+        vm = _arr(vertex_mark, np.uint8)
+        assert vm.shape[0] == n
     kk = max(int(k), 0)
     oi, oj, ol = (np.zeros(max(kk, 1), np.uint32) for _ in range(3))
     osc = np.zeros(max(kk, 1), np.float64)
     khi, klo = np.zeros(max(kk, 1), np.uint64), np.zeros(max(kk, 1), np.uint64)
     nout, tot = ctypes.c_uint64(0), ctypes.c_uint64(0)
-    rc = _load().orc_topk(n, m, _ptr(s, ctypes.c_uint32), _ptr(d, ctypes.c_uint32), _ptr(ww, ctypes.c_uint32), kk,
-                          float(p), int(nthreads), filt, None if mark is None else _ptr(mark, ctypes.c_uint8),
-                          _ptr(oi, ctypes.c_uint32), _ptr(oj, ctypes.c_uint32), _ptr(ol, ctypes.c_uint32),
-                          _ptr(osc, ctypes.c_double), _ptr(khi, ctypes.c_uint64), _ptr(klo, ctypes.c_uint64),
-                          ctypes.byref(nout), ctypes.byref(tot))
+    rc = _load().orc_topk_marked(n, m, _ptr(s, ctypes.c_uint32), _ptr(d, ctypes.c_uint32),
+                                 _ptr(ww, ctypes.c_uint32), kk, float(p), int(nthreads),
+                                 None if em is None else _ptr(em, ctypes.c_uint8),
+                                 None if vm is None else _ptr(vm, ctypes.c_uint8),
+                                 _ptr(oi, ctypes.c_uint32), _ptr(oj, ctypes.c_uint32), _ptr(ol, ctypes.c_uint32),
+                                 _ptr(osc, ctypes.c_double), _ptr(khi, ctypes.c_uint64),
+                                 _ptr(klo, ctypes.c_uint64), ctypes.byref(nout), ctypes.byref(tot))
     if rc != OK:
         raise OracleError(rc)
     r = int(nout.value)
@@ -170,23 +181,40 @@ def splitmix64(seed: int, i: int) -> int:
     return int(_load().orc_splitmix64_at(seed & (2**64 - 1), i))
 
 
-def es_draw(w, p: float, budget: int, seed: int, return_draws: bool = False):
-    """Alg. 3's edge draws.  Returns the per-edge mark array (and the draw sequence)."""
+def es_draw(w, p: float, budget: int, seed: int, return_draws: bool = False, q: float | None = None):
+    """Alg. 3's edge draws with the sampling exponent of p, or with q when it is given.
+    Returns the per-edge mark array (and the draw sequence)."""
     ww = _arr(w, np.uint32)
     m = ww.shape[0]
     mark = np.zeros(max(m, 1), np.uint8)
     draws = np.zeros(max(budget, 1), np.uint64) if return_draws else None
-    rc = _load().orc_es_draw(m, _ptr(ww, ctypes.c_uint32), float(p), int(budget), seed & (2**64 - 1),
-                             _ptr(mark, ctypes.c_uint8), None if draws is None else _ptr(draws, ctypes.c_uint64))
+    args = (m, _ptr(ww, ctypes.c_uint32))
+    rest = (int(budget), seed & (2**64 - 1), _ptr(mark, ctypes.c_uint8),
+            None if draws is None else _ptr(draws, ctypes.c_uint64))
+    if q is None:
+        rc = _load().orc_es_draw(*args, float(p), *rest)
+    else:
+        rc = _load().orc_es_draw_q(*args, float(q), *rest)
     if rc != OK:
         raise OracleError(rc)
     mark = mark[:m]
     return (mark, draws[:budget]) if return_draws else mark
 
 
-def sample_heavy_triangles(n, src, dst, w, k: int, p: float, budget: int, seed: int, nthreads: int = 0):
+def es_prefix_f64(w, q: float) -> np.ndarray:
+    """The FP64 prefix sums of w^q that the draws of a non-integer q search."""
+    ww = _arr(w, np.uint32)
+    P = np.zeros(max(ww.shape[0], 1), np.float64)
+    rc = _load().orc_es_prefix_f64(ww.shape[0], _ptr(ww, ctypes.c_uint32), float(q), _ptr(P, ctypes.c_double))
+    if rc != OK:
+        raise OracleError(rc)
+    return P[: ww.shape[0]]
+
+
+def sample_heavy_triangles(n, src, dst, w, k: int, p: float, budget: int, seed: int, nthreads: int = 0,
+                           q: float | None = None):
     """Alg. 3 end to end: draws, union of the triangles on the drawn edges, top-k by m_p."""
-    mark = es_draw(w, p, budget, seed)
+    mark = es_draw(w, p, budget, seed, q=q)
     out = topk(n, src, dst, w, k, p, nthreads=nthreads, edge_mark=mark)
     out["distinct_edges"] = int(mark.sum())
     return out

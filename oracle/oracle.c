@@ -21,7 +21,8 @@
  *     top-weighted triangles").  The result is by construction the first k of the total
  *     order above.
  *   - Weighted edge sampling (Alg. 3, Prop. 1): t independent draws of an edge with
- *     probability w_e^q / Z, by inverse CDF over the edges in input order; the result
+ *     probability w_e^q / Z, by inverse CDF over the edges in input order (q = p for finite
+ *     p > 0, else 1, unless the caller names q); the result
  *     set is the union over the draws of every triangle on the drawn edge, i.e. every
  *     triangle that has at least one drawn edge.  The uniform draws come from SplitMix64
  *     (Steele, Lea, Flood, OOPSLA 2014) so the GPU can replay the same sequence.
@@ -253,14 +254,14 @@ static void heap_push(heap_t *H, uint64_t k, const rec_t *r) {
 typedef struct {
     int mode; double p; uint64_t k;
     heap_t *heaps;
-    int filter; const uint8_t *mark;
+    const uint8_t *emark, *vmark; /* NULL: no condition */
 } topk_ctx;
 
 static void visit_topk(void *vctx, int tid, uint32_t i, uint32_t j, uint32_t l, uint32_t wij, uint32_t wil,
                        uint32_t wjl, uint64_t eij, uint64_t eil, uint64_t ejl) {
     topk_ctx *c = (topk_ctx *)vctx;
-    if (c->filter == FILTER_EDGE_MARK && !(c->mark[eij] | c->mark[eil] | c->mark[ejl])) return;
-    if (c->filter == FILTER_VERTEX_MARK && !(c->mark[i] | c->mark[j] | c->mark[l])) return;
+    if (c->emark && !(c->emark[eij] | c->emark[eil] | c->emark[ejl])) return;
+    if (c->vmark && !(c->vmark[i] | c->vmark[j] | c->vmark[l])) return;
     rec_t r;
     score3(c->mode, c->p, wij, wil, wjl, &r.key, &r.score);
     r.i = i; r.j = j; r.l = l;
@@ -271,14 +272,16 @@ static void visit_topk(void *vctx, int tid, uint32_t i, uint32_t j, uint32_t l, 
 
 /*
  * Top-k triangles by (score desc, i, j, l).  Writes min(k, T) records; *t_total = T (the
- * number of triangles admitted by the filter).  filter: 0 none; 1 mark[] over input edge
- * IDs (a triangle is admitted if one of its edges is marked); 2 mark[] over vertices.
+ * number of triangles admitted).  A triangle is admitted if emark is NULL or one of its
+ * edges is marked (emark[] over input edge IDs), and vmark is NULL or one of its vertices is
+ * marked (vmark[] over vertices).
  */
-int orc_topk(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w, uint64_t k,
-             double p, int nthreads, int filter, const uint8_t *mark, uint32_t *oi, uint32_t *oj, uint32_t *ol,
-             double *oscore, uint64_t *okey_hi, uint64_t *okey_lo, uint64_t *n_out, uint64_t *t_total) {
+int orc_topk_marked(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w,
+                    uint64_t k, double p, int nthreads, const uint8_t *emark, const uint8_t *vmark, uint32_t *oi,
+                    uint32_t *oj, uint32_t *ol, double *oscore, uint64_t *okey_hi, uint64_t *okey_lo,
+                    uint64_t *n_out, uint64_t *t_total) {
     if (n_out) *n_out = 0;
-    if (isnan(p) || (m && (!src || !dst || !w)) || (filter && !mark) || !n_out) return O_E_ARG;
+    if (isnan(p) || (m && (!src || !dst || !w)) || !n_out) return O_E_ARG;
     if (k && (!oi || !oj || !ol || !oscore)) return O_E_ARG;
     if (nthreads > 0) omp_set_num_threads(nthreads);
     adj_t g = {0};
@@ -291,7 +294,7 @@ int orc_topk(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, c
         heaps[t].h = (rec_t *)malloc((k ? k : 1) * sizeof(rec_t));
         if (!heaps[t].h) { for (int u = 0; u < T; u++) free(heaps[u].h); free(heaps); adj_free(&g); return O_E_NOMEM; }
     }
-    topk_ctx ctx = {orc_mode(p), p, k, heaps, filter, mark};
+    topk_ctx ctx = {orc_mode(p), p, k, heaps, emark, vmark};
     enumerate(&g, visit_topk, &ctx);
     uint64_t total = 0, kept = 0;
     for (int t = 0; t < T; t++) { total += heaps[t].count; kept += heaps[t].size; }
@@ -313,6 +316,17 @@ int orc_topk(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, c
     free(heaps);
     adj_free(&g);
     return O_OK;
+}
+
+/* One filter: 0 none; 1 mark[] over input edge IDs; 2 mark[] over vertices. */
+int orc_topk(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w, uint64_t k,
+             double p, int nthreads, int filter, const uint8_t *mark, uint32_t *oi, uint32_t *oj, uint32_t *ol,
+             double *oscore, uint64_t *okey_hi, uint64_t *okey_lo, uint64_t *n_out, uint64_t *t_total) {
+    if (n_out) *n_out = 0;
+    if ((filter && !mark) || filter < 0 || filter > FILTER_VERTEX_MARK) return O_E_ARG;
+    return orc_topk_marked(n, m, src, dst, w, k, p, nthreads, filter == FILTER_EDGE_MARK ? mark : NULL,
+                           filter == FILTER_VERTEX_MARK ? mark : NULL, oi, oj, ol, oscore, okey_hi, okey_lo,
+                           n_out, t_total);
 }
 
 /* ------------------------------------------------------------------ listing (small graphs) */
@@ -366,11 +380,10 @@ double orc_sample_exponent(double p) { return (isfinite(p) && p > 0.0) ? p : 1.0
  * input order and r = (x >> 11) * 2^-53 * Z.  Sets mark[e] = 1 for every drawn edge and,
  * if out_eids is not NULL, writes the draws in order.
  */
-int orc_es_draw(uint64_t m, const uint32_t *w, double p, uint64_t budget, uint64_t seed, uint8_t *mark,
-                uint64_t *out_eids) {
-    if (!mark || (m && !w) || isnan(p)) return O_E_ARG;
+int orc_es_draw_q(uint64_t m, const uint32_t *w, double q, uint64_t budget, uint64_t seed, uint8_t *mark,
+                  uint64_t *out_eids) {
+    if (!mark || (m && !w) || !(q > 0.0) || isinf(q)) return O_E_ARG;
     if (m == 0 || budget == 0) return O_OK;
-    const double q = orc_sample_exponent(p);
     const int exact = (q == 1.0 || q == 2.0 || q == 3.0);
     if (exact) {
         const int qi = (int)q;
@@ -413,6 +426,22 @@ int orc_es_draw(uint64_t m, const uint32_t *w, double p, uint64_t budget, uint64
         }
         free(P);
     }
+    return O_OK;
+}
+
+/* The draws with the sampling exponent of p (q = p for finite p > 0, else 1). */
+int orc_es_draw(uint64_t m, const uint32_t *w, double p, uint64_t budget, uint64_t seed, uint8_t *mark,
+                uint64_t *out_eids) {
+    if (isnan(p)) return O_E_ARG;
+    return orc_es_draw_q(m, w, orc_sample_exponent(p), budget, seed, mark, out_eids);
+}
+
+/* The FP64 inclusive prefix sums of w^q in input order that the draws of a non-integer q
+ * search (the same sequential sum as orc_es_draw_q). */
+int orc_es_prefix_f64(uint64_t m, const uint32_t *w, double q, double *P) {
+    if ((m && (!w || !P)) || !(q > 0.0) || isinf(q)) return O_E_ARG;
+    double acc = 0.0;
+    for (uint64_t e = 0; e < m; e++) { acc += pow((double)w[e], q); P[e] = acc; }
     return O_OK;
 }
 

@@ -149,6 +149,29 @@ def test_validation_codes():
     assert e.value.code == oracle.E_DUP_EDGE
 
 
+# Several faults in one input: the first failing rule in the order vertex range, self-loop,
+# zero weight, duplicate pair is reported (the reading of the simple-graph, positive-weight
+# requirement of Sec. 1), whatever the order of the faulty edges in the list.
+MULTI_FAULT = [
+    # (n, src, dst, w, expected)
+    (4, [0, 1, 2, 3], [1, 1, 3, 5], [1, 1, 1, 1], oracle.E_VERTEX_RANGE),        # loop, then range
+    (4, [0, 3, 1], [7, 3, 2], [0, 1, 1], oracle.E_VERTEX_RANGE),                 # range+zero, loop
+    (4, [0, 2, 1, 0], [1, 2, 0, 3], [1, 1, 1, 0], oracle.E_SELF_LOOP),           # loop, dup, zero
+    (4, [1, 0, 3], [0, 1, 3], [0, 1, 1], oracle.E_SELF_LOOP),                    # zero+dup, loop
+    (4, [0, 1, 2, 1], [1, 0, 3, 2], [1, 1, 0, 1], oracle.E_ZERO_WEIGHT),         # dup before zero
+    (4, [0, 1, 2, 3, 3], [1, 2, 0, 0, 2], [1, 1, 1, 1, 0], oracle.E_ZERO_WEIGHT),
+    (5, [0, 1, 0, 2, 4, 3], [1, 0, 2, 0, 3, 4], [1, 1, 1, 1, 1, 1], oracle.E_DUP_EDGE),  # three repeats
+]
+
+
+@pytest.mark.parametrize("case", range(len(MULTI_FAULT)))
+def test_validation_precedence_with_several_faults(case):
+    n, s, d, w, want = MULTI_FAULT[case]
+    assert oracle.validate(n, s, d, w) == want
+    # the same edges in reverse order report the same rule
+    assert oracle.validate(n, s[::-1], d[::-1], w[::-1]) == want
+
+
 # ---------------------------------------------------------------------------------- enumeration
 
 @pytest.mark.parametrize("seed", range(6))
@@ -303,6 +326,28 @@ def test_fewer_than_k_and_k_zero():
     assert oracle.topk(5, [], [], [], 3, 1.0)["n_out"] == 0
 
 
+def test_edge_and_vertex_filters_together():
+    """Both marks: a triangle is admitted when it has a marked edge AND a marked vertex."""
+    rng = np.random.default_rng(18)
+    n = 26
+    s, d, w = _rand_graph(rng, n, 0.5, 1, 12)
+    vm = np.zeros(n, np.uint8)
+    vm[[2, 9, 17]] = 1
+    em = (rng.random(len(s)) < 0.3).astype(np.uint8)
+    E = brute.edge_dict(s, d, w)
+    marked = {(min(int(a), int(b)), max(int(a), int(b))) for a, b, x in zip(s, d, em) if x}
+    tris = [t for t in brute.all_triangles(n, s, d, w)
+            if (vm[t[0]] or vm[t[1]] or vm[t[2]])
+            and ((t[0], t[1]) in marked or (t[0], t[2]) in marked or (t[1], t[2]) in marked)]
+    tris.sort(key=lambda t: (-(t[3] + t[4] + t[5]), t[0], t[1], t[2]))
+    out = oracle.topk(n, s, d, w, 12, 1.0, edge_mark=em, vertex_mark=vm)
+    assert out["total"] == len(tris) and len(E) == len(s)
+    assert list(zip(out["i"].tolist(), out["j"].tolist(), out["l"].tolist())) == [t[:3] for t in tris[:12]]
+    only_e = oracle.topk(n, s, d, w, 0, 1.0, edge_mark=em)["total"]
+    only_v = oracle.topk(n, s, d, w, 0, 1.0, vertex_mark=vm)["total"]
+    assert len(tris) <= min(only_e, only_v)
+
+
 def test_vertex_filter_matches_brute_force():
     rng = np.random.default_rng(8)
     n = 24
@@ -366,6 +411,68 @@ def test_exact_draw_is_inverse_cdf():
             assert int(draws[s]) == want
 
 
+def _replay_exact(w, q, seed, budget):
+    """The integer-q draw rule in Python integers: r = floor(x Z / 2^64), first e with
+    prefix[e] > r (bisect), for the first `budget` SplitMix64 outputs."""
+    import bisect
+    pref = list(itertools.accumulate(int(x) ** q for x in w.tolist()))
+    Z = pref[-1]
+    return Z, [bisect.bisect_right(pref, (oracle.splitmix64(seed, s) * Z) >> 64) for s in range(budget)]
+
+
+@pytest.mark.parametrize("case", ["near_2_32_q2", "near_2_32_q3", "planted_x1000_q3"])
+def test_exact_draw_target_above_2_64(case):
+    """Integer q with Z >= 2^64: the draw target floor(x Z / 2^64) has a high part x * floor(Z /
+    2^64) as well as the carry of x * (Z mod 2^64); dropping either term moves the draws.  Weights
+    near 2^32 - 1 at q = 2 and 3, and Zipf(1.8) weights with a few planted x1000 edges (the
+    1M-vertex workload's weight recipe) at q = 3."""
+    rng = np.random.default_rng(64)
+    if case.startswith("near_2_32"):
+        w = rng.integers(2**32 - 5000, 2**32, 257, dtype=np.uint64).astype(np.uint32)
+        q = 2 if case.endswith("q2") else 3
+    else:
+        w = graphgen.zipf(4_000_000, 1.8, seed=7)  # its w^3 tail alone reaches Z > 2^64
+        hot = rng.choice(len(w), size=300, replace=False)
+        w[hot] = (w[hot].astype(np.uint64) * 1000).astype(np.uint32)
+        q = 3
+    budget, seed = 4000, 2024 + q
+    Z, want = _replay_exact(w, q, seed, budget)
+    assert Z >= 2**64, Z
+    _, draws = oracle.es_draw(w, float(q), budget, seed=seed, return_draws=True)
+    assert draws.astype(np.int64).tolist() == want
+    # the high term matters: a target without x * floor(Z / 2^64) picks other edges
+    pref = list(itertools.accumulate(int(x) ** q for x in w.tolist()))
+    import bisect
+    lo_only = [bisect.bisect_right(pref, (oracle.splitmix64(seed, s) * (Z % 2**64)) >> 64) for s in range(50)]
+    assert lo_only != want[:50]
+
+
+def test_draw_with_q_override():
+    """The sampling exponent can be named (Alg. 3 samples by w^q; q = p is the default reading
+    for finite p > 0): the draws with q given equal the draws of p = q, for any p, and a
+    non-integer q draws the first edge whose FP64 prefix of w^q exceeds (x >> 11) 2^-53 Z."""
+    w = graphgen.zipf(5000, 1.8, seed=3)
+    for q in (1.0, 2.0, 0.5, 1.5):
+        a = oracle.es_draw(w, q, 3000, 77, return_draws=True)[1]
+        for p in (q, -1.0, math.inf, 0.0):
+            b = oracle.es_draw(w, p, 3000, 77, return_draws=True, q=q)[1]
+            assert np.array_equal(a, b), (q, p)
+    for q in (0.5, 1.5, 2.5):
+        P = oracle.es_prefix_f64(w, q)
+        # the prefix is the running sum of w^q: its total agrees with an exactly rounded sum
+        assert abs(P[-1] - math.fsum(float(x) ** q for x in w.tolist())) <= 1e-12 * P[-1]
+        assert np.all(np.diff(P) > 0)
+        _, draws = oracle.es_draw(w, 1.0, 2000, 5, return_draws=True, q=q)
+        for s in range(2000):
+            r = float(oracle.splitmix64(5, s) >> 11) * 2.0**-53 * P[-1]
+            e = int(draws[s])
+            assert P[e] > r and (e == 0 or P[e - 1] <= r), (q, s)
+    with pytest.raises(oracle.OracleError):
+        oracle.es_draw(w, 1.0, 10, 1, q=0.0)
+    with pytest.raises(oracle.OracleError):
+        oracle.es_draw(w, 1.0, 10, 1, q=math.inf)
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_es_union_matches_replay(seed):
     rng = np.random.default_rng(300 + seed)
@@ -396,4 +503,5 @@ def test_es_with_large_budget_is_exact():
     exact = oracle.topk(g.n, g.src, g.dst, g.w, 50, 1.0)
     es = oracle.sample_heavy_triangles(g.n, g.src, g.dst, g.w, 50, 1.0, budget, seed=3)
     assert es["distinct_edges"] == g.m
-    assert es["i"].tolist() == exact["i"].tolist() and es["l"].tolist() == exact["l"].tolist()
+    for x in ("i", "j", "l", "score"):
+        assert es[x].tolist() == exact[x].tolist(), x
