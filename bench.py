@@ -4,19 +4,27 @@
 One step = one pass of the whole hot path over the resident edge list of the workload:
   1. graph_load from device-resident src/dst/w (validation + degree-oriented CSR build);
   2. exact top-k queries (topk_triangles) at each p of the workload;
-  3. weighted edge sampling queries (sample_heavy_triangles) at the same p's;
+  3. weighted edge sampling queries (sample_heavy_triangles) at the same p's (workloads with a
+     sampling budget);
   4. graph_free.
 `value` is queries per second over the timed steps (all queries of a step / step time).
 
-Default workload ("medium"): Chung-Lu n=1M, ~20M edges, gamma 2.1, Zipf(s=1.8) weights on
-[1, 1e6], plus 50 planted 4-cliques with weights x1000, seed 0; top-1000 at
-p in {-inf, 1, 2, +inf}; sampling budget 1e7 draws.
+Default workload ("large"): Chung-Lu n=100M, ~2B edges, gamma 2.0, Zipf(s=1.5) weights on
+[1, 1e6], seed 0; top-1000 at p = 1 and p = +inf, the CSR built cold in every step (queries
+on the resident CSR are reported beside it).  "medium" (n=1M, ~20M edges, 50 planted heavy
+4-cliques, four p, sampling 1e7 draws), "small", "batch" and "serve" are the other workloads.
 
 The JSON line also carries:
-  roofline     : the enumeration kernel (k_enum), algorithmic bytes per launch / its mean
-                 duration measured with HIP events on the graph's stream;
-  cpu_baseline : the CPU oracle (plain enumeration + per-thread heaps) timed on a bounded
-                 sample of the same workload on this host's cores.
+  roofline       : the enumeration pass (k_enum: filter + intersect kernels of one band),
+                   algorithmic bytes per pass / its mean duration measured with HIP events on
+                   the graph's stream; bytes per unit: 6 per streamed entry (its weight and the
+                   amortised row-maximum gathers), 20 per candidate entry (two row extents and
+                   its weight), 8 per intersected adjacency entry, 8 per triangle found;
+                   `traffic` is the counter-measured HBM bytes per pass from profiles/;
+  build_roofline : the cold CSR build, 20 bytes per edge (12 read, 8 written) / its duration;
+  cpu_baseline   : the CPU oracle (plain enumeration + per-thread heaps) timed on this host's
+                   cores; on the 2B-edge graph time-boxed on the whole graph, with a
+                   vertex-sample extrapolation and a one-thread time beside it.
 """
 from __future__ import annotations
 
@@ -34,11 +42,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "top-k triangle queries/sec + intersected edges/sec (HBM GB/s %); p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes of the enumeration kernel, per unit
-B_STREAM = 20   # per oriented entry streamed: tail, head, weight (12 B) + two row maxima (8 B)
-B_CAND = 32     # per candidate entry: the two row extents (4 x 8 B)
-B_INTER = 8     # per intersected entry: neighbour ID + weight
-B_EMIT = 32     # per triangle written to the candidate buffer
+# algorithmic bytes of the enumeration pass, per unit: a streaming pass reads each entry's
+# weight (4 B) plus the row maxima it is compared with, gathered once per row and amortised
+# over the row (<= 2 B per entry: 8-12 GB for a 2B-entry pass); a candidate reads its two row
+# extents and its weight (20 B); an intersected adjacency entry its head and weight (8 B); a
+# triangle found the two other weights (8 B)
+B_STREAM = 6
+B_CAND = 20
+B_INTER = 8
+B_EMIT = 8
+B_BUILD = 20    # cold CSR build, per edge: 12 B read (src, dst, w) + 8 B written (col, wgt)
 
 WORKLOADS = {
     "medium": dict(gen="medium", k=1000, ps=(-math.inf, 1.0, 2.0, math.inf), budget=10_000_000,
@@ -46,7 +59,7 @@ WORKLOADS = {
                         "top-1000 exact + edge sampling 1e7 draws at p in {-inf,1,2,+inf}"),
     "small": dict(gen="small", k=100, ps=(1.0,), budget=100_000,
                   desc="chung-lu n=2000 m~20k gamma2.5 zipf(2)[1,1e6] seed0; top-100 exact + edge sampling 1e5 at p=1"),
-    "large": dict(gen="large", k=1000, ps=(1.0, math.inf), budget=0, cpu_edges=20_000_000,
+    "large": dict(gen="large", k=1000, ps=(1.0, math.inf), budget=0, cpu_timebox=60.0,
                   desc="chung-lu n=100M m~2B gamma2.0 zipf(1.5)[1,1e6] seed0; top-1000 exact at p in {1,+inf}, "
                        "cold (CSR built in the step) and warm"),
 }
@@ -252,7 +265,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=sorted(WORKLOADS) + ["serve", "batch"])
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS) + ["serve", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sampling", action="store_true", help="exact queries only")
     ap.add_argument("--no-warm", action="store_true",
@@ -281,11 +294,23 @@ def main():
     if args.workload == "batch":
         return run_batch(args)
 
-    import torch
     import graphgen
-    import paper_1910_00692_amd as tt
 
     W = WORKLOADS[args.workload]
+    t = time.time()
+    g = getattr(graphgen, W["gen"])()
+    gen_s = time.time() - t
+    print(f"[bench] workload {args.workload}: n={g.n} m={g.m} (generated in {gen_s:.1f}s)", file=sys.stderr, flush=True)
+    k, ps, budget = W["k"], W["ps"], W["budget"]
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu = None
+    if not args.no_cpu_baseline and W.get("cpu_timebox"):
+        # before anything touches the GPU (the time-boxed run starts a child process)
+        cpu = cpu_baseline_timeboxed(g, W["gen"], k, W["cpu_timebox"], nthreads)
+
+    import torch
+    import paper_1910_00692_amd as tt
+
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.int32, device="cuda:0").fill_(1)
         b = torch.empty_like(a)
@@ -293,10 +318,6 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    t = time.time()
-    g = getattr(graphgen, W["gen"])()
-    gen_s = time.time() - t
-    print(f"[bench] workload {args.workload}: n={g.n} m={g.m} (generated in {gen_s:.1f}s)", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     s_d = torch.from_numpy(g.src.view(np.int32)).to(dev)
     d_d = torch.from_numpy(g.dst.view(np.int32)).to(dev)
@@ -304,15 +325,18 @@ def main():
     stream = torch.cuda.current_stream(dev)
     torch.cuda.synchronize()
 
-    k, ps, budget = W["k"], W["ps"], W["budget"]
     do_es = budget > 0 and not args.no_sampling
     lat = {"build": [], "exact": [], "sample": []}
     agg = {"stream": 0, "cand": 0, "inter": 0, "emit": 0, "kernel_ms": 0.0, "launches": 0, "queries": 0}
     first_results = {}
+    build_ev = []
 
     def step(record: bool, idx: int):
         t0 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         G = tt.Graph(g.n, s_d, d_d, w_d, stream=stream)
+        e1.record(stream)
         t1 = time.perf_counter()
         nq = 0
         for p in ps:
@@ -339,6 +363,7 @@ def main():
         G.close()
         if record:
             lat["build"].append((t1 - t0) * 1e3)
+            build_ev.append((e0, e1))
             agg["queries"] += nq
         return nq
 
@@ -359,12 +384,23 @@ def main():
     launches = max(agg["launches"], 1)
     mean_launch_ms = agg["kernel_ms"] / launches
     achieved = (alg_bytes / launches) / (mean_launch_ms * 1e-3) / 1e9 if mean_launch_ms > 0 else None
-    roofline = {"bound": "hbm", "kernel": "k_enum", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": recorded_traffic(args.workload),
-                "bytes_per_launch": alg_bytes / launches, "mean_launch_ms": mean_launch_ms, "launches": launches}
+    traffic = recorded_traffic(args.workload)
+    roofline = {"bound": "hbm", "kernel": "k_enum (k_filter + k_intersect + k_intersect_heavy of one band)",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                "traffic_over_algorithmic": (traffic / (alg_bytes / launches)) if traffic and alg_bytes else None,
+                "bytes_per_launch": alg_bytes / launches, "mean_launch_ms": mean_launch_ms, "launches": launches,
+                "units_per_launch": {x: agg[x] / launches for x in ("stream", "cand", "inter", "emit")}}
+    build_ms = float(np.median([a.elapsed_time(b) for a, b in build_ev])) if build_ev else None
+    build_roofline = None
+    if build_ms:
+        bach = B_BUILD * g.m / (build_ms * 1e-3) / 1e9
+        build_roofline = {"bound": "hbm", "kernel": "CSR build (graph_load: every build kernel)", "achieved": bach,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bach / HBM_PEAK_GBS,
+                          "bytes_per_launch": B_BUILD * g.m, "mean_launch_ms": build_ms}
 
     warm = {}
-    if W.get("cpu_edges") and not args.no_warm:
+    if args.workload == "large" and not args.no_warm:
         # queries on a resident CSR (the steps above build it cold every time): the second query
         # of each p, then the steady state once repeated queries of p have built its bound order
         def brief(r):
@@ -386,31 +422,21 @@ def main():
             warm[str(p)] = {"second_query": second, "with_bound_order": steady, "queries_until_order": n_q}
         G.close()
 
-    cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not W.get("cpu_timebox"):
         import oracle
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        ce = W.get("cpu_edges") or g.m
-        print(f"[bench] cpu baseline: oracle top-{k} at p=1 on {nthreads} threads, {ce} edges", file=sys.stderr,
+        print(f"[bench] cpu baseline: oracle top-{k} at p=1 on {nthreads} threads, {g.m} edges", file=sys.stderr,
               flush=True)
         tc = time.perf_counter()
-        want = oracle.topk(g.n, g.src[:ce], g.dst[:ce], g.w[:ce], k, 1.0, nthreads=nthreads)
+        want = oracle.topk(g.n, g.src, g.dst, g.w, k, 1.0, nthreads=nthreads)
         cpu_s = time.perf_counter() - tc
-        got = first_results.get(("exact", 1.0)) if ce == g.m else None
+        got = first_results.get(("exact", 1.0))
         checked = None
         if got is not None:
             checked = bool(np.array_equal(got["i"], want["i"]) and np.array_equal(got["j"], want["j"])
                            and np.array_equal(got["l"], want["l"]) and np.array_equal(got["score"], want["score"]))
-        if ce == g.m:
-            cpu = {"value": 1.0 / cpu_s, "unit": "queries/s", "cores": nthreads, "kind": "oracle",
-                   "sample": f"one exact top-{k} query at p=1 on the full workload graph ({want['total']} triangles "
-                             f"enumerated), {cpu_s:.2f}s", "gpu_matches_oracle": checked}
-        else:
-            # a bounded sample: the first ce edges of the edge list; the rate is scaled to the full
-            # graph linearly in m, which flatters the CPU (enumeration grows faster than m)
-            cpu = {"value": 1.0 / (cpu_s * g.m / ce), "unit": "queries/s", "cores": nthreads, "kind": "oracle",
-                   "sample": f"one exact top-{k} query at p=1 on the first {ce} edges of the workload "
-                             f"({want['total']} triangles), {cpu_s:.2f}s, scaled linearly to m={g.m}"}
+        cpu = {"value": 1.0 / cpu_s, "unit": "queries/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"one exact top-{k} query at p=1 on the full workload graph ({want['total']} triangles "
+                         f"enumerated), {cpu_s:.2f}s", "gpu_matches_oracle": checked, "cpu_model": cpu_model()}
 
     out = {
         "metric": METRIC, "value": value, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -420,6 +446,7 @@ def main():
                    "sample_budget": budget if do_es else 0, "queries_per_step": nq_total // max(args.steps, 1),
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "build_roofline": build_roofline,
         "cpu_baseline": cpu,
         "intersected_edges_per_s": agg["inter"] / elapsed,
         "latency_ms": {kk: {"p50": pct(v, 50), "p99": pct(v, 99), "n": len(v)} for kk, v in lat.items()},
@@ -428,6 +455,94 @@ def main():
     if warm:
         out["warm_resident_csr"] = warm
     print(json.dumps(out), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_child(conn, gen, k, nthreads):
+    """Generates the workload graph again (a fresh process: the oracle's OpenMP runtime must not
+    be inherited through fork) and runs the oracle on it; reports readiness, then the time."""
+    sys.path.insert(0, ROOT)
+    import graphgen
+    import oracle
+    g = getattr(graphgen, gen)()
+    conn.send("ready")
+    t = time.perf_counter()
+    r = oracle.topk(g.n, g.src, g.dst, g.w, k, 1.0, nthreads=nthreads)
+    conn.send((time.perf_counter() - t, r["total"]))
+    conn.close()
+
+
+def cpu_baseline_timeboxed(g, gen, k, budget_s, nthreads):
+    """The oracle on the whole graph, top-k at p = 1, in a child process stopped after budget_s
+    (the value is then an upper bound, as the paper reports a run that did not finish); beside it
+    the oracle on vertex samples (every vertex kept with probability f, the graph's IDs being a
+    random permutation: the vertices with ID < f n) at f = 0.1 and 0.15, extrapolated to f = 1
+    with t(f) = a f^2 + b f^3 (building the adjacency grows with the edges, f^2; enumeration with
+    the wedges and triangles, f^3), and the f = 0.1 sample on one thread."""
+    import multiprocessing as mp
+    import oracle
+    ctx = mp.get_context("spawn")
+    parent, child = ctx.Pipe(duplex=False)
+    print(f"[bench] cpu baseline: oracle on the whole graph, {nthreads} threads, time box {budget_s:.0f}s",
+          file=sys.stderr, flush=True)
+    proc = ctx.Process(target=_oracle_child, args=(child, gen, k, nthreads))
+    proc.start()
+    child.close()
+    whole = None
+    if parent.poll(600) and parent.recv() == "ready" and parent.poll(budget_s):
+        whole = parent.recv()
+    proc.kill()
+    proc.join()
+
+    def induced(f):
+        lim = np.uint32(int(f * g.n))
+        parts = []
+        for lo in range(0, g.m, 1 << 27):
+            s, d = g.src[lo:lo + (1 << 27)], g.dst[lo:lo + (1 << 27)]
+            parts.append(np.nonzero((s < lim) & (d < lim))[0] + lo)
+        sel = np.concatenate(parts)
+        return g.src[sel], g.dst[sel], g.w[sel]
+
+    samples = {}
+    for f in (0.1, 0.15):
+        s, d, w = induced(f)
+        t = time.perf_counter()
+        r = oracle.topk(g.n, s, d, w, k, 1.0, nthreads=nthreads)
+        samples[f] = (time.perf_counter() - t, len(s), r["total"])
+        print(f"[bench] cpu sample f={f}: {len(s)} edges, {r['total']} triangles, {samples[f][0]:.2f}s",
+              file=sys.stderr, flush=True)
+    s, d, w = induced(0.1)
+    t = time.perf_counter()
+    oracle.topk(g.n, s, d, w, k, 1.0, nthreads=1)
+    one_thread = time.perf_counter() - t
+    (f1, (t1, m1, T1)), (f2, (t2, m2, T2)) = sorted(samples.items())
+    # t = a f^2 + b f^3 through both points
+    b = (t2 / f2 ** 2 - t1 / f1 ** 2) / (f2 - f1)
+    a = t1 / f1 ** 2 - b * f1
+    a, b = max(a, 0.0), max(b, 0.0)
+    extrap = a + b if a + b > 0 else max(t1 / f1 ** 3, t2 / f2 ** 3)
+    if whole:
+        value, desc = 1.0 / whole[0], f"one exact top-{k} query at p=1 on the whole graph ({whole[1]} triangles), " \
+                                      f"{whole[0]:.1f}s"
+    else:
+        value = 1.0 / budget_s
+        desc = (f"one exact top-{k} query at p=1 on the whole graph, time-boxed: not finished in {budget_s:.0f}s, so "
+                f"the value is an upper bound; extrapolated from vertex samples: {extrap:.0f}s per query")
+    return {"value": value, "unit": "queries/s", "cores": nthreads, "kind": "oracle", "sample": desc,
+            "finished": bool(whole), "time_box_s": budget_s, "cpu_model": cpu_model(),
+            "vertex_samples": [{"f": f, "edges": m_, "triangles": T_, "s": t_}
+                               for f, (t_, m_, T_) in sorted(samples.items())],
+            "extrapolated_s_per_query": extrap, "extrapolated_queries_per_s": 1.0 / extrap,
+            "one_thread": {"f": 0.1, "s": one_thread, "threads_speedup": one_thread / samples[0.1][0]}}
 
 
 if __name__ == "__main__":

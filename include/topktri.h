@@ -114,15 +114,26 @@ int topk_triangles_ex(tt_graph *g, uint32_t k, double p, const uint32_t *subset,
  * by the true m_p, of the union of all triangles on the drawn edges.  Draw s uses the s-th
  * output of SplitMix64 started from `seed` (Steele, Lea, Flood 2014) and selects the first
  * edge, in input order, whose inclusive prefix sum of w^q exceeds floor(x_s * Z / 2^64)
- * (integer q in {1, 2, 3}, exact 128-bit arithmetic) or x_s * 2^-64 * Z (other q, FP64).
+ * (integer q in {1, 2, 3}, exact 128-bit arithmetic) or (x_s >> 11) * 2^-53 * Z (other q, FP64).
  * budget = 0 or k = 0 returns TT_OK with *n_out = 0.
  */
 int sample_heavy_triangles(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed, tt_triangle *out,
                            uint32_t *n_out);
 
-/* sample_heavy_triangles with optional stats (may be NULL). */
-int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed,
-                              tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
+/*
+ * sample_heavy_triangles with the sampling exponent named and the draws returned (Alg. 3;
+ * Prop. 1 gives the probability of a triangle for any exponent).
+ *   q      : edges are drawn with probability w_e^q / Z.  NaN selects the default reading
+ *            above (q = p for finite p > 0, else 1); otherwise q must be finite and > 0, else
+ *            TT_E_ARG.  The draw rule is the one above for this q (exact 128-bit for q in
+ *            {1, 2, 3}, FP64 prefix sums otherwise).  Ranking always uses the true m_p.
+ *   draws  : NULL, or a caller-owned HOST array of `budget` uint32 that receives the input
+ *            edge index of every draw, in draw order (draw s at draws[s]).  With draws given,
+ *            k = 0 runs the draws only.
+ *   stats  : may be NULL.
+ */
+int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed, double q,
+                              uint32_t *draws, tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
 
 /*
  * Serving: a request loop over one resident graph.  Callers: services that answer a stream of

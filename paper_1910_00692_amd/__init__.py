@@ -99,7 +99,7 @@ def library():
         lib.topk_triangles.argtypes = [vp, u32, dbl, ptri, p32]
         lib.topk_triangles_ex.argtypes = [vp, u32, dbl, p32, u32, ptri, p32, pst]
         lib.sample_heavy_triangles.argtypes = [vp, u32, dbl, u64, u64, ptri, p32]
-        lib.sample_heavy_triangles_ex.argtypes = [vp, u32, dbl, u64, u64, ptri, p32, pst]
+        lib.sample_heavy_triangles_ex.argtypes = [vp, u32, dbl, u64, u64, dbl, p32, ptri, p32, pst]
         lib.graph_num_vertices.argtypes = [vp]
         lib.graph_num_vertices.restype = u32
         lib.graph_num_edges.argtypes = [vp]
@@ -210,17 +210,25 @@ class Graph:
             out["stats"] = st.as_dict()
         return out
 
-    def sample(self, k: int, p: float, budget: int, seed: int, with_stats: bool = False):
-        """Weighted edge sampling (Alg. 3): top-k of the union of triangles on the drawn edges."""
+    def sample(self, k: int, p: float, budget: int, seed: int, with_stats: bool = False, q: float | None = None,
+               return_draws: bool = False):
+        """Weighted edge sampling (Alg. 3): top-k of the union of triangles on the drawn edges.
+        q names the sampling exponent (default: p for finite p > 0, else 1); return_draws adds
+        the input edge index of every draw ("draws", uint32[budget])."""
         lib = library()
         buf = (Triangle * max(int(k), 1))()
         n_out = ctypes.c_uint32(0)
         st = QueryStats()
-        _check(lib.sample_heavy_triangles_ex(self._h, int(k), float(p), int(budget), int(seed) & (2**64 - 1), buf,
-                                             ctypes.byref(n_out), ctypes.byref(st)))
+        draws = np.zeros(max(int(budget), 1), np.uint32) if return_draws else None
+        _check(lib.sample_heavy_triangles_ex(self._h, int(k), float(p), int(budget), int(seed) & (2**64 - 1),
+                                             math.nan if q is None else float(q),
+                                             None if draws is None else draws.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                             buf, ctypes.byref(n_out), ctypes.byref(st)))
         out = _result(buf, n_out.value)
         if with_stats:
             out["stats"] = st.as_dict()
+        if return_draws:
+            out["draws"] = draws[: int(budget)]
         return out
 
     def close(self):

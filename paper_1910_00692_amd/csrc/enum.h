@@ -11,49 +11,59 @@ __host__ __device__ __forceinline__ double u128_to_double(u128 x) {
     return (double)(uint64_t)(x >> 64) * 18446744073709551616.0 + (double)(uint64_t)x;
 }
 
+// The scoring and bound functions below are compiled for the host as well, so that their
+// pruning properties can be checked on the CPU.
+//
 // Eq. 1 for a generic p, rewritten so that no power overflows and small |p| loses nothing:
 // m = s * exp(log1p(mean(expm1(p * log(x/s)))) / p), s = max (p > 0) or min (p < 0).
-__device__ double gen_mean(double p, double a, double b, double c) {
+__host__ __device__ inline double gen_mean(double p, double a, double b, double c) {
     const double s = p > 0.0 ? fmax(a, fmax(b, c)) : fmin(a, fmin(b, c));
     const double acc = expm1(p * log(a / s)) + expm1(p * log(b / s)) + expm1(p * log(c / s));
     return s * exp(log1p(acc / 3.0) / p);
 }
 
+__host__ __device__ __forceinline__ uint32_t max3(uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t x = a > b ? a : b;
+    return x > c ? x : c;
+}
+__host__ __device__ __forceinline__ uint32_t min3(uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t x = a < b ? a : b;
+    return x < c ? x : c;
+}
+
 // Order key of the integer modes (every mode but the generic p).
-__device__ __forceinline__ u128 int_key(int mode, uint32_t a, uint32_t b, uint32_t c) {
+__host__ __device__ __forceinline__ u128 int_key(int mode, uint32_t a, uint32_t b, uint32_t c) {
     switch (mode) {
-    case MODE_MAX: return (u128)max(a, max(b, c));
-    case MODE_MIN: return (u128)min(a, min(b, c));
+    case MODE_MAX: return (u128)max3(a, b, c);
+    case MODE_MIN: return (u128)min3(a, b, c);
     case MODE_SUM: return (u128)((uint64_t)a + b + c);
     case MODE_SUMSQ: return (u128)((uint64_t)a * a) + (u128)((uint64_t)b * b) + (u128)((uint64_t)c * c);
-    default: { // MODE_PROD
-        const uint64_t ab = (uint64_t)a * b;
-        const uint64_t lo = ab * (uint64_t)c, hi = __umul64hi(ab, (uint64_t)c);
-        return ((u128)hi << 64) | lo;
-    }
+    default: // MODE_PROD
+        return (u128)((uint64_t)a * b) * (uint64_t)c;
     }
 }
 
 // The kernels of a pass are compiled twice: GEN for the generic p (FP64 bits of Eq. 1) and
 // !GEN for the integer modes, which then carry none of the transcendental code (and need far
 // fewer registers).
-template <bool GEN> __device__ __forceinline__ u128 score_key_t(int mode, double p, uint32_t a, uint32_t b, uint32_t c) {
-    if (GEN) return (u128)(uint64_t)__double_as_longlong(gen_mean(p, (double)a, (double)b, (double)c));
+template <bool GEN>
+__host__ __device__ __forceinline__ u128 score_key_t(int mode, double p, uint32_t a, uint32_t b, uint32_t c) {
+    if (GEN) return (u128)__builtin_bit_cast(uint64_t, gen_mean(p, (double)a, (double)b, (double)c));
     return int_key(mode, a, b, c);
 }
 
-__device__ __forceinline__ u128 score_key(int mode, double p, uint32_t a, uint32_t b, uint32_t c) {
+__host__ __device__ __forceinline__ u128 score_key(int mode, double p, uint32_t a, uint32_t b, uint32_t c) {
     return mode == MODE_GEN ? score_key_t<true>(mode, p, a, b, c) : int_key(mode, a, b, c);
 }
 
-__device__ double key_to_score(int mode, u128 key) {
+__host__ __device__ inline double key_to_score(int mode, u128 key) {
     switch (mode) {
     case MODE_MAX:
     case MODE_MIN: return (double)(uint64_t)key;
     case MODE_SUM: return (double)(uint64_t)key / 3.0;
     case MODE_SUMSQ: return sqrt(u128_to_double(key) / 3.0);
     case MODE_PROD: return cbrt(u128_to_double(key));
-    default: return __longlong_as_double((long long)(uint64_t)key);
+    default: return __builtin_bit_cast(double, (uint64_t)key);
     }
 }
 
@@ -84,7 +94,8 @@ struct Band {
 };
 
 // key(a, Wu, Wv) >= L : no triangle on this entry can reach the band otherwise
-template <bool GEN> __device__ __forceinline__ bool bound_ok(const Band &B, uint32_t a, uint32_t Wu, uint32_t Wv) {
+template <bool GEN>
+__host__ __device__ __forceinline__ bool bound_ok(const Band &B, uint32_t a, uint32_t Wu, uint32_t Wv) {
     if (B.L == 0) return true;
     if (GEN) {
         // cheap upper bounds first: m_p <= max for every p, m_p <= arithmetic mean for p <= 1
@@ -119,7 +130,7 @@ __host__ __device__ uint64_t gen_min_other(double p, double theta, double a, dou
 }
 
 // Smallest weight x (a lower bound of it) for which key(a, x, W) can still reach L.
-template <bool GEN> __device__ __forceinline__ uint64_t min_other(const Band &B, uint32_t a, uint32_t W) {
+template <bool GEN> __host__ __device__ __forceinline__ uint64_t min_other(const Band &B, uint32_t a, uint32_t W) {
     if (B.L == 0) return 0;
     if (GEN) return gen_min_other(B.p, B.theta, (double)a, (double)W);
     switch (B.mode) {
@@ -748,8 +759,8 @@ __global__ void k_band_gate(const unsigned long long *count, unsigned long long 
 
 // An integer >= the score of every triangle based at entry u->v (m_p of the entry's weight
 // and the two row maxima), at most the largest of the three.
-__device__ __forceinline__ uint32_t entry_bound(int mode, double p, uint32_t a, uint32_t Wu, uint32_t Wv) {
-    const uint32_t mx = max(a, max(Wu, Wv));
+__host__ __device__ __forceinline__ uint32_t entry_bound(int mode, double p, uint32_t a, uint32_t Wu, uint32_t Wv) {
+    const uint32_t mx = max3(a, Wu, Wv);
     const double sc = key_to_score(mode, score_key(mode, p, a, Wu, Wv));
     const double up = ceil(sc * (1.0 + 1e-9));
     return up >= (double)mx ? mx : (uint32_t)up;

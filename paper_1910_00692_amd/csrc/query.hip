@@ -213,9 +213,11 @@ __global__ __launch_bounds__(256) void k_es_guide(const void *prefix, uint64_t m
     }
 }
 
+// Draw s marks the entry of its edge; with `dump` it also records the edge's input index.
 template <int KIND>
 __global__ __launch_bounds__(256) void k_es_draw(const void *prefix, const uint32_t *G, uint32_t bits, uint64_t m,
-                                                 uint64_t budget, uint64_t seed, const uint32_t *opos, uint8_t *emark) {
+                                                 uint64_t budget, uint64_t seed, const uint32_t *opos, uint8_t *emark,
+                                                 uint32_t *dump) {
     typedef typename Draw<KIND>::T T;
     const T *P = (const T *)prefix;
     for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < budget; s += (uint64_t)gridDim.x * blockDim.x) {
@@ -223,6 +225,7 @@ __global__ __launch_bounds__(256) void k_es_draw(const void *prefix, const uint3
         const uint64_t j = x >> (64 - bits);
         const uint64_t e = first_above<T>(P, G[j], G[j + 1], Draw<KIND>::r(P, m, x));
         emark[opos[e]] = 1;
+        if (dump) dump[s] = (uint32_t)e;
     }
 }
 
@@ -1189,21 +1192,30 @@ extern "C" int topk_triangles(tt_graph *g, uint32_t k, double p, tt_triangle *ou
 }
 
 extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed,
-                                         tt_triangle *out, uint32_t *n_out, tt_query_stats *stats) {
+                                         double qexp, uint32_t *draws, tt_triangle *out, uint32_t *n_out,
+                                         tt_query_stats *stats) {
     Timer timer;
     int rc = check_query(g, p, out, k, n_out);
     if (rc) return rc;
+    if (!std::isnan(qexp) && !(qexp > 0.0 && std::isfinite(qexp)))
+        return fail(TT_E_ARG, "the sampling exponent q must be finite and > 0 (or NaN for the default)");
     if (stats) std::memset(stats, 0, sizeof(*stats));
-    if (k == 0 || budget == 0 || g->m == 0) { set_error(""); return TT_OK; }
+    if (budget == 0 || g->m == 0 || (k == 0 && !draws)) { set_error(""); return TT_OK; }
     std::lock_guard<std::mutex> lock(g->mu);
     (void)hipSetDevice(g->device);
     QueryCtx *q = &g->q;
     if ((rc = ensure_flags(g, q)) || (rc = ensure_scratch(g, q, 1, 1))) return rc;
     if (!g->emark && (rc = dev_alloc(g, (void **)&g->emark, g->m + 1))) return rc;
     if ((rc = ensure_opos(g, q->stream))) return rc;
-    const double qexp = (std::isfinite(p) && p > 0.0) ? p : 1.0;
+    if (std::isnan(qexp)) qexp = (std::isfinite(p) && p > 0.0) ? p : 1.0;
     const int kind = qexp == 1.0 ? 0 : (qexp == 2.0 || qexp == 3.0) ? 1 : 2;
     hipStream_t s = q->stream;
+    uint32_t *ddump = nullptr; // device copy of the draw sequence (draws != NULL)
+    if (draws && (rc = dev_alloc(nullptr, (void **)&ddump, budget * 4))) return rc;
+    struct DumpGuard { // returned to the cache once the stream is done with it
+        uint32_t *p; hipStream_t s;
+        ~DumpGuard() { if (p) { (void)hipStreamSynchronize(s); dev_free(nullptr, p, 0); } }
+    } dump_guard{ddump, s};
     HIP_TRY(hipEventRecord(q->ev[6], s));
     tt_graph::SampleTable *tab = nullptr;
     if ((rc = sample_table(g, qexp, kind, &tab))) return rc;
@@ -1212,12 +1224,21 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
     HIP_TRY(hipMemsetAsync(q->dcount + 14, 0, sizeof(unsigned long long), s)); // distinct draws
     const unsigned grid = (unsigned)std::min<uint64_t>((budget + 255) / 256, (uint64_t)num_cus() * 16);
     const uint32_t bits = g->guide_bits;
-    if (kind == 0) k_es_draw<0><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
-    else if (kind == 1) k_es_draw<1><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
-    else k_es_draw<2><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark);
+    if (kind == 0) k_es_draw<0><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark, ddump);
+    else if (kind == 1) k_es_draw<1><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark, ddump);
+    else k_es_draw<2><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark, ddump);
     k_mark_tails<<<enum_grid(g->m / 16 + 1), 256, 0, s>>>(g->emark, g->m, g->osrc, q->vflag, q->dcount + 14);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(q->ev[7], s));
+    if (ddump) {
+        HIP_TRY(hipMemcpyAsync(draws, ddump, budget * 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (k == 0) {
+            if (stats) stats->total_ms = timer.ms();
+            set_error("");
+            return TT_OK;
+        }
+    }
     BoundOrder *o = nullptr;
     if ((rc = acquire_order(g, q, p, &o))) return rc;
     q->ord = o;
@@ -1238,7 +1259,7 @@ extern "C" int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint
 
 extern "C" int sample_heavy_triangles(tt_graph *g, uint32_t k, double p, uint64_t budget, uint64_t seed,
                                       tt_triangle *out, uint32_t *n_out) {
-    return sample_heavy_triangles_ex(g, k, p, budget, seed, out, n_out, nullptr);
+    return sample_heavy_triangles_ex(g, k, p, budget, seed, __builtin_nan(""), nullptr, out, n_out, nullptr);
 }
 
 // ----------------------------------------------------------------------------- serving

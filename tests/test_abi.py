@@ -58,6 +58,8 @@ def test_argument_errors_before_device_work(lib):
     assert lib.topk_triangles(None, 4, 1.0, out, ctypes.byref(n_out)) == tt.TT_E_ARG
     assert n_out.value == 0
     assert lib.sample_heavy_triangles(None, 4, 1.0, 10, 1, out, ctypes.byref(n_out)) == tt.TT_E_ARG
+    assert lib.sample_heavy_triangles_ex(None, 4, 1.0, 10, 1, math.nan, None, out, ctypes.byref(n_out),
+                                         None) == tt.TT_E_ARG
     lib.graph_free(None)  # NULL-safe
     assert lib.graph_num_edges(None) == 0 and lib.graph_num_vertices(None) == 0
 

@@ -51,13 +51,18 @@ def test_medium_exact(medium, p):
         assert planted <= set(triples(got))
 
 
-@pytest.mark.parametrize("p", [1.0, -math.inf])
+@pytest.mark.parametrize("p", [-math.inf, 1.0, 2.0, math.inf, 3.0])
 def test_medium_sampling(medium, p):
+    """Edge sampling with 1e7 draws at every p of the workload (q = 1 for p = +-inf, q = 2 at
+    p = 2: the 128-bit prefix scan, guide table and draw at m = 20M), and at p = 3, where this
+    graph's weights give Z = sum w^3 > 2^64, so the draw target's high term is exercised."""
     g, G, ei = medium
     log(f"medium sampling p={p}")
     got = G.sample(1000, p, 10_000_000, seed=1234, with_stats=True)
     want = oracle.sample_heavy_triangles(g.n, g.src, g.dst, g.w, 1000, p, 10_000_000, 1234)
     log(f"  stats {got['stats']}")
+    if p == 3.0:
+        assert sum(int(x) ** 3 for x in np.sort(g.w)[-200000:].tolist()) >= 2**64
     assert got["stats"]["distinct_sampled"] == want["distinct_edges"]
     assert_parity(got, want, p, ei, ctx=f"medium es p={p}")
 

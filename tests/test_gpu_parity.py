@@ -383,8 +383,92 @@ def test_sampling_small_workload(tt, small, p):
         assert got["stats"]["distinct_sampled"] == want["distinct_edges"]
 
 
+def check_draws(gpu_draws, w, p, q, budget, seed, ctx):
+    """Draw for draw against the oracle's replay of Alg. 3.  Integer q: identical.  Other q: the
+    two FP64 prefix sums differ in rounding (the oracle sums in input order, the GPU in blocks),
+    so a draw may differ only where its target lies within 1e-12 Z of the oracle's boundary
+    between the two edges.  Returns the number of draws that differ."""
+    _, want = oracle.es_draw(w, p, budget, seed, return_draws=True, q=q)
+    got = np.asarray(gpu_draws, np.int64)
+    want = want.astype(np.int64)
+    qq = oracle.sample_exponent(p) if q is None else q
+    diff = np.nonzero(got != want)[0]
+    if qq in (1.0, 2.0, 3.0):
+        assert len(diff) == 0, (ctx, diff[:5], got[diff[:5]], want[diff[:5]])
+        return 0
+    P = oracle.es_prefix_f64(w, qq)
+    Z = P[-1]
+    for s in diff.tolist():
+        r = float(oracle.splitmix64(seed, s) >> 11) * 2.0**-53 * Z
+        e = int(got[s])
+        lo = P[e - 1] if e > 0 else 0.0
+        assert P[e] > r - 1e-12 * Z and lo <= r + 1e-12 * Z, (ctx, s, e, int(want[s]), r, lo, P[e])
+    return len(diff)
+
+
+@pytest.mark.parametrize("p,q", [(0.5, None), (1.5, None), (1.0, 1.5), (-1.0, 0.5), (math.inf, 2.5),
+                                 (2.0, 0.75)])
+def test_sampling_noninteger_exponent_with_draws(tt, small, p, q):
+    """Non-integer sampling exponents, the default reading (q = p for finite p > 0) and named q:
+    the GPU's draws are returned and checked against the oracle's replay (FP64 prefix sums,
+    1e-12 of a bucket edge), then the oracle enumerates the triangles on exactly those drawn
+    edges, and the GPU's answer must match it by the parity rule."""
+    g, G = small
+    ei = EdgeIndex(g.src, g.dst, g.w)
+    for budget, seed in ((1000, 4), (200000, 8)):
+        got = G.sample(100, p, budget, seed, q=q, return_draws=True, with_stats=True)
+        nd = check_draws(got["draws"], g.w, p, q, budget, seed, ctx=f"p={p} q={q} budget={budget}")
+        log(f"es p={p} q={q} budget={budget}: {nd} draws on a rounding boundary")
+        mark = np.zeros(g.m, np.uint8)
+        mark[got["draws"].astype(np.int64)] = 1
+        assert got["stats"]["distinct_sampled"] == int(mark.sum())
+        want = oracle.topk(g.n, g.src, g.dst, g.w, 100, p, edge_mark=mark)
+        assert_parity(got, want, p, ei, ctx=f"es on the GPU's draws p={p} q={q}")
+        if nd == 0:  # same draws: the oracle's own replay of the whole query agrees as well
+            ref = oracle.sample_heavy_triangles(g.n, g.src, g.dst, g.w, 100, p, budget, seed, q=q)
+            assert_parity(got, ref, p, ei, ctx=f"es replay p={p} q={q}")
+
+
+def test_sampling_integer_exponent_draws_and_override(tt, small):
+    """Integer q: the returned draws equal the oracle's draw for draw, with q named or implied,
+    and the draws-only call (k = 0) returns the same sequence."""
+    g, G = small
+    ei = EdgeIndex(g.src, g.dst, g.w)
+    for p, q in ((1.0, None), (2.0, None), (3.0, None), (-math.inf, 2.0), (0.0, 3.0), (1.5, 1.0)):
+        got = G.sample(100, p, 50000, 21, q=q, return_draws=True)
+        check_draws(got["draws"], g.w, p, q, 50000, 21, ctx=f"p={p} q={q}")
+        want = oracle.sample_heavy_triangles(g.n, g.src, g.dst, g.w, 100, p, 50000, 21, q=q)
+        assert_parity(got, want, p, ei, ctx=f"es p={p} q={q}")
+        only = G.sample(0, p, 50000, 21, q=q, return_draws=True)
+        assert only["n_out"] == 0 and np.array_equal(only["draws"], got["draws"])
+    for bad in (0.0, -1.0, math.inf):
+        with pytest.raises(tt.TopKError) as e:
+            G.sample(10, 1.0, 100, 1, q=bad)
+        assert e.value.code == tt.TT_E_ARG
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_sampling_draw_target_above_2_64(tt, q):
+    """Weights near 2^32 - 1 make Z = sum w^q exceed 2^64 (q = 2: ~m 2^64; q = 3: ~m 2^96), so the
+    128-bit draw target x * floor(Z / 2^64) + floor(x * (Z mod 2^64) / 2^64) needs both terms.
+    Draw for draw against the oracle, and the sampled top-k."""
+    rng = np.random.default_rng(640 + q)
+    n = 40
+    s, d, _ = rand_graph(rng, n, 0.5)
+    w = rng.integers(2**32 - 100000, 2**32, len(s), dtype=np.uint64).astype(np.uint32)
+    w[rng.choice(len(w), size=len(w) // 3, replace=False)] = rng.integers(1, 1000, len(w) // 3).astype(np.uint32)
+    assert sum(int(x) ** q for x in w.tolist()) >= 2**64
+    ei = EdgeIndex(s, d, w)
+    with tt.Graph(n, s, d, w) as G:
+        for budget, seed in ((7, 1), (300, 2), (20000, 3)):
+            got = G.sample(50, float(q), budget, seed, return_draws=True)
+            check_draws(got["draws"], w, float(q), None, budget, seed, ctx=f"q={q} budget={budget}")
+            want = oracle.sample_heavy_triangles(n, s, d, w, 50, float(q), budget, seed)
+            assert_parity(got, want, float(q), ei, ctx=f"big-w es q={q} budget={budget}")
+
+
 def test_sampling_converges_to_exact(tt, small):
     g, G = small
     exact = G.topk(100, 1.0)
     es = G.sample(100, 1.0, 50_000_000, 11)
-    assert triples(es) == triples(exact)
+    assert triples(es) == triples(exact) and np.array_equal(es["score"], exact["score"])
