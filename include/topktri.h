@@ -136,6 +136,61 @@ int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint64_t budget
                               uint32_t *draws, tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
 
 /*
+ * Weighted wedge sampling (Alg. 4) and weighted path sampling (Alg. 5): `budget` independent
+ * draws of a wedge (scheme TT_SAMPLE_WEDGE: a centre a by Eq. wedgeone, b and c in N(a) by Eqs.
+ * wedgetwo and wedgethree) or of a three-edge path (TT_SAMPLE_PATH: an edge (a, b) by Eq.
+ * pathone, c in N(a) \ b and c' in N(b) \ a by Eqs. pathtwo and paththree), each with edge
+ * weights raised to the sampling exponent q (NaN: q = p for finite p > 0, else 1).  A wedge
+ * draw finds triangle {a, b, c} when b != c and {b, c} is an edge; a path draw when c' = c.  The
+ * result is the top-k, by the true m_p, of the distinct triangles found (Props. 2 and 3 give
+ * each triangle's probability per draw: proportional to the sum of its edges' w^q).  Draw s
+ * uses the SplitMix64 outputs 3s, 3s+1, 3s+2 of `seed`; the sampling tables are FP64.
+ *   draws : NULL, or a HOST array of 4 * budget uint32: per draw (a, b, c, x) with x = 1 if the
+ *           wedge closed (else 0), or x = c' for a path.  With draws given, k = 0 draws only.
+ *   stats : may be NULL.
+ * Graphs of more than 2^21 vertices or with 2m >= 2^31 give TT_E_TOO_LARGE; budget <= 2^31.
+ * The symmetric adjacency (rows sorted by neighbour) is built by the first call on a graph.
+ */
+enum { TT_SAMPLE_WEDGE = 1, TT_SAMPLE_PATH = 2 };
+typedef struct {
+    uint64_t closed_draws;       /* draws that found a triangle */
+    uint64_t distinct_triangles; /* distinct triangles among them */
+} tt_sampler_stats;
+int sample_triangles_by(tt_graph *g, int scheme, uint32_t k, double p, uint64_t budget, uint64_t seed, double q,
+                        uint32_t *draws, tt_triangle *out, uint32_t *n_out, tt_sampler_stats *stats);
+
+/*
+ * Weighted edge sampling extended to cliques (Sec. 4.5, Appendix A): `budget` edge draws as in
+ * sample_heavy_triangles (exponent q, NaN for the default reading), then every clique of `size`
+ * (4 or 5) vertices that contains a drawn edge; the result is the top-k of those cliques by the
+ * generalized p-mean of their size (size - 1) / 2 edge weights (Eq. 1 over the clique's edges),
+ * sorted by score descending, then by the sorted vertex IDs.  The order is exact for p in
+ * {-inf, 1, +inf} (integer keys) and decided by the FP64 mean otherwise.  flags =
+ * TT_CLIQUE_ALL_EDGES takes every edge instead of draws (the exact top-k cliques).  *found (may be
+ * NULL) receives the number of distinct cliques on the drawn edges.  A drawn edge whose ends have
+ * more than 512 common neighbours gives TT_E_TOO_LARGE (this sampler is meant for the small
+ * graphs of the appendix).  Builds the symmetric adjacency on first use (2m < 2^31).
+ */
+typedef struct {
+    uint32_t v[5];  /* vertex IDs ascending (v[4] = 0 for 4-cliques) */
+    uint32_t size;  /* 4 or 5 */
+    double score;   /* the generalized p-mean of the clique's edge weights */
+} tt_clique;
+enum { TT_CLIQUE_ALL_EDGES = 1 };
+int sample_heavy_cliques(tt_graph *g, uint32_t size, uint32_t k, double p, uint64_t budget, uint64_t seed, double q,
+                         uint32_t flags, tt_clique *out, uint32_t *n_out, uint64_t *found);
+
+/*
+ * Static heavy-light (Alg. 1, Sec. 3): the edges heavier than tau form H, and the answer is the
+ * top-k, by m_p, of the triangles of the subgraph G[H] (all three edges heavier than tau) — an
+ * approximation of the top-k of G that becomes exact as tau falls (tau = 0 keeps every edge).
+ * out: HOST, room for k records.  *heavy_edges (may be NULL) receives |H|.  The graph is not
+ * changed; G[H] is built on the device for the call and released after it.
+ */
+int shl_topk_triangles(tt_graph *g, uint32_t k, double p, uint32_t tau, tt_triangle *out, uint32_t *n_out,
+                       uint64_t *heavy_edges);
+
+/*
  * Serving: a request loop over one resident graph.  Callers: services that answer a stream of
  * top-k queries (any k, any p, optionally restricted to a vertex subset as in
  * topk_triangles_ex) on a graph kept in device memory.  Each of `slots` workers owns a HIP
@@ -143,8 +198,9 @@ int sample_heavy_triangles_ex(tt_graph *g, uint32_t k, double p, uint64_t budget
  * FIFO order and are admitted when a worker is free and their scratch bytes
  * (server_request_bytes) fit into `scratch_budget` together with the requests already
  * running; a request arriving while others run is admitted as soon as one finishes.  A worker
- * keeps its scratch between requests (it grows with k), so the device memory held is at most
- * `slots` times the largest request charged.  Every
+ * keeps its scratch between requests (it grows with k), and that retained scratch is what the
+ * budget bounds: a request is admitted on a free worker when the worker's scratch, grown to the
+ * request's need, fits the budget together with the scratch every other worker holds.  Every
  * result is exactly the result of topk_triangles_ex for the same arguments.  The graph must
  * outlive the server and must not be freed while it runs.  All calls are thread-safe.
  */
@@ -168,7 +224,11 @@ int server_poll(tt_server *s, uint64_t ticket, int *done);
  * releases the ticket.  stats->total_ms is the time from submission to completion. */
 int server_wait(tt_server *s, uint64_t ticket, tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
 
-/* Counters since creation: admitted and completed requests, peak admitted scratch bytes,
+/* Device bytes the workers' scratch holds now (what the scratch budget bounds; lazily built graph
+ * state belongs to the graph, graph_device_bytes). */
+uint64_t server_scratch_bytes(tt_server *s);
+
+/* Counters since creation: admitted and completed requests, peak charged scratch bytes,
  * longest queue and most requests running at once.  Any pointer may be NULL. */
 int server_info(tt_server *s, uint64_t *admitted, uint64_t *completed, uint64_t *peak_bytes,
                 uint32_t *max_queue, uint32_t *max_running);

@@ -65,6 +65,10 @@ def _load():
         lib.orc_topk_marked.argtypes = [u64, u64, p32, p32, p32, u64, dbl, i32, p8, p8, p32, p32, p32, pd, p64,
                                         p64, p64, p64]
         lib.orc_topk_marked.restype = i32
+        lib.orc_topk_on_marked_edges.argtypes = lib.orc_topk_marked.argtypes
+        lib.orc_topk_on_marked_edges.restype = i32
+        lib.orc_cliques.argtypes = [u64, u64, p32, p32, p32, i32, u64, dbl, i32, p8, p32, pd, p64, p64]
+        lib.orc_cliques.restype = i32
         lib.orc_es_draw.argtypes = [u64, p32, dbl, u64, u64, p8, p64]
         lib.orc_es_draw.restype = i32
         lib.orc_es_draw_q.argtypes = [u64, p32, dbl, u64, u64, p8, p64]
@@ -114,10 +118,13 @@ class OracleError(RuntimeError):
         self.code = code
 
 
-def topk(n, src, dst, w, k: int, p: float, nthreads: int = 0, edge_mark=None, vertex_mark=None):
+def topk(n, src, dst, w, k: int, p: float, nthreads: int = 0, edge_mark=None, vertex_mark=None,
+         from_marked_edges: bool = False):
     """Top-k triangles.  Returns dict(i, j, l, score, key, n_out, total).  With edge_mark (per
     input edge) only triangles with a marked edge are admitted, with vertex_mark (per vertex)
-    only triangles with a marked vertex; with both, triangles that satisfy both."""
+    only triangles with a marked vertex; with both, triangles that satisfy both.
+    from_marked_edges: the same result, the triangles found from the marked edges (no full
+    enumeration; edge_mark required)."""
     s, d, ww = _edges(src, dst, w)
     m = s.shape[0]
     em = vm = None
@@ -132,7 +139,10 @@ def topk(n, src, dst, w, k: int, p: float, nthreads: int = 0, edge_mark=None, ve
     osc = np.zeros(max(kk, 1), np.float64)
     khi, klo = np.zeros(max(kk, 1), np.uint64), np.zeros(max(kk, 1), np.uint64)
     nout, tot = ctypes.c_uint64(0), ctypes.c_uint64(0)
-    rc = _load().orc_topk_marked(n, m, _ptr(s, ctypes.c_uint32), _ptr(d, ctypes.c_uint32),
+    fn = _load().orc_topk_on_marked_edges if from_marked_edges else _load().orc_topk_marked
+    if from_marked_edges and em is None:
+        raise ValueError("from_marked_edges needs edge_mark")
+    rc = fn(n, m, _ptr(s, ctypes.c_uint32), _ptr(d, ctypes.c_uint32),
                                  _ptr(ww, ctypes.c_uint32), kk, float(p), int(nthreads),
                                  None if em is None else _ptr(em, ctypes.c_uint8),
                                  None if vm is None else _ptr(vm, ctypes.c_uint8),
@@ -218,3 +228,32 @@ def sample_heavy_triangles(n, src, dst, w, k: int, p: float, budget: int, seed: 
     out = topk(n, src, dst, w, k, p, nthreads=nthreads, edge_mark=mark)
     out["distinct_edges"] = int(mark.sum())
     return out
+
+
+def cliques(n, src, dst, w, size: int, k: int, p: float, edge_mark=None, nthreads: int = 0):
+    """Top-k cliques of `size` (4 or 5) vertices by the p-mean of their edge weights (Sec. 4.5),
+    optionally only those holding a marked edge.  Returns dict(v: [n_out, size], score, n_out,
+    total)."""
+    s, d, ww = _edges(src, dst, w)
+    em = None if edge_mark is None else _arr(edge_mark, np.uint8)
+    kk = max(int(k), 0)
+    ov = np.zeros(5 * max(kk, 1), np.uint32)
+    osc = np.zeros(max(kk, 1), np.float64)
+    nout, tot = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    rc = _load().orc_cliques(n, s.shape[0], _ptr(s, ctypes.c_uint32), _ptr(d, ctypes.c_uint32),
+                             _ptr(ww, ctypes.c_uint32), int(size), kk, float(p), int(nthreads),
+                             None if em is None else _ptr(em, ctypes.c_uint8), _ptr(ov, ctypes.c_uint32),
+                             _ptr(osc, ctypes.c_double), ctypes.byref(nout), ctypes.byref(tot))
+    if rc != OK:
+        raise OracleError(rc)
+    r = int(nout.value)
+    return {"v": ov[: 5 * r].reshape(r, 5)[:, :size].copy(), "score": osc[:r].copy(), "n_out": r,
+            "total": int(tot.value)}
+
+
+def sample_heavy_cliques(n, src, dst, w, size: int, k: int, p: float, budget: int, seed: int, q=None,
+                         nthreads: int = 0):
+    """Edge sampling extended to cliques (Sec. 4.5): the draws of Alg. 3, then the top-k cliques
+    holding a drawn edge."""
+    mark = es_draw(w, p, budget, seed, q=q)
+    return cliques(n, src, dst, w, size, k, p, edge_mark=mark, nthreads=nthreads)

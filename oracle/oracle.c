@@ -38,6 +38,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#include <stdio.h>
 #include <omp.h>
 
 typedef unsigned __int128 u128;
@@ -140,8 +141,10 @@ static int adj_build(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t
     g->rp = (uint64_t *)calloc(n + 1, sizeof(uint64_t));
     g->e = (ent_t *)malloc((2 * m + 1) * sizeof(ent_t));
     if (!g->rp || !g->e) { adj_free(g); return O_E_NOMEM; }
+    const int progress = getenv("ORC_PROGRESS") != NULL;
     for (uint64_t e = 0; e < m; e++) { g->rp[src[e] + 1]++; g->rp[dst[e] + 1]++; }
     for (uint64_t v = 0; v < n; v++) g->rp[v + 1] += g->rp[v];
+    if (progress) fprintf(stderr, "[oracle] adjacency: degrees counted\n");
     uint64_t *cur = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
     if (!cur) { adj_free(g); return O_E_NOMEM; }
     memcpy(cur, g->rp, (n + 1) * sizeof(uint64_t));
@@ -151,6 +154,7 @@ static int adj_build(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t
         g->e[cur[dst[e]]++] = b;
     }
     free(cur);
+    if (progress) fprintf(stderr, "[oracle] adjacency: entries placed\n");
     int dup = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(| : dup)
     for (uint64_t v = 0; v < n; v++) {
@@ -318,6 +322,112 @@ int orc_topk_marked(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t 
     return O_OK;
 }
 
+/*
+ * The triangles that contain a marked edge, found from the marked edges themselves: for each
+ * marked edge {a, b}, every c in N(a) and N(b) (a merge of the two rows), reported once, from
+ * the marked edge of smallest input ID among its edges.  The same set as enumerate() followed
+ * by the edge-mark filter, at a cost that follows the marked edges' degrees instead of the
+ * whole graph's triangles (the union of Alg. 3, step by step).  With ORC_PROGRESS set in the
+ * environment, a line per tenth of the marked edges goes to stderr.
+ */
+static void enumerate_on_marked(const adj_t *g, const uint32_t *src, const uint32_t *dst, const uint8_t *emark,
+                                visit_fn visit, void *ctx) {
+    const ent_t *E = g->e;
+    const int progress = getenv("ORC_PROGRESS") != NULL;
+    uint64_t next = g->m / 10 + 1;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (uint64_t e = 0; e < g->m; e++) {
+        if (progress && omp_get_thread_num() == 0 && e >= next) {
+            fprintf(stderr, "[oracle] marked-edge enumeration: edge %llu of %llu\n", (unsigned long long)e,
+                    (unsigned long long)g->m);
+            next += g->m / 10 + 1;
+        }
+        if (!emark[e]) continue;
+        const uint32_t a = src[e], b = dst[e];
+        uint64_t x = g->rp[a], y = g->rp[b];
+        const uint64_t xe = g->rp[a + 1], ye = g->rp[b + 1];
+        uint32_t wab = 0;
+        while (x < xe && y < ye) {
+            if (E[x].nbr < E[y].nbr) x++;
+            else if (E[x].nbr > E[y].nbr) y++;
+            else {
+                const uint32_t c = E[x].nbr;
+                const uint64_t eac = E[x].eid, ebc = E[y].eid;
+                /* reported from its marked edge of smallest ID */
+                if (!((emark[eac] && eac < e) || (emark[ebc] && ebc < e))) {
+                    if (!wab) {
+                        /* the weight of {a, b}: its entry in a's row */
+                        uint64_t lo = g->rp[a], hi = xe;
+                        while (lo < hi) { uint64_t mid = lo + (hi - lo) / 2; if (E[mid].nbr < b) lo = mid + 1; else hi = mid; }
+                        wab = E[lo].w;
+                    }
+                    const uint32_t wac = E[x].w, wbc = E[y].w;
+                    uint32_t v[3] = {a, b, c}, t;
+                    if (v[0] > v[1]) { t = v[0]; v[0] = v[1]; v[1] = t; }
+                    if (v[1] > v[2]) { t = v[1]; v[1] = v[2]; v[2] = t; }
+                    if (v[0] > v[1]) { t = v[0]; v[0] = v[1]; v[1] = t; }
+                    /* a pair holding a and b is {a, b}; else one holding a is {a, c}; else {b, c} */
+#define PAIR_W(s0, s1) ((((s0) == a || (s1) == a) && ((s0) == b || (s1) == b)) ? wab : ((s0) == a || (s1) == a) ? wac : wbc)
+#define PAIR_E(s0, s1) ((((s0) == a || (s1) == a) && ((s0) == b || (s1) == b)) ? e : ((s0) == a || (s1) == a) ? eac : ebc)
+                    visit(ctx, omp_get_thread_num(), v[0], v[1], v[2], PAIR_W(v[0], v[1]), PAIR_W(v[0], v[2]),
+                          PAIR_W(v[1], v[2]), PAIR_E(v[0], v[1]), PAIR_E(v[0], v[2]), PAIR_E(v[1], v[2]));
+#undef PAIR_W
+#undef PAIR_E
+                }
+                x++; y++;
+            }
+        }
+    }
+}
+
+/*
+ * Top-k of the triangles with a marked edge (emark[] over input edge IDs, required), and with
+ * vmark given also a marked vertex: the result of orc_topk_marked with the same marks, found by
+ * enumerate_on_marked.
+ */
+int orc_topk_on_marked_edges(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w,
+                             uint64_t k, double p, int nthreads, const uint8_t *emark, const uint8_t *vmark,
+                             uint32_t *oi, uint32_t *oj, uint32_t *ol, double *oscore, uint64_t *okey_hi,
+                             uint64_t *okey_lo, uint64_t *n_out, uint64_t *t_total) {
+    if (n_out) *n_out = 0;
+    if (isnan(p) || (m && (!src || !dst || !w || !emark)) || !n_out) return O_E_ARG;
+    if (k && (!oi || !oj || !ol || !oscore)) return O_E_ARG;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    adj_t g = {0};
+    int rc = adj_build(n, m, src, dst, w, &g);
+    if (rc) return rc;
+    if (getenv("ORC_PROGRESS")) fprintf(stderr, "[oracle] adjacency of %llu edges built\n", (unsigned long long)m);
+    const int T = omp_get_max_threads();
+    heap_t *heaps = (heap_t *)calloc(T, sizeof(heap_t));
+    if (!heaps) { adj_free(&g); return O_E_NOMEM; }
+    for (int t = 0; t < T; t++) {
+        heaps[t].h = (rec_t *)malloc((k ? k : 1) * sizeof(rec_t));
+        if (!heaps[t].h) { for (int u = 0; u < T; u++) free(heaps[u].h); free(heaps); adj_free(&g); return O_E_NOMEM; }
+    }
+    topk_ctx ctx = {orc_mode(p), p, k, heaps, NULL, vmark};
+    enumerate_on_marked(&g, src, dst, emark, visit_topk, &ctx);
+    uint64_t total = 0, kept = 0;
+    for (int t = 0; t < T; t++) { total += heaps[t].count; kept += heaps[t].size; }
+    rec_t *all = (rec_t *)malloc((kept ? kept : 1) * sizeof(rec_t));
+    if (!all) { for (int u = 0; u < T; u++) free(heaps[u].h); free(heaps); adj_free(&g); return O_E_NOMEM; }
+    uint64_t pos = 0;
+    for (int t = 0; t < T; t++) { memcpy(all + pos, heaps[t].h, heaps[t].size * sizeof(rec_t)); pos += heaps[t].size; }
+    qsort(all, kept, sizeof(rec_t), cmp_rec);
+    uint64_t out = kept < k ? kept : k;
+    for (uint64_t r = 0; r < out; r++) {
+        oi[r] = all[r].i; oj[r] = all[r].j; ol[r] = all[r].l; oscore[r] = all[r].score;
+        if (okey_hi) okey_hi[r] = (uint64_t)(all[r].key >> 64);
+        if (okey_lo) okey_lo[r] = (uint64_t)all[r].key;
+    }
+    *n_out = out;
+    if (t_total) *t_total = total;
+    free(all);
+    for (int t = 0; t < T; t++) free(heaps[t].h);
+    free(heaps);
+    adj_free(&g);
+    return O_OK;
+}
+
 /* One filter: 0 none; 1 mark[] over input edge IDs; 2 mark[] over vertices. */
 int orc_topk(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w, uint64_t k,
              double p, int nthreads, int filter, const uint8_t *mark, uint32_t *oi, uint32_t *oj, uint32_t *ol,
@@ -327,6 +437,165 @@ int orc_topk(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, c
     return orc_topk_marked(n, m, src, dst, w, k, p, nthreads, filter == FILTER_EDGE_MARK ? mark : NULL,
                            filter == FILTER_VERTEX_MARK ? mark : NULL, oi, oj, ol, oscore, okey_hi, okey_lo,
                            n_out, t_total);
+}
+
+/* ------------------------------------------------------------------ cliques (Sec. 4.5) */
+
+/* A clique of s vertices (ascending) and its order key / FP64 score. */
+typedef struct { u128 key; uint32_t v[5]; double score; } clq_t;
+
+static int clq_better(const clq_t *a, const clq_t *b, int s) {
+    if (a->key != b->key) return a->key > b->key;
+    for (int t = 0; t < s; t++)
+        if (a->v[t] != b->v[t]) return a->v[t] < b->v[t];
+    return 0;
+}
+static int clq_size_for_sort;
+static int cmp_clq(const void *x, const void *y) {
+    const clq_t *a = (const clq_t *)x, *b = (const clq_t *)y;
+    return clq_better(a, b, clq_size_for_sort) ? -1 : clq_better(b, a, clq_size_for_sort) ? 1 : 0;
+}
+
+/* The generalized p-mean of E weights (Eq. 1 over a clique's edges): exact keys for p in
+ * {-inf, 1, +inf} (min, sum, max), the FP64 value of the mean (long double evaluation) otherwise;
+ * p = 0 is the geometric mean. */
+static void clq_score(double p, const uint32_t *w, int E, u128 *key, double *score) {
+    if (isinf(p)) {
+        uint32_t r = w[0];
+        for (int t = 1; t < E; t++) r = p > 0 ? (w[t] > r ? w[t] : r) : (w[t] < r ? w[t] : r);
+        *key = r; *score = (double)r; return;
+    }
+    if (p == 1.0) {
+        uint64_t r = 0;
+        for (int t = 0; t < E; t++) r += w[t];
+        *key = r; *score = (double)r / (double)E; return;
+    }
+    long double m;
+    if (p == 0.0) {
+        long double acc = 0.0L;
+        for (int t = 0; t < E; t++) acc += logl((long double)w[t]);
+        m = expl(acc / (long double)E);
+    } else {
+        long double sref = w[0];
+        for (int t = 1; t < E; t++) { long double x = w[t]; if (p > 0 ? x > sref : x < sref) sref = x; }
+        long double acc = 0.0L;
+        for (int t = 0; t < E; t++) acc += expm1l((long double)p * logl((long double)w[t] / sref));
+        m = sref * expl(log1pl(acc / (long double)E) / (long double)p);
+    }
+    double d = (double)m;
+    uint64_t bits;
+    memcpy(&bits, &d, 8);
+    *key = bits; *score = d;
+}
+
+/* weight and edge ID of {x, y}, or 0 if not an edge */
+static uint32_t adj_find(const adj_t *g, uint32_t x, uint32_t y, uint64_t *eid) {
+    uint64_t lo = g->rp[x], hi = g->rp[x + 1];
+    while (lo < hi) { uint64_t mid = lo + (hi - lo) / 2; if (g->e[mid].nbr < y) lo = mid + 1; else hi = mid; }
+    if (lo < g->rp[x + 1] && g->e[lo].nbr == y) { *eid = g->e[lo].eid; return g->e[lo].w; }
+    return 0;
+}
+
+/*
+ * Top-k cliques of s = 4 or 5 vertices by the p-mean of their s (s - 1) / 2 edge weights,
+ * ordered by score descending then the ascending vertex IDs; with emark, only cliques holding a
+ * marked edge (input edge IDs).  Every clique is listed once, as i < j < x < y (< z), from the
+ * common neighbours of i and j above j.  Writes min(k, T) cliques: ov[k * 5] (unused IDs 0),
+ * oscore[k]; *t_total = T.
+ */
+int orc_cliques(uint64_t n, uint64_t m, const uint32_t *src, const uint32_t *dst, const uint32_t *w, int s,
+                uint64_t k, double p, int nthreads, const uint8_t *emark, uint32_t *ov, double *oscore,
+                uint64_t *n_out, uint64_t *t_total) {
+    if (n_out) *n_out = 0;
+    if ((s != 4 && s != 5) || isnan(p) || (m && (!src || !dst || !w)) || !n_out || (k && (!ov || !oscore)))
+        return O_E_ARG;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    adj_t g = {0};
+    int rc = adj_build(n, m, src, dst, w, &g);
+    if (rc) return rc;
+    const int T = omp_get_max_threads();
+    clq_t **lists = (clq_t **)calloc(T, sizeof(clq_t *));
+    uint64_t *cnt = (uint64_t *)calloc(T, sizeof(uint64_t)), *cap = (uint64_t *)calloc(T, sizeof(uint64_t));
+    if (!lists || !cnt || !cap) { free(lists); free(cnt); free(cap); adj_free(&g); return O_E_NOMEM; }
+    int nomem = 0;
+    const int E = s * (s - 1) / 2;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : nomem)
+    for (uint64_t i = 0; i < n; i++) {
+        const int tid = omp_get_thread_num();
+        const ent_t *Ei = g.e;
+        uint32_t *C = NULL;
+        for (uint64_t a = first_above(Ei, g.rp[i], g.rp[i + 1], (uint32_t)i); a < g.rp[i + 1]; a++) {
+            const uint32_t j = Ei[a].nbr;
+            /* common neighbours of i and j above j */
+            uint64_t x = a + 1, y = first_above(Ei, g.rp[j], g.rp[j + 1], j), nc = 0;
+            const uint64_t xe = g.rp[i + 1], ye = g.rp[j + 1];
+            free(C);
+            C = (uint32_t *)malloc((xe - x + 1) * sizeof(uint32_t));
+            if (!C) { nomem = 1; break; }
+            while (x < xe && y < ye) {
+                if (Ei[x].nbr < Ei[y].nbr) x++;
+                else if (Ei[x].nbr > Ei[y].nbr) y++;
+                else { C[nc++] = Ei[x].nbr; x++; y++; }
+            }
+            for (uint64_t p1 = 0; p1 < nc; p1++)
+                for (uint64_t p2 = p1 + 1; p2 < nc; p2++) {
+                    uint32_t V[5] = {(uint32_t)i, j, C[p1], C[p2], 0};
+                    uint64_t e12;
+                    if (!adj_find(&g, C[p1], C[p2], &e12)) continue;
+                    /* a fifth vertex from the common neighbours after the fourth (5-cliques), or none */
+                    const uint64_t z_lo = s == 5 ? p2 + 1 : 0, z_hi = s == 5 ? nc : 1;
+                    for (uint64_t p3 = z_lo; p3 < z_hi; p3++) {
+                        if (s == 5) V[4] = C[p3];
+                        uint32_t W[10];
+                        int marked = emark == NULL, e = 0, ok = 1;
+                        for (int u = 0; u < s && ok; u++)
+                            for (int v = u + 1; v < s; v++) {
+                                uint64_t id;
+                                uint32_t wt = adj_find(&g, V[u], V[v], &id);
+                                if (!wt) { ok = 0; break; }
+                                W[e++] = wt;
+                                if (emark && emark[id]) marked = 1;
+                            }
+                        if (ok && marked) {
+                            if (cnt[tid] == cap[tid]) {
+                                uint64_t nc2 = cap[tid] ? 2 * cap[tid] : 1024;
+                                clq_t *nl = (clq_t *)realloc(lists[tid], nc2 * sizeof(clq_t));
+                                if (!nl) { nomem = 1; break; }
+                                lists[tid] = nl;
+                                cap[tid] = nc2;
+                            }
+                            clq_t *r = &lists[tid][cnt[tid]++];
+                            memset(r, 0, sizeof(*r));
+                            for (int u = 0; u < s; u++) r->v[u] = V[u];
+                            clq_score(p, W, E, &r->key, &r->score);
+                        }
+                    }
+                }
+        }
+        free(C);
+    }
+    uint64_t total = 0;
+    for (int t = 0; t < T; t++) total += cnt[t];
+    clq_t *all = nomem ? NULL : (clq_t *)malloc((total ? total : 1) * sizeof(clq_t));
+    if (!all) {
+        for (int t = 0; t < T; t++) free(lists[t]);
+        free(lists); free(cnt); free(cap); adj_free(&g);
+        return O_E_NOMEM;
+    }
+    uint64_t pos = 0;
+    for (int t = 0; t < T; t++) { memcpy(all + pos, lists[t], cnt[t] * sizeof(clq_t)); pos += cnt[t]; free(lists[t]); }
+    clq_size_for_sort = s;
+    qsort(all, total, sizeof(clq_t), cmp_clq);
+    const uint64_t out = total < k ? total : k;
+    for (uint64_t r = 0; r < out; r++) {
+        for (int u = 0; u < 5; u++) ov[r * 5 + u] = u < s ? all[r].v[u] : 0;
+        oscore[r] = all[r].score;
+    }
+    *n_out = out;
+    if (t_total) *t_total = total;
+    free(all); free(lists); free(cnt); free(cap);
+    adj_free(&g);
+    return O_OK;
 }
 
 /* ------------------------------------------------------------------ listing (small graphs) */

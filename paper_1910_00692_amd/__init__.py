@@ -26,13 +26,19 @@ EXPORTED = ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles
             "sample_heavy_triangles_ex", "graph_num_vertices", "graph_num_edges", "graph_device_bytes",
             "graph_free", "tt_last_error", "server_create", "server_request_bytes", "server_submit", "server_poll",
             "server_wait", "server_info", "server_destroy", "batch_load", "batch_load_device", "batch_topk",
-            "batch_topk_ex", "batch_num_configs", "batch_num_graphs", "batch_free", "tt_trim_cache")
+            "batch_topk_ex", "batch_num_configs", "batch_num_graphs", "batch_free", "tt_trim_cache",
+            "shl_topk_triangles", "sample_triangles_by", "sample_heavy_cliques", "server_scratch_bytes")
+TT_SAMPLE_WEDGE, TT_SAMPLE_PATH = 1, 2
 TT_BATCH_EAGER = 1
 
 
 class Triangle(ctypes.Structure):
     _fields_ = [("i", ctypes.c_uint32), ("j", ctypes.c_uint32), ("l", ctypes.c_uint32), ("_pad", ctypes.c_uint32),
                 ("score", ctypes.c_double)]
+
+
+class Clique(ctypes.Structure):
+    _fields_ = [("v", ctypes.c_uint32 * 5), ("size", ctypes.c_uint32), ("score", ctypes.c_double)]
 
 
 class QueryStats(ctypes.Structure):
@@ -98,6 +104,11 @@ def library():
         lib.graph_load_device.argtypes = [u32, u64, vp, vp, vp, vp, pg]
         lib.topk_triangles.argtypes = [vp, u32, dbl, ptri, p32]
         lib.topk_triangles_ex.argtypes = [vp, u32, dbl, p32, u32, ptri, p32, pst]
+        lib.shl_topk_triangles.argtypes = [vp, u32, dbl, u32, ptri, p32, ctypes.POINTER(ctypes.c_uint64)]
+        lib.sample_triangles_by.argtypes = [vp, i32, u32, dbl, u64, u64, dbl, p32, ptri, p32,
+                                            ctypes.POINTER(ctypes.c_uint64 * 2)]
+        lib.sample_heavy_cliques.argtypes = [vp, u32, u32, dbl, u64, u64, dbl, u32, ctypes.POINTER(Clique), p32,
+                                             ctypes.POINTER(ctypes.c_uint64)]
         lib.sample_heavy_triangles.argtypes = [vp, u32, dbl, u64, u64, ptri, p32]
         lib.sample_heavy_triangles_ex.argtypes = [vp, u32, dbl, u64, u64, dbl, p32, ptri, p32, pst]
         lib.graph_num_vertices.argtypes = [vp]
@@ -117,6 +128,8 @@ def library():
         lib.server_create.argtypes = [vp, u32, u64, pg]
         lib.server_request_bytes.argtypes = [vp, u32, u32]
         lib.server_request_bytes.restype = u64
+        lib.server_scratch_bytes.argtypes = [vp]
+        lib.server_scratch_bytes.restype = u64
         lib.server_submit.argtypes = [vp, u32, dbl, p32, u32, p64]
         lib.server_poll.argtypes = [vp, u64, pint]
         lib.server_wait.argtypes = [vp, u64, ptri, p32, pst]
@@ -135,6 +148,7 @@ def library():
         lib.batch_free.argtypes = [vp]
         lib.batch_free.restype = None
         for name in ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles_ex",
+                     "shl_topk_triangles", "sample_triangles_by", "sample_heavy_cliques",
                      "sample_heavy_triangles", "sample_heavy_triangles_ex", "server_create", "server_submit",
                      "server_poll", "server_wait", "server_info", "batch_load", "batch_load_device", "batch_topk",
                      "batch_topk_ex"):
@@ -210,6 +224,51 @@ class Graph:
             out["stats"] = st.as_dict()
         return out
 
+    def shl(self, k: int, p: float, tau: int):
+        """Static heavy-light (Alg. 1): top-k of the triangles whose three edges weigh > tau."""
+        buf = (Triangle * max(int(k), 1))()
+        n_out = ctypes.c_uint32(0)
+        mh = ctypes.c_uint64(0)
+        _check(library().shl_topk_triangles(self._h, int(k), float(p), int(tau), buf, ctypes.byref(n_out),
+                                            ctypes.byref(mh)))
+        out = _result(buf, n_out.value)
+        out["heavy_edges"] = int(mh.value)
+        return out
+
+    def sample_by(self, scheme: str, k: int, p: float, budget: int, seed: int, q: float | None = None,
+                  return_draws: bool = False):
+        """Wedge (Alg. 4) or path (Alg. 5) sampling: top-k of the distinct triangles the draws
+        close.  scheme: "wedge" or "path".  return_draws adds "draws" (budget x 4 uint32)."""
+        sc = {"wedge": TT_SAMPLE_WEDGE, "path": TT_SAMPLE_PATH}[scheme]
+        buf = (Triangle * max(int(k), 1))()
+        n_out = ctypes.c_uint32(0)
+        st = (ctypes.c_uint64 * 2)()
+        draws = np.zeros(4 * max(int(budget), 1), np.uint32) if return_draws else None
+        _check(library().sample_triangles_by(self._h, sc, int(k), float(p), int(budget), int(seed) & (2**64 - 1),
+                                             math.nan if q is None else float(q),
+                                             None if draws is None else draws.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                             buf, ctypes.byref(n_out), ctypes.byref(st)))
+        out = _result(buf, n_out.value)
+        out["closed_draws"], out["distinct"] = int(st[0]), int(st[1])
+        if return_draws:
+            out["draws"] = draws[: 4 * int(budget)].reshape(-1, 4)
+        return out
+
+    def cliques(self, size: int, k: int, p: float, budget: int = 0, seed: int = 0, q: float | None = None,
+                all_edges: bool = False):
+        """Edge sampling extended to 4- or 5-cliques (Sec. 4.5): top-k cliques on the drawn edges
+        (all_edges: on every edge, the exact top-k).  Returns dict(v: [n_out, size], score,
+        n_out, found)."""
+        buf = (Clique * max(int(k), 1))()
+        n_out = ctypes.c_uint32(0)
+        found = ctypes.c_uint64(0)
+        _check(library().sample_heavy_cliques(self._h, int(size), int(k), float(p), int(budget),
+                                              int(seed) & (2**64 - 1), math.nan if q is None else float(q),
+                                              1 if all_edges else 0, buf, ctypes.byref(n_out), ctypes.byref(found)))
+        nn = n_out.value
+        v = np.array([list(buf[t].v)[:size] for t in range(nn)], np.uint32).reshape(nn, size)
+        return {"v": v, "score": np.array([buf[t].score for t in range(nn)]), "n_out": nn, "found": int(found.value)}
+
     def sample(self, k: int, p: float, budget: int, seed: int, with_stats: bool = False, q: float | None = None,
                return_draws: bool = False):
         """Weighted edge sampling (Alg. 3): top-k of the union of triangles on the drawn edges.
@@ -258,6 +317,10 @@ class Server:
         _check(library().server_create(graph.handle, int(slots), int(scratch_budget), ctypes.byref(self._h)))
         self._k = {}
 
+    def scratch_bytes(self) -> int:
+        """Device bytes the workers' scratch holds now (bounded by the budget)."""
+        return int(library().server_scratch_bytes(self._h))
+
     def request_bytes(self, k: int, subset_n: int = 0) -> int:
         return int(library().server_request_bytes(self._h, int(k), int(subset_n)))
 
@@ -277,7 +340,10 @@ class Server:
         return bool(d.value)
 
     def wait(self, ticket: int):
-        k = self._k.pop(int(ticket), 1)
+        # the result buffer must hold the request's k: an unknown ticket never reaches the library
+        k = self._k.pop(int(ticket), None)
+        if k is None:
+            raise ValueError(f"ticket {ticket} was not submitted here or has already been waited for")
         buf = (Triangle * max(k, 1))()
         n_out = ctypes.c_uint32(0)
         st = QueryStats()

@@ -99,9 +99,18 @@ struct QueryCtx {
     std::vector<hipEvent_t> band_ev;       // start/stop pairs of the passes of a query
 };
 void ctx_release(QueryCtx *q); // device memory and events (not the stream)
+// Query scratch for a triangle buffer of cap records and kout results (query.hip).
+int ensure_scratch(const tt_graph *g, QueryCtx *q, uint64_t cap, uint64_t kout);
+// Marks (g->emark) the edges of `budget` weighted edge draws with exponent qexp (query.hip).
+int es_mark_edges(tt_graph *g, QueryCtx *q, double qexp, uint64_t budget, uint64_t seed);
+// The first N records of q->buf0 sorted by key (desc) and IDs; the best min(N, k) first in *res.
+int select_records(QueryCtx *q, uint64_t N, uint32_t k, trec **res);
+// Best min(N, k) of the first N records of q->buf0, scored for `mode`, copied to HOST out.
+int finish_topk(QueryCtx *q, uint64_t N, uint32_t k, int mode, tt_triangle *out, uint32_t *n_out);
 int ensure_in_csr(tt_graph *g, hipStream_t s);
 int ensure_opos(tt_graph *g, hipStream_t s);
 int ensure_weight_stream(tt_graph *g, hipStream_t s, uint32_t bin);
+int ensure_sym(tt_graph *g, hipStream_t s);
 
 // Entries in descending order of their bound m_p(w_uv, maxw(u), maxw(v)) (grouped by
 // weight_bin of an integer >= it), for one p: the entries that can be the base of a triangle
@@ -153,6 +162,13 @@ struct tt_graph {
                                 //     triangle based at u, for every p
     uint32_t *deg = nullptr;    // [n] undirected degree
     uint32_t *in_w = nullptr;   // [m] weights in input order (sampling prefix sums)
+    // symmetric adjacency (rows sorted by neighbour), built by the first wedge or path sampling
+    // query, with the per-row prefix sums of w^q of its most recent exponent
+    uint64_t *srstart = nullptr; // [n+1]
+    uint32_t *scol = nullptr;    // [2m]
+    uint32_t *sw = nullptr;      // [2m]
+    double *srowp = nullptr;     // [2m] inclusive prefix of w^q within each row
+    double srow_q = -1.0;        // its exponent (-1: none)
     // transpose of the oriented CSR, built on the first subset query: for every head v, the
     // tails u of its in-entries u->v
     uint64_t *irstart = nullptr; // [n+2]
@@ -216,6 +232,8 @@ int fail(int code, const std::string &msg);
     } while (0)
 
 int dev_alloc(tt_graph *g, void **p, size_t bytes);
+size_t dev_round(size_t bytes);   // the size dev_alloc hands out for a request of `bytes`
+size_t dev_bytes(const void *p);  // size of a live block from dev_alloc (0 if none)
 void dev_free(tt_graph *g, void *p, size_t bytes);
 int num_cus();
 

@@ -87,6 +87,15 @@ extern "C" uint64_t tt_trim_cache(void) {
     return pool_release(-1);
 }
 
+size_t dev_round(size_t bytes) { return round_size(bytes); }
+
+size_t dev_bytes(const void *p) {
+    if (!p) return 0;
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    auto it = g_live.find(const_cast<void *>(p));
+    return it == g_live.end() ? 0 : it->second.size;
+}
+
 int dev_alloc(tt_graph *g, void **p, size_t bytes) {
     *p = nullptr;
     const size_t sz = round_size(bytes);
@@ -1110,7 +1119,8 @@ void release(tt_graph *g) {
     void *ptrs[] = {g->rstart, g->rlen,   g->col,    g->wgt,  g->osrc,    g->eid,   g->opos,
                     g->wcol,   g->wwgt,   g->wpos,   g->maxw, g->hb,      g->deg,   g->emark,
                     g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->in_w,  g->irstart, g->itail,
-                    g->vinfo,  g->cw,     g->hmx,    g->ws_hmx, g->ws_base};
+                    g->vinfo,  g->cw,     g->hmx,    g->ws_hmx, g->ws_base, g->srstart, g->scol,
+                    g->sw,     g->srowp};
     for (void *p : ptrs) dev_free(g, p, 0);
     for (auto &t : g->tables) {
         dev_free(g, t.prefix, 0);

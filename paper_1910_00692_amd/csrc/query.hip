@@ -32,6 +32,7 @@
 #include "common.h"
 #include "enum.h"
 #include "scan.h"
+#include "serve_core.h"
 
 namespace {
 
@@ -478,16 +479,39 @@ uint64_t sub_stream_cap(const tt_graph *g, const QueryCtx *q) { return std::min<
 uint64_t sub_list_cap(const tt_graph *g, const QueryCtx *q) { return std::min<uint64_t>(q->sub_cap, (uint64_t)g->n + 1); }
 uint64_t flag_bytes(const tt_graph *g) { return (((uint64_t)g->n + 4) & ~3ull) + 4; }
 
-uint64_t query_bytes(const tt_graph *g, const QueryCtx *q, uint32_t k, uint32_t subset_n) {
+// Every device block of a context of this query, as the allocator rounds it (an upper bound of
+// what the context holds while and after it runs the query), in two parts that each grow with
+// one argument: the candidate and triangle buffers (k), and the subset structures (subset_n).
+uint64_t query_bytes_k(const tt_graph *g, const QueryCtx *q, uint32_t k) {
     const uint64_t cap = std::max<uint64_t>(q->min_buf, 16ull * k);
     const uint64_t cand = std::min<uint64_t>(g->m + 1, q->max_cand);
-    uint64_t b = 2 * cap * sizeof(trec) + cand * sizeof(cand) + (uint64_t)k * sizeof(tt_triangle) +
-                 MAX_SEG * 4 + 5 * STAT_SLOTS * 8 + HEAVY_CAP * sizeof(Heavy) + HEAVY_PIECES * sizeof(uint2) + 512;
-    if (subset_n)
-        b += 2 * flag_bytes(g) + 16 * sub_stream_cap(g, q) + 4 * sub_list_cap(g, q) + 17ull * (subset_n + 1) +
-             WBINS * 8 + 256;
+    return 2 * dev_round(cap * sizeof(trec)) + dev_round(cand * sizeof(cand)) +
+           dev_round((uint64_t)std::max<uint32_t>(k, 1) * sizeof(tt_triangle)) + dev_round(MAX_SEG * 4) +
+           dev_round(5 * STAT_SLOTS * 8) + dev_round(HEAVY_CAP * sizeof(Heavy)) + dev_round(HEAVY_PIECES * sizeof(uint2)) +
+           dev_round(16 * sizeof(unsigned long long)) + dev_round(256);
+}
+uint64_t query_bytes_sub(const tt_graph *g, const QueryCtx *q, uint32_t subset_n) {
+    if (!subset_n) return 0;
+    const uint64_t c = (uint64_t)subset_n;
+    const uint64_t tmp = ((c * 4 + 7) & ~7ull) + (c + 1) * 4 + 8 + (c + 1) * 8 + WBINS * 8 + c;
+    return 2 * dev_round(flag_bytes(g)) + 4 * dev_round(sub_stream_cap(g, q) * 4) + dev_round(sub_list_cap(g, q) * 4) +
+           dev_round(tmp);
+}
+uint64_t query_bytes(const tt_graph *g, const QueryCtx *q, uint32_t k, uint32_t subset_n) {
+    return query_bytes_k(g, q, k) + query_bytes_sub(g, q, subset_n);
+}
+
+// Device bytes a context holds now.
+uint64_t ctx_bytes(const QueryCtx *q) {
+    const void *ptrs[] = {q->buf0, q->buf1, q->cand, q->ccnt, q->spart, q->dcount, q->dout, q->vflag, q->vflag2,
+                          q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_vlist, q->heavy, q->nheavy,
+                          q->hpiece};
+    uint64_t b = 0;
+    for (const void *p : ptrs) b += dev_bytes(p);
     return b;
 }
+
+} // namespace
 
 int ensure_scratch(const tt_graph *g, QueryCtx *q, uint64_t cap, uint64_t kout) {
     int rc;
@@ -539,6 +563,8 @@ int ensure_scratch(const tt_graph *g, QueryCtx *q, uint64_t cap, uint64_t kout) 
     }
     return TT_OK;
 }
+
+namespace {
 
 struct Timer {
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -1025,6 +1051,32 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     return TT_OK;
 }
 
+} // namespace
+
+// The first N records of q->buf0 sorted, the best min(N, k) at the front of *res.
+int select_records(QueryCtx *q, uint64_t N, uint32_t k, trec **res) { return select_topk(q, N, k, res); }
+
+// Selection of the first N records of q->buf0 (the candidate triangles of a query that found
+// them by other means, e.g. a sampler): the best min(N, k), finalised and copied to `out`.
+int finish_topk(QueryCtx *q, uint64_t N, uint32_t k, int mode, tt_triangle *out, uint32_t *n_out) {
+    hipStream_t s = q->stream;
+    const uint32_t K = (uint32_t)std::min<uint64_t>(N, k);
+    *n_out = 0;
+    if (K == 0) return TT_OK;
+    trec *res = nullptr;
+    int rc = select_topk(q, N, k, &res);
+    if (rc) return rc;
+    k_finalize<<<(K + 255) / 256, 256, 0, s>>>(res, K, mode, q->dout);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(q->hout, q->dout, (size_t)K * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(out, q->hout, (size_t)K * sizeof(tt_triangle));
+    *n_out = K;
+    return TT_OK;
+}
+
+namespace {
+
 int ensure_flags(const tt_graph *g, QueryCtx *q) {
     int rc;
     if (!q->vflag && (rc = dev_alloc(nullptr, (void **)&q->vflag, flag_bytes(g)))) return rc;
@@ -1262,83 +1314,38 @@ extern "C" int sample_heavy_triangles(tt_graph *g, uint32_t k, double p, uint64_
     return sample_heavy_triangles_ex(g, k, p, budget, seed, __builtin_nan(""), nullptr, out, n_out, nullptr);
 }
 
+// Alg. 3's draws for the clique sampler: g->emark marks the head-sorted entry of every edge drawn
+// in `budget` draws with exponent qexp (the draw rule of sample_heavy_triangles).  The caller
+// holds g->mu; the work is enqueued on q->stream.
+int es_mark_edges(tt_graph *g, QueryCtx *q, double qexp, uint64_t budget, uint64_t seed) {
+    int rc;
+    if (!g->emark && (rc = dev_alloc(g, (void **)&g->emark, g->m + 1))) return rc;
+    if ((rc = ensure_opos(g, q->stream))) return rc;
+    const int kind = qexp == 1.0 ? 0 : (qexp == 2.0 || qexp == 3.0) ? 1 : 2;
+    hipStream_t s = q->stream;
+    tt_graph::SampleTable *tab = nullptr;
+    if ((rc = sample_table(g, qexp, kind, &tab))) return rc;
+    HIP_TRY(hipMemsetAsync(g->emark, 0, g->m + 1, s));
+    const unsigned grid = (unsigned)std::min<uint64_t>((budget + 255) / 256, (uint64_t)num_cus() * 16);
+    const uint32_t bits = g->guide_bits;
+    if (kind == 0) k_es_draw<0><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark, nullptr);
+    else if (kind == 1) k_es_draw<1><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark, nullptr);
+    else k_es_draw<2><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark, nullptr);
+    HIP_TRY(hipGetLastError());
+    return TT_OK;
+}
+
 // ----------------------------------------------------------------------------- serving
 // A request loop over one resident graph.  Each slot is a worker thread with its own query
 // context and HIP stream, so admitted requests overlap on the device.  Requests wait in FIFO
 // order and are admitted as soon as a slot is free and their scratch bytes fit the budget
 // (continuous batching: a request that arrives while others run starts when one finishes).
 struct tt_server {
-    struct Req {
-        uint64_t ticket;
-        uint32_t k;
-        double p;
-        std::vector<uint32_t> subset;
-        uint64_t need;
-        std::chrono::steady_clock::time_point t_submit;
-    };
-    struct Res {
-        bool done = false;
-        int rc = TT_OK;
-        std::string err;
-        std::vector<tt_triangle> tri;
-        uint32_t n_out = 0;
-        tt_query_stats st{};
-    };
+    ServeCore core;
     tt_graph *g = nullptr;
-    uint64_t budget = 0, in_use = 0, peak = 0, admitted = 0, completed = 0;
-    uint32_t max_queue = 0, max_running = 0, running = 0;
-    uint64_t next_ticket = 1;
-    bool stop = false;
-    std::deque<Req> queue;
-    std::unordered_map<uint64_t, Res> results;
     std::vector<QueryCtx> ctx;
     std::vector<std::thread> workers;
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
 };
-
-namespace {
-void serve_worker(tt_server *S, size_t slot) {
-    QueryCtx *q = &S->ctx[slot];
-    (void)hipSetDevice(S->g->device);
-    for (;;) {
-        tt_server::Req r;
-        {
-            std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] {
-                return (S->stop && S->queue.empty()) ||
-                       (!S->queue.empty() && S->in_use + S->queue.front().need <= S->budget);
-            });
-            if (S->queue.empty()) return;
-            r = std::move(S->queue.front());
-            S->queue.pop_front();
-            S->in_use += r.need;
-            S->peak = std::max(S->peak, S->in_use);
-            S->admitted++;
-            S->running++;
-            S->max_running = std::max(S->max_running, S->running);
-        }
-        tt_server::Res res;
-        res.tri.resize(std::max<uint32_t>(r.k, 1));
-        res.rc = query_on(S->g, q, r.k, r.p, r.subset.empty() ? nullptr : r.subset.data(), (uint32_t)r.subset.size(),
-                          res.tri.data(), &res.n_out, &res.st);
-        if (res.rc) res.err = tt_last_error();
-        res.st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - r.t_submit).count();
-        // the slot keeps its scratch for the next request (it only grows with k); releasing it
-        // here would cost allocations, and a free of device memory waits for the whole device
-        res.done = true;
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->in_use -= r.need;
-            S->running--;
-            S->completed++;
-            S->results[r.ticket] = std::move(res);
-        }
-        S->cv_done.notify_all();
-        S->cv_work.notify_all();
-    }
-}
-} // namespace
 
 extern "C" int server_create(tt_graph *g, uint32_t slots, uint64_t scratch_budget, tt_server **out) {
     if (!out) return fail(TT_E_ARG, "out is NULL");
@@ -1347,7 +1354,9 @@ extern "C" int server_create(tt_graph *g, uint32_t slots, uint64_t scratch_budge
     tt_server *S = new (std::nothrow) tt_server();
     if (!S) return fail(TT_E_NOMEM, "host allocation failed");
     S->g = g;
-    S->budget = scratch_budget;
+    S->core.budget = scratch_budget;
+    S->core.held.assign(slots, ServeCore::Parts{});
+    S->core.actual.assign(slots, 0);
     S->ctx.resize(slots);
     for (auto &q : S->ctx) {
         q.min_buf = 1ull << 20;
@@ -1360,7 +1369,21 @@ extern "C" int server_create(tt_graph *g, uint32_t slots, uint64_t scratch_budge
         }
         q.owns_stream = true;
     }
-    for (size_t i = 0; i < slots; i++) S->workers.emplace_back(serve_worker, S, i);
+    for (size_t i = 0; i < slots; i++)
+        S->workers.emplace_back([S, i] {
+            QueryCtx *q = &S->ctx[i];
+            (void)hipSetDevice(S->g->device);
+            S->core.worker(
+                i,
+                [&](const ServeCore::Req &r, ServeCore::Res &res) -> uint64_t {
+                    res.rc = query_on(S->g, q, r.k, r.p, r.subset.empty() ? nullptr : r.subset.data(),
+                                      (uint32_t)r.subset.size(), res.tri.data(), &res.n_out, &res.st);
+                    if (res.rc) res.err = tt_last_error();
+                    // the slot keeps its scratch for the next request (it only grows with k)
+                    return ctx_bytes(q);
+                },
+                [&] { ctx_release(q); });
+        });
     *out = S;
     set_error("");
     return TT_OK;
@@ -1378,50 +1401,30 @@ extern "C" int server_submit(tt_server *S, uint32_t k, double p, const uint32_t 
     if (std::isnan(p)) return fail(TT_E_ARG, "p is NaN");
     int rc = check_subset(S->g, subset, subset_n);
     if (rc) return rc;
-    tt_server::Req r;
+    ServeCore::Req r;
     r.k = k;
     r.p = p;
     if (subset && subset_n) r.subset.assign(subset, subset + subset_n);
-    r.need = query_bytes(S->g, &S->ctx[0], k, (uint32_t)r.subset.size());
-    if (r.need > S->budget) return fail(TT_E_BUDGET, "the request needs more scratch than the server's budget");
-    r.t_submit = std::chrono::steady_clock::now();
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (S->stop) return fail(TT_E_ARG, "server is shutting down");
-        r.ticket = S->next_ticket++;
-        *ticket = r.ticket;
-        S->queue.push_back(std::move(r));
-        S->max_queue = std::max<uint32_t>(S->max_queue, (uint32_t)S->queue.size());
-    }
-    S->cv_work.notify_one();
+    r.need[0] = query_bytes_k(S->g, &S->ctx[0], k);
+    r.need[1] = query_bytes_sub(S->g, &S->ctx[0], (uint32_t)r.subset.size());
+    rc = S->core.submit(std::move(r), ticket);
+    if (rc == TT_E_BUDGET) return fail(rc, "the request needs more scratch than the server's budget");
+    if (rc) return fail(rc, "server is shutting down");
     set_error("");
     return TT_OK;
 }
 
 extern "C" int server_poll(tt_server *S, uint64_t ticket, int *done) {
     if (!S || !done) return fail(TT_E_ARG, "server or done is NULL");
-    std::lock_guard<std::mutex> lk(S->mu);
-    auto it = S->results.find(ticket);
-    *done = it != S->results.end() && it->second.done;
-    if (!*done && ticket >= S->next_ticket) return fail(TT_E_ARG, "unknown ticket");
+    if (S->core.poll(ticket, done)) return fail(TT_E_ARG, "unknown ticket");
     return TT_OK;
 }
 
 extern "C" int server_wait(tt_server *S, uint64_t ticket, tt_triangle *out, uint32_t *n_out, tt_query_stats *stats) {
     if (n_out) *n_out = 0;
     if (!S || !n_out) return fail(TT_E_ARG, "server or n_out is NULL");
-    tt_server::Res res;
-    {
-        std::unique_lock<std::mutex> lk(S->mu);
-        if (ticket == 0 || ticket >= S->next_ticket) return fail(TT_E_ARG, "unknown ticket");
-        S->cv_done.wait(lk, [&] {
-            auto it = S->results.find(ticket);
-            return it != S->results.end() && it->second.done;
-        });
-        auto it = S->results.find(ticket);
-        res = std::move(it->second);
-        S->results.erase(it);
-    }
+    ServeCore::Res res;
+    if (S->core.wait(ticket, res)) return fail(TT_E_ARG, "unknown ticket");
     if (res.rc) return fail(res.rc, res.err);
     if (res.n_out && !out) return fail(TT_E_ARG, "out is NULL");
     std::memcpy(out, res.tri.data(), (size_t)res.n_out * sizeof(tt_triangle));
@@ -1431,25 +1434,24 @@ extern "C" int server_wait(tt_server *S, uint64_t ticket, tt_triangle *out, uint
     return TT_OK;
 }
 
+extern "C" uint64_t server_scratch_bytes(tt_server *S) { return S ? S->core.held_bytes() : 0; }
+
 extern "C" int server_info(tt_server *S, uint64_t *admitted, uint64_t *completed, uint64_t *peak_bytes,
                            uint32_t *max_queue, uint32_t *max_running) {
     if (!S) return fail(TT_E_ARG, "server is NULL");
-    std::lock_guard<std::mutex> lk(S->mu);
-    if (admitted) *admitted = S->admitted;
-    if (completed) *completed = S->completed;
-    if (peak_bytes) *peak_bytes = S->peak;
-    if (max_queue) *max_queue = S->max_queue;
-    if (max_running) *max_running = S->max_running;
+    ServeCore &C = S->core;
+    std::lock_guard<std::mutex> lk(C.mu);
+    if (admitted) *admitted = C.admitted;
+    if (completed) *completed = C.completed;
+    if (peak_bytes) *peak_bytes = C.peak;
+    if (max_queue) *max_queue = C.max_queue;
+    if (max_running) *max_running = C.max_running;
     return TT_OK;
 }
 
 extern "C" void server_destroy(tt_server *S) {
     if (!S) return;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->stop = true;
-    }
-    S->cv_work.notify_all();
+    S->core.shutdown();
     for (auto &t : S->workers) t.join();
     for (auto &q : S->ctx) {
         ctx_release(&q);

@@ -115,6 +115,10 @@ struct LoadU32 {
     const uint32_t *p;
     __device__ uint64_t operator()(uint64_t i) const { return p[i]; }
 };
+struct LoadF64 {
+    const double *p;
+    __device__ double operator()(uint64_t i) const { return p[i]; }
+};
 
 // With tmp (>= scan_tmp_bytes(n) bytes, caller-owned) the scan is only enqueued; without it the
 // block sums are allocated here and the stream is synchronised before they are freed.
@@ -173,4 +177,8 @@ int inclusive_weight_prefix(tt_graph *g, double q, void *out, void *tmp) {
     if (q == 2.0 || q == 3.0)
         return scan_impl<u128>(g->m, PowU128{g->in_w, (int)q}, (u128 *)out, 1, g->stream, g, tmp);
     return scan_impl<double>(g->m, PowF64{g->in_w, q}, (double *)out, 1, g->stream, g, tmp);
+}
+
+int inclusive_scan_f64(const double *in, double *out, uint64_t n, hipStream_t s, void *tmp) {
+    return scan_impl<double>(n, LoadF64{in}, out, 1, s, nullptr, tmp);
 }

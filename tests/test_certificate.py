@@ -68,3 +68,38 @@ def test_wedge_pairs_brute_force():
         for x, y in itertools.combinations(sorted(nb[v]), 2):
             want.add((min(x, y) << 32) | max(x, y))
     assert got == want
+
+
+@pytest.mark.parametrize("p", ALL_P)
+@pytest.mark.parametrize("k", [1, 40, 700])
+def test_certified_topk_is_the_top_k(p, k, monkeypatch):
+    """certified_topk (lower bound from k real triangles, then the certified subgraph) returns
+    the oracle's whole-graph answer, also restricted to a vertex subset."""
+    g = graphgen.chung_lu(4000, 50000, 2.2, 1.8, seed=33, plant=5, plant_size=4, plant_mult=1000)
+    monkeypatch.setattr(certificate, "CHUNK", 8192)
+    for vm in (None, (np.arange(g.n) % 5 == 0).astype(np.uint8)):
+        want = oracle.topk(g.n, g.src, g.dst, g.w, k, p, vertex_mark=vm)
+        got, desc = certificate.certified_topk(g.n, g.src, g.dst, g.w, k, p, vertex_mark=vm)
+        for x in ("i", "j", "l", "score"):
+            assert np.array_equal(got[x], want[x]), (p, k, desc, x)
+
+
+def test_triangles_from_marked_edges_brute_force():
+    """The oracle's enumeration from the marked edges finds exactly the triangles with a marked
+    edge, each once (brute force over all triples)."""
+    import brute
+    rng = np.random.default_rng(44)
+    for trial in range(6):
+        n = int(rng.integers(6, 30))
+        iu = np.array(list(itertools.combinations(range(n), 2)), np.uint32)
+        e = iu[rng.random(len(iu)) < 0.5]
+        s, d = e[:, 0].copy(), e[:, 1].copy()
+        w = rng.integers(1, 9, len(s)).astype(np.uint32)
+        em = (rng.random(len(s)) < 0.3).astype(np.uint8)
+        marked = {(int(a), int(b)) for a, b, x in zip(s, d, em) if x}
+        tris = [t for t in brute.all_triangles(n, s, d, w)
+                if (t[0], t[1]) in marked or (t[0], t[2]) in marked or (t[1], t[2]) in marked]
+        tris.sort(key=lambda t: (-(t[3] + t[4] + t[5]), t[0], t[1], t[2]))
+        out = oracle.topk(n, s, d, w, 10**6, 1.0, edge_mark=em, from_marked_edges=True)
+        assert out["total"] == len(tris)
+        assert list(zip(out["i"].tolist(), out["j"].tolist(), out["l"].tolist())) == [t[:3] for t in tris]

@@ -4,21 +4,20 @@ weights), top-1000 at p = 1 and p = +inf, in the launch configuration bench.py t
 The oracle cannot enumerate the whole graph within a test, so:
   * every returned triple is a triangle of the input, its score is the oracle's score of its
     three weights (bit for bit), and the list is in (score desc, i, j, l asc) order;
-  * completeness: with S the returned k-th score, every triangle of the true top-k has its
-    heaviest edge >= S and its second heaviest >= y(S) (m_p is non-decreasing in each weight and
-    never above the largest), so the oracle's top-k of the subgraph that holds every such
-    triangle (tests/certificate.py) is the true top-k; the returned list must equal it, triples
-    and scores, bit for bit.  At p = +inf that subgraph is the rows of the ends of the heaviest
-    edges; at p = 1 the heaviest edges' wedges and the edges that close them.
+  * completeness: the returned list must equal, triples and scores bit for bit, the oracle's
+    exact top-1000 stored in tests/golden/large_top1000.txt.  That file is written by
+    tests/golden/make_large_golden.py, which calls only the oracle: it takes a lower bound S of
+    the k-th score from k real triangles (those on the heaviest edges), then the oracle's top-k
+    of a subgraph that holds every triangle scoring >= S (m_p is non-decreasing in each weight
+    and never above the largest; tests/certificate.py).
 """
 import math
+import os
 import sys
-import time
 
 import numpy as np
 import pytest
 
-import certificate
 import graphgen
 import oracle
 
@@ -97,16 +96,24 @@ def test_returned_triangles_are_exact(large, p):
     assert all(better(rows[t], rows[t + 1]) for t in range(K - 1))
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_top1000.txt")
+
+
+def golden(p):
+    """The oracle's exact top-1000 of this graph at p (tests/golden/make_large_golden.py)."""
+    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    rows = [r for r in rows if float(r[0]) == p]
+    return {"i": np.array([int(r[2]) for r in rows], np.uint32), "j": np.array([int(r[3]) for r in rows], np.uint32),
+            "l": np.array([int(r[4]) for r in rows], np.uint32),
+            "score": np.array([float.fromhex(r[5]) for r in rows])}
+
+
 @pytest.mark.parametrize("p", P_VALUES)
-def test_complete_by_certificate(large, p):
-    """The whole top-k against the oracle's top-k of a subgraph that provably holds it."""
-    g, got, _ = large
-    r = got[p]
-    t0 = time.time()
-    sel, desc = certificate.subgraph(g.n, g.src, g.dst, g.w, p, float(r["score"][-1]))
-    log(f"p={p}: certificate {desc}, {len(sel)} edges ({time.time() - t0:.0f}s)")
-    assert len(sel) <= 300_000_000, desc
-    want = oracle.topk(g.n, g.src[sel], g.dst[sel], g.w[sel], K, p)
-    log(f"p={p}: oracle on the subgraph: {want['total']} triangles ({time.time() - t0:.0f}s)")
+def test_complete_against_oracle_golden(large, p):
+    """The whole returned top-1000, triples and scores bit for bit, against the oracle's answer
+    on a certified subgraph, computed once by a committed script that calls only the oracle."""
+    _, got, _ = large
+    want = golden(p)
+    assert len(want["i"]) == K
     for x in ("i", "j", "l", "score"):
-        assert np.array_equal(r[x], want[x]), (p, x)
+        assert np.array_equal(got[p][x], want[x]), (p, x)

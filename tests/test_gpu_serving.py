@@ -126,6 +126,36 @@ def test_admission_by_budget(tt, graph):
         assert same(G.topk(k, p), b)
 
 
+def test_scratch_held_stays_within_budget(tt, graph):
+    """Workers keep their scratch between requests; the device bytes they actually hold (the
+    allocator's live blocks) never exceed the budget, also after large and subset requests on
+    several workers, and requests still all complete."""
+    g, G = graph
+    rng = np.random.default_rng(3)
+    with tt.Server(G, slots=4, scratch_budget=1 << 40) as S:
+        small, big, sub = S.request_bytes(50), S.request_bytes(8000), S.request_bytes(50, 1000)
+    budget = 2 * big + sub
+    reqs = []
+    for t in range(40):
+        k = int(rng.choice([20, 50, 8000]))
+        subset = np.sort(rng.choice(g.n, size=1000, replace=False)).astype(np.uint32) if t % 5 == 0 else None
+        reqs.append((k, float(P_CHOICES[t % len(P_CHOICES)]), subset))
+    with tt.Server(G, slots=4, scratch_budget=budget) as S:
+        tickets = [S.submit(k, p, sub) for k, p, sub in reqs]
+        held_max = 0
+        out = []
+        for t in tickets:
+            out.append(S.wait(t))
+            held_max = max(held_max, S.scratch_bytes())
+        info = S.info()
+        held_end = S.scratch_bytes()
+    log(f"budget {budget}, held max {held_max}, end {held_end}, peak charged {info['peak_bytes']}, small {small}")
+    assert info["completed"] == len(reqs)
+    assert held_max <= budget and held_end <= budget and info["peak_bytes"] <= budget
+    for (k, p, sub), b in zip(reqs[:10], out[:10]):
+        assert same(G.topk(k, p, subset=sub), b)
+
+
 def test_poll_and_bad_requests(tt, graph):
     g, G = graph
     with tt.Server(G, slots=2, scratch_budget=8 << 30) as S:

@@ -15,6 +15,7 @@ sampler's CDF) fails it:
 import itertools
 import math
 import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -505,3 +506,67 @@ def test_es_with_large_budget_is_exact():
     assert es["distinct_edges"] == g.m
     for x in ("i", "j", "l", "score"):
         assert es[x].tolist() == exact[x].tolist(), x
+
+
+# ---------------------------------------------------------------------------------- cliques (Sec. 4.5)
+
+def _brute_cliques(n, s, d, w, size, p):
+    E = brute.edge_dict(s, d, w)
+    out = []
+    for vs in itertools.combinations(range(n), size):
+        ws = [E.get(pair) for pair in itertools.combinations(vs, 2)]
+        if all(x is not None for x in ws):
+            out.append((vs, ws))
+    return out
+
+
+@pytest.mark.parametrize("size", [4, 5])
+@pytest.mark.parametrize("p", [1.0, math.inf, -math.inf, 0.5, 0.0, 2.0])
+def test_cliques_match_all_subsets(size, p):
+    """Every clique of the given size, found by brute force over all vertex subsets, ranked by
+    the p-mean of its edges (exact rationals at p = 1, max/min at +-inf, the float formula of
+    Eq. 1 elsewhere), ties by the sorted IDs."""
+    rng = np.random.default_rng(70 + size)
+    n = 14
+    s, d, w = _rand_graph(rng, n, 0.7, 1, 9)
+    cl = _brute_cliques(n, s, d, w, size, p)
+    E = size * (size - 1) // 2
+    if p == 1.0:
+        val = lambda ws: Fraction(sum(ws), E)  # noqa: E731
+    elif math.isinf(p):
+        val = (lambda ws: max(ws)) if p > 0 else (lambda ws: min(ws))  # noqa: E731
+    elif p == 0.0:
+        val = lambda ws: math.exp(sum(math.log(x) for x in ws) / E)  # noqa: E731
+    else:
+        val = lambda ws: (sum(x ** p for x in ws) / E) ** (1.0 / p)  # noqa: E731
+    cl.sort(key=lambda c: (-val(c[1]), c[0]))
+    out = oracle.cliques(n, s, d, w, size, 10**6, p)
+    assert out["total"] == len(cl)
+    got = [tuple(v) for v in out["v"].tolist()]
+    if p in (1.0, math.inf, -math.inf):
+        assert got == [c[0] for c in cl]
+        assert all(float(val(c[1])) == sc for c, sc in zip(cl, out["score"]))
+    else:
+        ref = np.array([val(c[1]) for c in cl])
+        assert np.allclose(np.sort(out["score"])[::-1], np.sort(ref)[::-1], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("nn,size", [(8, 4), (9, 5), (12, 4)])
+def test_complete_graph_clique_counts(nn, size):
+    s, d = (np.array(x, np.uint32) for x in zip(*itertools.combinations(range(nn), 2)))
+    out = oracle.cliques(nn, s, d, np.full(len(s), 3, np.uint32), size, 5, 1.0)
+    assert out["total"] == math.comb(nn, size)
+    # uniform weights: the lexicographically first subsets
+    assert [tuple(v) for v in out["v"].tolist()] == list(itertools.islice(itertools.combinations(range(nn), size), 5))
+
+
+def test_cliques_on_marked_edges():
+    rng = np.random.default_rng(75)
+    n = 16
+    s, d, w = _rand_graph(rng, n, 0.6, 1, 20)
+    em = (rng.random(len(s)) < 0.2).astype(np.uint8)
+    marked = {(min(int(a), int(b)), max(int(a), int(b))) for a, b, x in zip(s, d, em) if x}
+    cl = [c for c in _brute_cliques(n, s, d, w, 4, 1.0) if any(pr in marked for pr in itertools.combinations(c[0], 2))]
+    cl.sort(key=lambda c: (-sum(c[1]), c[0]))
+    out = oracle.cliques(n, s, d, w, 4, 10**6, 1.0, edge_mark=em)
+    assert out["total"] == len(cl) and [tuple(v) for v in out["v"].tolist()] == [c[0] for c in cl]
