@@ -217,11 +217,15 @@ uint64_t server_request_bytes(tt_server *s, uint32_t k, uint32_t subset_n);
 int server_submit(tt_server *s, uint32_t k, double p, const uint32_t *subset, uint32_t subset_n,
                   uint64_t *ticket);
 
-/* *done = 1 once the request has finished (its result waits for server_wait). */
+/* *done = 1 once the request has finished (its result waits for server_wait).  TT_E_ARG (and
+ * *done = 0) for a ticket that is not outstanding: never issued, or already released by
+ * server_wait. */
 int server_poll(tt_server *s, uint64_t ticket, int *done);
 
 /* Blocks until the request has finished, then returns its result (out: HOST, room for k) and
- * releases the ticket.  stats->total_ms is the time from submission to completion. */
+ * releases the ticket.  stats->total_ms is the time from submission to completion.  TT_E_ARG for
+ * a ticket that is not outstanding (never issued, or released by an earlier or concurrent
+ * server_wait): it never blocks on such a ticket. */
 int server_wait(tt_server *s, uint64_t ticket, tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
 
 /* Device bytes the workers' scratch holds now (what the scratch budget bounds; lazily built graph

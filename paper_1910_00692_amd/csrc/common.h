@@ -43,7 +43,7 @@ struct cand {
 };
 
 // A candidate with many entries to intersect, handed from the wave that found it to a kernel
-// that spreads its entries over many waves (48 bytes).
+// that spreads its entries over many waves (56 bytes).
 struct Heavy {
     uint64_t Ab, Bb;           // iterated row (weight-sorted copy), other row (both copies)
     uint32_t qA, qB, Blen, zB; // admissible entries of each row, other row's length and floor

@@ -484,8 +484,8 @@ uint64_t flag_bytes(const tt_graph *g) { return (((uint64_t)g->n + 4) & ~3ull) +
 // one argument: the candidate and triangle buffers (k), and the subset structures (subset_n).
 uint64_t query_bytes_k(const tt_graph *g, const QueryCtx *q, uint32_t k) {
     const uint64_t cap = std::max<uint64_t>(q->min_buf, 16ull * k);
-    const uint64_t cand = std::min<uint64_t>(g->m + 1, q->max_cand);
-    return 2 * dev_round(cap * sizeof(trec)) + dev_round(cand * sizeof(cand)) +
+    const uint64_t nc = std::min<uint64_t>(g->m + 1, q->max_cand);
+    return 2 * dev_round(cap * sizeof(trec)) + dev_round(nc * sizeof(struct cand)) +
            dev_round((uint64_t)std::max<uint32_t>(k, 1) * sizeof(tt_triangle)) + dev_round(MAX_SEG * 4) +
            dev_round(5 * STAT_SLOTS * 8) + dev_round(HEAVY_CAP * sizeof(Heavy)) + dev_round(HEAVY_PIECES * sizeof(uint2)) +
            dev_round(16 * sizeof(unsigned long long)) + dev_round(256);

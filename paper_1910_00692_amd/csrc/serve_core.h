@@ -144,6 +144,7 @@ struct ServeCore {
             if (stop) return TT_E_ARG;
             r.ticket = next_ticket++;
             *ticket = r.ticket;
+            results[r.ticket] = Res{}; // outstanding until server_wait hands it over
             queue.push_back(std::move(r));
             max_queue = std::max<uint32_t>(max_queue, (uint32_t)queue.size());
         }
@@ -152,24 +153,29 @@ struct ServeCore {
     }
 
     // Blocks until the request has finished and hands its result over (the ticket is released).
+    // TT_E_ARG for a ticket that is not outstanding: never issued, or already handed over (also
+    // to another thread that waited on the same ticket at the same time).
     int wait(uint64_t ticket, Res &out) {
         std::unique_lock<std::mutex> lk(mu);
-        if (ticket == 0 || ticket >= next_ticket) return TT_E_ARG;
         cv_done.wait(lk, [&] {
             auto it = results.find(ticket);
-            return it != results.end() && it->second.done;
+            return it == results.end() || it->second.done;
         });
         auto it = results.find(ticket);
+        if (it == results.end()) return TT_E_ARG;
         out = std::move(it->second);
         results.erase(it);
         return TT_OK;
     }
 
+    // TT_E_ARG for a ticket that is not outstanding (as wait).
     int poll(uint64_t ticket, int *done) {
         std::lock_guard<std::mutex> lk(mu);
         auto it = results.find(ticket);
-        *done = it != results.end() && it->second.done;
-        return !*done && ticket >= next_ticket ? TT_E_ARG : TT_OK;
+        *done = 0;
+        if (it == results.end()) return TT_E_ARG;
+        *done = it->second.done;
+        return TT_OK;
     }
 
     uint64_t held_bytes() {

@@ -2,7 +2,8 @@
 // stand-in for the query (a short sleep), a submitter queues requests of random scratch needs
 // (some close to the budget, so idle slots must give their scratch back), and a waiter collects
 // every result.  Checks: every request completes with its own result, the charged scratch never
-// exceeds the budget, and the loop ends.  Built with a thread sanitizer by test_serve_core.py.
+// exceeds the budget, tickets no longer outstanding are refused, and the loop ends.  Built with
+// a thread sanitizer by test_serve_core.py.
 #include <atomic>
 #include <chrono>
 #include <cstdio>
@@ -75,6 +76,13 @@ int main(int argc, char **argv) {
         done++;
     }
     submitter.join();
+    // a ticket already handed over, or never issued, is refused (not waited for)
+    {
+        ServeCore::Res res;
+        int d = 1;
+        if (N > 0 && (C.wait(tickets[0], res) != TT_E_ARG || C.poll(tickets[0], &d) != TT_E_ARG || d != 0)) bad++;
+        if (C.wait(0, res) != TT_E_ARG || C.wait(1ull << 40, res) != TT_E_ARG) bad++;
+    }
     C.shutdown();
     for (auto &t : workers) t.join();
     printf("requests %d completed %llu over_budget %llu bad %llu releases %llu peak %llu max_running %u\n", done,

@@ -3,6 +3,7 @@
 Every request's result must equal the single-query result for the same arguments (alone vs in
 the mix), admission must respect the scratch budget, and results are checked against the
 oracle for a sample of requests."""
+import ctypes
 import math
 import sys
 
@@ -169,4 +170,13 @@ def test_poll_and_bad_requests(tt, graph):
         t2 = S.submit(20, -math.inf)
         r = S.wait(t2)
         assert r["n_out"] == 20
-        assert not S.done(t2)  # the ticket was released by wait
+        # the ticket was released by wait: polling or waiting again is refused, never blocks
+        with pytest.raises(tt.TopKError) as e:
+            S.done(t2)
+        assert e.value.code == tt.TT_E_ARG
+        with pytest.raises(ValueError):
+            S.wait(t2)
+        buf = (tt.Triangle * 32)()
+        n_out = ctypes.c_uint32(0)
+        assert tt.library().server_wait(S._h, t2, buf, ctypes.byref(n_out), None) == tt.TT_E_ARG
+        assert tt.library().server_wait(S._h, 10**9, buf, ctypes.byref(n_out), None) == tt.TT_E_ARG
