@@ -109,6 +109,20 @@ int topk_triangles_ex(tt_graph *g, uint32_t k, double p, const uint32_t *subset,
                       tt_triangle *out, uint32_t *n_out, tt_query_stats *stats);
 
 /*
+ * topk_triangles for callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  It computes exactly what topk_triangles computes
+ * (same kernels) but allocates nothing: no device or pinned memory, no events, and nothing of
+ * the graph built on first use (a weight-ordered stream or a bound order built by earlier
+ * topk_triangles calls is used; otherwise the rows are streamed in row order).  Its device
+ * scratch is one static array of 64 MiB per device, held by each device the library runs on
+ * until the process ends, which keeps the last call's contents (each call clears what must
+ * start at zero).  Calls on one device are serialised by a lock; the work runs on the graph's
+ * stream and has finished when the call returns.  out: caller-owned HOST array of k records.
+ * k > 16384 gives TT_E_TOO_LARGE.  No stats.
+ */
+int topk_triangles_noalloc(tt_graph *g, uint32_t k, double p, tt_triangle *out, uint32_t *n_out);
+
+/*
  * Weighted edge sampling (Alg. 3): `budget` independent draws of an edge e with probability
  * w_e^q / Z (Prop. 1), q = p for finite p > 0 and q = 1 otherwise; the result is the top-k,
  * by the true m_p, of the union of all triangles on the drawn edges.  Draw s uses the s-th

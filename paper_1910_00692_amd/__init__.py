@@ -27,7 +27,7 @@ EXPORTED = ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles
             "graph_free", "tt_last_error", "server_create", "server_request_bytes", "server_submit", "server_poll",
             "server_wait", "server_info", "server_destroy", "batch_load", "batch_load_device", "batch_topk",
             "batch_topk_ex", "batch_num_configs", "batch_num_graphs", "batch_free", "tt_trim_cache",
-            "shl_topk_triangles", "sample_triangles_by", "sample_heavy_cliques", "server_scratch_bytes")
+            "topk_triangles_noalloc", "shl_topk_triangles", "sample_triangles_by", "sample_heavy_cliques", "server_scratch_bytes")
 TT_SAMPLE_WEDGE, TT_SAMPLE_PATH = 1, 2
 TT_BATCH_EAGER = 1
 
@@ -104,6 +104,7 @@ def library():
         lib.graph_load_device.argtypes = [u32, u64, vp, vp, vp, vp, pg]
         lib.topk_triangles.argtypes = [vp, u32, dbl, ptri, p32]
         lib.topk_triangles_ex.argtypes = [vp, u32, dbl, p32, u32, ptri, p32, pst]
+        lib.topk_triangles_noalloc.argtypes = [vp, u32, dbl, ptri, p32]
         lib.shl_topk_triangles.argtypes = [vp, u32, dbl, u32, ptri, p32, ctypes.POINTER(ctypes.c_uint64)]
         lib.sample_triangles_by.argtypes = [vp, i32, u32, dbl, u64, u64, dbl, p32, ptri, p32,
                                             ctypes.POINTER(ctypes.c_uint64 * 2)]
@@ -147,7 +148,7 @@ def library():
         lib.batch_num_graphs.restype = u32
         lib.batch_free.argtypes = [vp]
         lib.batch_free.restype = None
-        for name in ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles_ex",
+        for name in ("graph_load", "graph_load_device", "topk_triangles", "topk_triangles_ex", "topk_triangles_noalloc",
                      "shl_topk_triangles", "sample_triangles_by", "sample_heavy_cliques",
                      "sample_heavy_triangles", "sample_heavy_triangles_ex", "server_create", "server_submit",
                      "server_poll", "server_wait", "server_info", "batch_load", "batch_load_device", "batch_topk",
@@ -268,6 +269,13 @@ class Graph:
         nn = n_out.value
         v = np.array([list(buf[t].v)[:size] for t in range(nn)], np.uint32).reshape(nn, size)
         return {"v": v, "score": np.array([buf[t].score for t in range(nn)]), "n_out": nn, "found": int(found.value)}
+
+    def topk_noalloc(self, k: int, p: float):
+        """topk_triangles_noalloc: the same answer as topk(k, p), with no allocation."""
+        buf = (Triangle * max(int(k), 1))()
+        n_out = ctypes.c_uint32(0)
+        _check(library().topk_triangles_noalloc(self._h, int(k), float(p), buf, ctypes.byref(n_out)))
+        return _result(buf, n_out.value)
 
     def sample(self, k: int, p: float, budget: int, seed: int, with_stats: bool = False, q: float | None = None,
                return_draws: bool = False):

@@ -95,6 +95,11 @@ struct QueryCtx {
     bool sub_active = false;               // the passes stream the compact list
     std::vector<uint64_t> sub_hist;        // host: its entries per weight_bin(w)
     BoundOrder *ord = nullptr;             // bound order of the running query's p (or NULL)
+    // A context whose device scratch is a fixed region handed in by the caller of the
+    // no-allocation query: it allocates nothing (no device or pinned memory, no events), builds
+    // nothing of the graph lazily (streams and bound orders are used only once placed), and
+    // copies the results straight to the caller's buffer.
+    bool fixed = false;
     hipEvent_t ev[8] = {};
     std::vector<hipEvent_t> band_ev;       // start/stop pairs of the passes of a query
 };

@@ -515,6 +515,10 @@ uint64_t ctx_bytes(const QueryCtx *q) {
 
 int ensure_scratch(const tt_graph *g, QueryCtx *q, uint64_t cap, uint64_t kout) {
     int rc;
+    if (q->fixed)
+        return q->buf_cap >= cap && q->dout_cap >= kout && q->cand_cap >= 1
+                   ? TT_OK
+                   : fail(TT_E_TOO_LARGE, "the query needs more scratch than the fixed region holds");
     if (!q->dcount) {
         if ((rc = dev_alloc(nullptr, (void **)&q->dcount, 16 * sizeof(unsigned long long)))) return rc;
         if (hipHostMalloc((void **)&q->hcount, 16 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
@@ -618,7 +622,8 @@ struct Stream {
 // The shortest of the streams that hold every possible base entry of a band triangle: rows
 // with hb >= score floor (row order), entries with weight >= weight floor, and (when the
 // query has one) entries whose bound reaches the score floor.
-Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u128 L) {
+// placed_only: the weight-ordered stream is taken only where its bins are already in place.
+Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u128 L, bool placed_only = false) {
     Stream r{g->osrc, g->col, g->wgt, nullptr, entries_for(g, mode, L), g->hmx, (uint32_t)WBINS};
     const uint64_t z = weight_floor(mode, p, L, g->wmax);
     if (z > 0xFFFFFFFFull) {
@@ -626,7 +631,8 @@ Stream pick_stream(const tt_graph *g, const BoundOrder *o, int mode, double p, u
     } else if (z > 0) {
         const uint32_t b = weight_bin((uint32_t)z);
         const uint64_t E2 = g->wbase[b] + g->whist[b];
-        if (E2 < r.E) r = Stream{g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, E2, g->ws_hmx, b};
+        if (E2 < r.E && (!placed_only || g->ws_low.load(std::memory_order_acquire) <= b))
+            r = Stream{g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, E2, g->ws_hmx, b};
     }
     if (o) {
         const uint64_t t = score_floor(mode, L);
@@ -697,7 +703,7 @@ int acquire_order(tt_graph *g, QueryCtx *q, double p, BoundOrder **out) {
             }
         }
         slot = empty ? empty : lru;
-        if (!slot) return TT_OK;
+        if (!slot || q->fixed) return TT_OK;
         if (streamed_at(g, pb).entries <= ORDER_AFTER * g->m) return TT_OK;
         // reserved: built below without the lock, so queries of other p are not held up
         slot->valid = false;
@@ -756,6 +762,7 @@ void release_order(tt_graph *g, BoundOrder *o) {
 }
 
 int ensure_band_events(QueryCtx *q, size_t pairs) {
+    if (q->fixed) return TT_OK; // no timing
     while (q->band_ev.size() < 2 * pairs) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return fail(TT_E_DEVICE, "hipEventCreate failed");
@@ -782,8 +789,8 @@ template <bool GEN> void enqueue_pair(int filter, const EnumArgs &A, unsigned ig
 // intersected in pieces of at most cand_cap entries.  `slot` picks its event pair.
 int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool gated, size_t slot) {
     Stream S = q->sub_active ? Stream{q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_len, nullptr, (uint32_t)WBINS}
-                             : pick_stream(g, q->ord, B.mode, B.p, B.L);
-    if (!q->sub_active && S.wbin < (uint32_t)WBINS) {
+                             : pick_stream(g, q->ord, B.mode, B.p, B.L, q->fixed);
+    if (!q->sub_active && S.wbin < (uint32_t)WBINS && !q->fixed) {
         // the weight-ordered stream: its bins down to S.wbin are placed on first need (lazily
         // built graph state, guarded by the graph's init lock); the stream's arrays are read
         // again after the acquire of ws_low that shows them placed
@@ -824,7 +831,7 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
     A.hpiece = q->hpiece;
     A.heavy_min = HEAVY_MIN;
     A.hstat = q->dcount + 12;
-    HIP_TRY(hipEventRecord(q->band_ev[2 * slot], q->stream));
+    if (!q->fixed) HIP_TRY(hipEventRecord(q->band_ev[2 * slot], q->stream));
     for (uint64_t off = 0; off < S.E; off += q->cand_cap) {
         const uint64_t E = std::min<uint64_t>(S.E - off, q->cand_cap);
         A.s_src = S.src + off;
@@ -841,13 +848,13 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
         else enqueue_pair<false>(filter, A, igrid, q->stream);
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipEventRecord(q->band_ev[2 * slot + 1], q->stream));
+    if (!q->fixed) HIP_TRY(hipEventRecord(q->band_ev[2 * slot + 1], q->stream));
     return TT_OK;
 }
 
 // After the stream has been synchronised: add the durations of passes [0, n).
 void add_enum_time(QueryCtx *q, tt_query_stats *st, size_t n) {
-    if (!st) return;
+    if (!st || q->fixed) return;
     for (size_t i = 0; i < n; i++) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, q->band_ev[2 * i], q->band_ev[2 * i + 1]) == hipSuccess) st->enum_kernel_ms += ms;
@@ -872,7 +879,7 @@ Band make_band(int mode, double p, u128 L, uint32_t Li, uint32_t Lj, uint32_t Ll
 constexpr uint64_t EAGER_PIECES = 8;
 
 uint64_t band_pieces(const tt_graph *g, const QueryCtx *q, const Band &B) {
-    const uint64_t E = q->sub_active ? q->sub_len : pick_stream(g, q->ord, B.mode, B.p, B.L).E;
+    const uint64_t E = q->sub_active ? q->sub_len : pick_stream(g, q->ord, B.mode, B.p, B.L, q->fixed).E;
     return std::max<uint64_t>(1, (E + q->cand_cap - 1) / q->cand_cap);
 }
 
@@ -925,7 +932,7 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     };
     HIP_TRY(hipMemsetAsync(q->dcount, 0, 8 * sizeof(unsigned long long), s));
     HIP_TRY(hipMemsetAsync(q->dcount + 12, 0, 2 * sizeof(unsigned long long), s));
-    HIP_TRY(hipEventRecord(q->ev[0], s));
+    if (!q->fixed) HIP_TRY(hipEventRecord(q->ev[0], s));
     std::vector<u128> Ls;     // thresholds of the bands enqueued, in order
     std::vector<double> Ms;   // their ranks
     size_t launched = 0;      // bands whose events are recorded
@@ -996,15 +1003,15 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
     while (overflow) {
         // the k-th best of the records kept is a lower bound on the k-th best overall
         trec *res = nullptr;
-        HIP_TRY(hipEventRecord(q->ev[2], s));
+        if (!q->fixed) HIP_TRY(hipEventRecord(q->ev[2], s));
         if ((rc = select_topk(q, q->buf_cap, k, &res))) return rc;
         trec kth;
         HIP_TRY(hipMemcpyAsync(&kth, res + (k - 1), sizeof(trec), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(q->ev[3], s));
+        if (!q->fixed) HIP_TRY(hipEventRecord(q->ev[3], s));
         HIP_TRY(hipMemsetAsync(q->dcount, 0, sizeof(unsigned long long), s));
         HIP_TRY(hipStreamSynchronize(s));
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, q->ev[2], q->ev[3]);
+        if (!q->fixed) (void)hipEventElapsedTime(&ms, q->ev[2], q->ev[3]);
         sel_ms += ms;
         const u128 L = ((u128)kth.khi << 64) | kth.klo;
         rc = launch_enum(g, q, make_band(mode, p, L, kth.i, kth.j, kth.l, false, 0), filter, false, 0);
@@ -1016,7 +1023,7 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
         cnt = q->hcount[0];
         overflow = cnt > q->buf_cap;
     }
-    HIP_TRY(hipEventRecord(q->ev[1], s));
+    if (!q->fixed) HIP_TRY(hipEventRecord(q->ev[1], s));
     const uint64_t N = cnt;
     const uint32_t K = (uint32_t)std::min<uint64_t>(N, k);
     if (K > 0) {
@@ -1025,19 +1032,23 @@ int run_topk(const tt_graph *g, QueryCtx *q, uint32_t k, double p, int filter, t
         k_finalize<<<(K + 255) / 256, 256, 0, s>>>(res, K, mode, q->dout);
         HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipEventRecord(q->ev[2], s));
+    if (!q->fixed) HIP_TRY(hipEventRecord(q->ev[2], s));
     k_reduce_stats<<<5, 256, 0, s>>>(q->spart, q->dcount + 1);
-    // results through pinned staging (the caller's buffer is ordinary host memory), counters in
-    // one copy
-    if (K > 0) HIP_TRY(hipMemcpyAsync(q->hout, q->dout, (size_t)K * sizeof(tt_triangle), hipMemcpyDeviceToHost, s));
+    // results through pinned staging (the caller's buffer is ordinary host memory; a fixed
+    // context copies straight to it), counters in one copy
+    if (K > 0)
+        HIP_TRY(hipMemcpyAsync(q->fixed ? (void *)out : (void *)q->hout, q->dout, (size_t)K * sizeof(tt_triangle),
+                               hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(q->hcount, q->dcount, 16 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (K > 0) std::memcpy(out, q->hout, (size_t)K * sizeof(tt_triangle));
+    if (K > 0 && !q->fixed) std::memcpy(out, q->hout, (size_t)K * sizeof(tt_triangle));
     *n_out = K;
     if (st) {
         float e_ms = 0.f, s_ms = 0.f;
-        (void)hipEventElapsedTime(&e_ms, q->ev[0], q->ev[1]);
-        (void)hipEventElapsedTime(&s_ms, q->ev[1], q->ev[2]);
+        if (!q->fixed) {
+            (void)hipEventElapsedTime(&e_ms, q->ev[0], q->ev[1]);
+            (void)hipEventElapsedTime(&s_ms, q->ev[1], q->ev[2]);
+        }
         st->enum_ms += e_ms;
         st->select_ms += s_ms + sel_ms;
         st->candidate_edges += q->hcount[1];
@@ -1333,6 +1344,90 @@ int es_mark_edges(tt_graph *g, QueryCtx *q, double qexp, uint64_t budget, uint64
     else k_es_draw<2><<<grid, 256, 0, s>>>(tab->prefix, tab->guide, bits, g->m, budget, seed, g->opos, g->emark, nullptr);
     HIP_TRY(hipGetLastError());
     return TT_OK;
+}
+
+// ----------------------------------------------------------------------------- no allocation
+// topk_triangles_noalloc: topk_triangles with its device scratch in one static array per
+// device (`scratch`), for callers that cannot allocate.  The array's device address is taken
+// once per device with hipGetSymbolAddress; the host-side name is never used as an address.
+namespace {
+constexpr uint64_t NOALLOC_BYTES = 64ull << 20;
+constexpr uint32_t NOALLOC_MAX_K = 16384;
+constexpr uint64_t NOALLOC_BUF = 16ull * NOALLOC_MAX_K; // triangle records per buffer
+constexpr int NOALLOC_DEVICES = 64;
+} // namespace
+
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+struct NoAllocDevice {
+    std::mutex mu;                  // one call at a time per device
+    unsigned char *base = nullptr;  // device address of this device's `scratch`
+    QueryCtx q;                     // its fields point into `scratch` (q.fixed)
+    unsigned long long hcount[16] = {};
+};
+NoAllocDevice g_noalloc[NOALLOC_DEVICES];
+
+// With the device current: the array's address and the query context carved from it.
+int noalloc_setup(NoAllocDevice &D) {
+    void *addr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !addr)
+        return fail(TT_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    unsigned char *base = (unsigned char *)addr;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        void *r = base + off;
+        off += (bytes + 255) & ~255ull;
+        return r;
+    };
+    QueryCtx &q = D.q;
+    q.fixed = true;
+    q.dcount = (unsigned long long *)take(16 * sizeof(unsigned long long));
+    q.spart = (unsigned long long *)take(5 * STAT_SLOTS * sizeof(unsigned long long));
+    q.ccnt = (uint32_t *)take(MAX_SEG * sizeof(uint32_t));
+    q.nheavy = (unsigned long long *)take(256);
+    q.heavy = (Heavy *)take(HEAVY_CAP * sizeof(Heavy));
+    q.hpiece = (uint2 *)take(HEAVY_PIECES * sizeof(uint2));
+    q.dout = (tt_triangle *)take(NOALLOC_MAX_K * sizeof(tt_triangle));
+    q.dout_cap = NOALLOC_MAX_K;
+    q.buf0 = (trec *)take(NOALLOC_BUF * sizeof(trec));
+    q.buf1 = (trec *)take(NOALLOC_BUF * sizeof(trec));
+    q.buf_cap = q.min_buf = NOALLOC_BUF;
+    q.cand = (cand *)(base + off); // the rest: candidate entries of a piece of a pass
+    q.cand_cap = q.max_cand = (NOALLOC_BYTES - off) / sizeof(cand);
+    q.hcount = D.hcount;
+    D.base = base;
+    return TT_OK;
+}
+} // namespace
+
+extern "C" int topk_triangles_noalloc(tt_graph *g, uint32_t k, double p, tt_triangle *out, uint32_t *n_out) {
+    static_assert(NOALLOC_BYTES >= (16ull << 20) + 2 * NOALLOC_BUF * sizeof(trec) + 2 * HEAVY_CAP * sizeof(Heavy),
+                  "the fixed region leaves room for a candidate list");
+    int rc = check_query(g, p, out, k, n_out);
+    if (rc) return rc;
+    if (k > NOALLOC_MAX_K) return fail(TT_E_TOO_LARGE, "topk_triangles_noalloc: k must be <= 16384");
+    if (k == 0 || g->m == 0) { set_error(""); return TT_OK; }
+    if (g->device < 0 || g->device >= NOALLOC_DEVICES) return fail(TT_E_DEVICE, "device ordinal beyond 63");
+    NoAllocDevice &D = g_noalloc[g->device];
+    std::lock_guard<std::mutex> dlock(D.mu);
+    std::lock_guard<std::mutex> glock(g->mu);
+    (void)hipSetDevice(g->device);
+    if (!D.base && (rc = noalloc_setup(D))) return rc;
+    QueryCtx *q = &D.q;
+    q->stream = g->stream;
+    // the array keeps the previous call's contents: the spread counters start at zero (the
+    // other counters are cleared by the query itself)
+    HIP_TRY(hipMemsetAsync(q->spart, 0, 5 * STAT_SLOTS * sizeof(unsigned long long), q->stream));
+    BoundOrder *o = nullptr;
+    if ((rc = acquire_order(g, q, p, &o))) return rc; // an order already built, never a new one
+    q->ord = o;
+    rc = run_topk(g, q, k, p, FILTER_NONE, out, n_out, nullptr);
+    q->ord = nullptr;
+    release_order(g, o);
+    if (!rc) set_error("");
+    return rc;
 }
 
 // ----------------------------------------------------------------------------- serving
