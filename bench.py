@@ -83,6 +83,24 @@ def recorded_traffic(workload):
     return int(fields["traffic_bytes_per_pass"])
 
 
+def single_breakdown(reqs, ms, res):
+    """Where the single-query path spends its time: per p and for subset requests, the count,
+    the mean wall time and the mean device time of the passes and the selection."""
+    groups = {}
+    fields = ("passes", "edges_streamed", "candidate_edges", "intersected_entries", "restarts", "bound_order")
+    for r, t, x in zip(reqs, ms, res):
+        key = "subset" if r["subset"] is not None else f"p={r['p']}"
+        st = x["stats"]
+        g = groups.setdefault(key, {"n": 0, "ms": 0.0, "device_ms": 0.0, **{f: 0.0 for f in fields}})
+        g["n"] += 1
+        g["ms"] += t
+        g["device_ms"] += st["enum_kernel_ms"] + st["select_ms"]
+        for f in fields:
+            g[f] += st[f]
+    return {k: {"n": g["n"], "mean_ms": g["ms"] / g["n"], "mean_device_ms": g["device_ms"] / g["n"],
+                **{"mean_" + f: g[f] / g["n"] for f in fields}} for k, g in sorted(groups.items())}
+
+
 def run_serve(args):
     """Served workload: a resident n=10M, ~200M-edge graph and a Poisson request stream (mean
     2,000 req/s; k log-uniform in [10, 1e4]; p from {-inf, -1, 0, 1, 2, +inf}; 20% restricted
@@ -117,7 +135,7 @@ def run_serve(args):
     t0 = time.perf_counter()
     for r in reqs:
         a = time.perf_counter()
-        single_res.append(G.topk(r["k"], r["p"], subset=r["subset"]))
+        single_res.append(G.topk(r["k"], r["p"], subset=r["subset"], with_stats=True))
         single.append((time.perf_counter() - a) * 1e3)
     single_s = time.perf_counter() - t0
     print(f"[bench] single-query path: {len(reqs) / single_s:.1f} req/s", file=sys.stderr, flush=True)
@@ -176,6 +194,7 @@ def run_serve(args):
                               "p99_ms": pct(single, 99)},
         "offered_rate": len(reqs) / max(reqs[-1]["t"], 1e-9), "server": info, "build_ms": build_ms,
         "gpu_matches_single": mismatched == 0, "mismatched_requests": mismatched,
+        "single_by_kind": single_breakdown(reqs, single, single_res),
     }
     print(json.dumps(out), flush=True)
 
