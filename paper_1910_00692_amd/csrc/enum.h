@@ -164,7 +164,9 @@ __device__ __forceinline__ bool in_band(const Band &B, u128 key, uint32_t i, uin
 
 // ----------------------------------------------------------------------------- enumeration
 enum { FILTER_NONE = 0, FILTER_EDGES = 1, FILTER_VERTICES = 2 };
-enum { FL_MARK_UV = 1, FL_REQ_A = 2, FL_REQ_B = 4, FL_REQ_C = 8 };
+// FL_PAIRS: a FL_REQ_C candidate whose iterated side is the run of u's heads in the subset
+// (EnumArgs::sp_*), not a prefix of u's weight-sorted row; qB then holds that side's floor.
+enum { FL_MARK_UV = 1, FL_REQ_A = 2, FL_REQ_B = 4, FL_REQ_C = 8, FL_PAIRS = 16 };
 // Admissible entries of the other row scanned instead of a binary search (EnumArgs::scan_max).
 constexpr uint32_t SCAN_MAX = 32;
 
@@ -191,6 +193,10 @@ struct EnumArgs {
     const uint8_t *emark;  // FILTER_EDGES: drawn entries (head-sorted positions)
     const uint8_t *vflag;  // FILTER_EDGES: vertex has a drawn out-entry; FILTER_VERTICES: vertex in subset
     const uint8_t *vflag2; // FILTER_VERTICES: vertex has an out-neighbour in the subset
+    // FILTER_VERTICES on the compact stream: for the listed in-neighbour with index i (the
+    // stream's position field), its heads in the subset and their weights are
+    // sp_c / sp_w[sp_start[i] .. sp_start[i] + sp_cnt[i]); NULL elsewhere
+    const uint32_t *sp_c, *sp_w, *sp_start, *sp_cnt;
     trec *out;
     unsigned long long *count;
     uint64_t cap;
@@ -365,8 +371,10 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
                 v[k] = A.s_col[x];
                 a[k] = A.s_wgt[x];
                 if (!BATCH && A.s_hmx) mv[k] = A.s_hmx[x];
-                // the entry position is needed only by the drawn-entry marks
+                // the entry position is needed only by the drawn-entry marks; the subset's
+                // compact stream holds the tail's index in the list of in-neighbours there
                 if (!BATCH && FILTER == FILTER_EDGES) pos[k] = A.s_pos ? A.s_pos[e] : (uint32_t)(e + A.pos_off);
+                if (!BATCH && FILTER == FILTER_VERTICES && A.sp_c) pos[k] = A.s_pos[e];
             }
         }
         uint32_t n_pass = 0, rank[FILTER_UNROLL];
@@ -475,6 +483,20 @@ template <int FILTER, bool BATCH, bool GEN>
 __device__ __forceinline__ bool lookup_entry(const EnumArgs &A, uint64_t pa, uint64_t Bb, uint32_t Blen, uint32_t qB,
                                              uint32_t zB, uint32_t a, uint32_t u, uint32_t v, uint32_t fl,
                                              uint32_t g, trec &r) {
+    if (FILTER == FILTER_VERTICES && (fl & FL_PAIRS)) {
+        // a head c of u in the subset (weight x >= the floor kept in qB), looked up in v's
+        // head-sorted row
+        const uint32_t c = A.sp_c[pa], x = A.sp_w[pa];
+        if (x < qB) return false;
+        uint64_t lo = Bb, hi = Bb + Blen;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (A.cw[mid].x < c) lo = mid + 1; else hi = mid;
+        }
+        const uint2 hit = lo < Bb + Blen ? A.cw[lo] : make_uint2(~0u, 0u);
+        if (hit.x != c || hit.y < zB) return false;
+        return make_rec<BATCH, GEN>(A, g, a, x, hit.y, u, v, c, r);
+    }
     const uint32_t c = A.wcol[pa], x = A.wwgt[pa];
     if (FILTER == FILTER_VERTICES && (fl & FL_REQ_C) && !A.vflag[c]) return false;
     uint8_t markA = 0;
@@ -589,13 +611,27 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
             if (FILTER == FILTER_VERTICES && !A.vflag[u] && !A.vflag[v]) fl |= FL_REQ_C;
             const uint64_t zu = min_other<GEN>(B, a, Wv), zv = min_other<GEN>(B, a, Wu);
             pass = zu <= Wu && zv <= Wv; // then both floors fit 32 bits
-            if (pass && ul + vl <= A.merge_max) {
+            // a triangle of a candidate with neither end in the subset must close on a subset
+            // vertex: with the subset's lists, only u's heads in the subset are looked up
+            const bool pairs = FILTER == FILTER_VERTICES && (fl & FL_REQ_C) && A.sp_c != nullptr;
+            if (pass && pairs) {
+                const uint32_t li = c.pos;
+                Ab = A.sp_start[li];
+                qA = A.sp_cnt[li];
+                qB = (uint32_t)zu; // the floor of w_uc
+                Bb = vb;
+                Blen = vl;
+                zB = (uint32_t)zv;
+                fl |= FL_PAIRS;
+                if (qA == 0) pass = false;
+            }
+            if (pass && !pairs && ul + vl <= A.merge_max) {
                 merge = true;
                 pass = false;
                 Ab = ub; qA = ul; zA = (uint32_t)zu;
                 Bb = vb; Blen = vl; zB = (uint32_t)zv;
             }
-            if (pass) {
+            if (pass && !pairs) {
                 uint32_t qu, qv;
                 count_pair(A.wwgt, ub, ul, zu, vb, vl, zv, qu, qv);
                 const bool uA = qu <= qv;
@@ -613,27 +649,27 @@ template <int FILTER, bool BATCH, bool GEN> __global__ __launch_bounds__(256) vo
                     if (!fb) fl |= FL_REQ_A; // only drawn entries of the iterated row can help
                     if (!fa) fl |= FL_REQ_B;
                 }
-                if (pass && qA > A.heavy_min && A.heavy) {
-                    // reserve a record and the pieces; a range reserved past the list's end is
-                    // marked empty and the candidate stays with its wave
-                    const unsigned long long h = atomicAdd(A.nheavy, 1ull);
-                    bool spread = false;
-                    if (h < HEAVY_CAP) {
-                        const uint32_t np = (qA + HEAVY_PIECE - 1) / HEAVY_PIECE;
-                        const unsigned long long p0 = atomicAdd(A.nheavy + 1, (unsigned long long)np);
-                        if (p0 + np <= HEAVY_PIECES) {
-                            A.heavy[h] = Heavy{Ab, Bb, qA, qB, Blen, zB, a, u, v, fl, g, 0u};
-                            for (uint32_t k2 = 0; k2 < np; k2++)
-                                A.hpiece[p0 + k2] = make_uint2((uint32_t)h, k2);
-                            spread = true;
-                            pass = false; // its entries are intersected by k_intersect_heavy
-                        } else {
-                            for (unsigned long long k2 = p0; k2 < HEAVY_PIECES; k2++)
-                                A.hpiece[k2] = make_uint2(~0u, 0u);
-                        }
+            }
+            if (pass && qA > A.heavy_min && A.heavy) {
+                // reserve a record and the pieces; a range reserved past the list's end is
+                // marked empty and the candidate stays with its wave
+                const unsigned long long h = atomicAdd(A.nheavy, 1ull);
+                bool spread = false;
+                if (h < HEAVY_CAP) {
+                    const uint32_t np = (qA + HEAVY_PIECE - 1) / HEAVY_PIECE;
+                    const unsigned long long p0 = atomicAdd(A.nheavy + 1, (unsigned long long)np);
+                    if (p0 + np <= HEAVY_PIECES) {
+                        A.heavy[h] = Heavy{Ab, Bb, qA, qB, Blen, zB, a, u, v, fl, g, 0u};
+                        for (uint32_t k2 = 0; k2 < np; k2++)
+                            A.hpiece[p0 + k2] = make_uint2((uint32_t)h, k2);
+                        spread = true;
+                        pass = false; // its entries are intersected by k_intersect_heavy
+                    } else {
+                        for (unsigned long long k2 = p0; k2 < HEAVY_PIECES; k2++)
+                            A.hpiece[k2] = make_uint2(~0u, 0u);
                     }
-                    if (A.hstat) atomicAdd(A.hstat + (spread ? 0 : 1), 1ull);
                 }
+                if (A.hstat) atomicAdd(A.hstat + (spread ? 0 : 1), 1ull);
             }
         }
         const uint32_t work = pass ? qA : 0;

@@ -1616,6 +1616,7 @@ extern "C" uint64_t graph_device_bytes(const tt_graph *g) { return g ? g->bytes 
 void ctx_release(QueryCtx *q) {
     void *ptrs[] = {q->buf0,    q->buf1,    q->cand,    q->ccnt,    q->spart,    q->dcount, q->dout,
                     q->vflag,   q->vflag2,  q->sub_src, q->sub_col, q->sub_wgt,  q->sub_pos, q->sub_vlist,
+                    q->sp_c,    q->sp_w,    q->sp_start, q->sp_cnt,
                     q->heavy,   q->nheavy,  q->hpiece};
     for (void *p : ptrs) dev_free(nullptr, p, 0);
     q->buf0 = q->buf1 = nullptr;
@@ -1629,6 +1630,7 @@ void ctx_release(QueryCtx *q) {
     q->dout = nullptr;
     q->vflag = q->vflag2 = nullptr;
     q->sub_src = q->sub_col = q->sub_wgt = q->sub_pos = q->sub_vlist = nullptr;
+    q->sp_c = q->sp_w = q->sp_start = q->sp_cnt = nullptr;
     q->sub_active = false;
     q->buf_cap = q->cand_cap = q->dout_cap = 0;
     if (q->hcount) (void)hipHostFree(q->hcount);

@@ -334,13 +334,19 @@ __global__ __launch_bounds__(256) void k_sub_in(const uint32_t *ids, uint32_t cn
 // One wave per row: rows 0..cnt-1 are the subset ids (owned copies only, every entry kept),
 // rows cnt..cnt+nv-1 the listed in-neighbours (entries whose head is in S or has an
 // out-neighbour in S).  Kept entries go to the compact stream (cnt8[2]) with their weight
-// histogram (hist, by weight_bin).
+// histogram (hist, by weight_bin); the stream's position field holds, for an entry of a listed
+// in-neighbour u, u's index in vlist (~0 for a subset row).  A listed row's entries whose head is
+// in S are also written, in row order, to one run of sp_c / sp_w reserved for the row (cnt8[3]),
+// recorded in sp_start / sp_cnt: the candidate u->v whose triangles must close on a subset
+// vertex then looks up only those heads in v's row.
 __global__ __launch_bounds__(256) void k_sub_rows(const uint32_t *ids, const uint8_t *own, uint32_t cnt,
                                                   const uint32_t *vlist, uint32_t nv, const uint64_t *rstart,
                                                   const uint32_t *rlen, const uint32_t *col, const uint32_t *wgt,
                                                   const uint8_t *vflag, const uint8_t *vflag2, uint32_t *o_src,
                                                   uint32_t *o_col, uint32_t *o_wgt, uint32_t *o_pos, uint64_t cap,
-                                                  unsigned long long *cnt8, unsigned long long *hist) {
+                                                  uint32_t *sp_c, uint32_t *sp_w, uint32_t *sp_start,
+                                                  uint32_t *sp_cnt, unsigned long long *cnt8,
+                                                  unsigned long long *hist) {
     __shared__ uint32_t h[WBINS];
     for (int t = threadIdx.x; t < WBINS; t += blockDim.x) h[t] = 0;
     __syncthreads();
@@ -353,13 +359,44 @@ __global__ __launch_bounds__(256) void k_sub_rows(const uint32_t *ids, const uin
         const uint32_t u = in_s ? ids[r] : vlist[r - cnt];
         const uint64_t b = rstart[u];
         const uint32_t len = rlen[u];
+        const uint32_t li = in_s ? ~0u : (uint32_t)(r - cnt); // index in vlist
+        // a listed row: its heads in S counted first, then one run reserved for them
+        uint64_t sp0 = 0;
+        uint32_t spn = 0;
+        if (!in_s) {
+            for (uint32_t t0 = 0; t0 < len; t0 += 64) {
+                const uint32_t t = t0 + lane;
+                spn += (uint32_t)__popcll(__ballot(t < len && vflag[col[b + t]]));
+            }
+            unsigned long long s0 = 0;
+            if (lane == 0 && spn) s0 = atomicAdd(&cnt8[3], (unsigned long long)spn);
+            sp0 = __shfl(s0, 0, 64);
+            if (lane == 0) {
+                // a run past the capacity is recorded empty (then the kept stream overflows too)
+                const bool fits = sp0 + spn <= cap;
+                sp_start[li] = fits ? (uint32_t)sp0 : 0u;
+                sp_cnt[li] = fits ? spn : 0u;
+            }
+        }
+        uint32_t spr = 0; // heads in S written so far
         for (uint32_t t0 = 0; t0 < len; t0 += 64) {
             const uint32_t t = t0 + lane;
-            bool keep = false;
-            uint32_t v = 0;
+            bool keep = false, ins = false;
+            uint32_t v = 0, w = 0;
             if (t < len) {
                 v = col[b + t];
-                keep = in_s || vflag[v] || vflag2[v];
+                ins = vflag[v];
+                keep = in_s || ins || vflag2[v];
+                if (keep) w = wgt[b + t];
+            }
+            if (!in_s) {
+                const uint64_t sb = __ballot(ins);
+                const uint64_t ps = sp0 + spr + __popcll(sb & ((1ull << lane) - 1ull));
+                if (ins && sp0 + spn <= cap) {
+                    sp_c[ps] = v;
+                    sp_w[ps] = w;
+                }
+                spr += (uint32_t)__popcll(sb);
             }
             const uint64_t bal = __ballot(keep);
             if (!bal) continue;
@@ -368,11 +405,10 @@ __global__ __launch_bounds__(256) void k_sub_rows(const uint32_t *ids, const uin
             b0 = __shfl(b0, 0, 64);
             const uint64_t slot = b0 + __popcll(bal & ((1ull << lane) - 1ull));
             if (keep && slot < cap) {
-                const uint32_t w = wgt[b + t];
                 o_src[slot] = u;
                 o_col[slot] = v;
                 o_wgt[slot] = w;
-                o_pos[slot] = (uint32_t)(b + t);
+                o_pos[slot] = li;
                 atomicAdd(&h[weight_bin(w)], 1u);
             }
         }
@@ -494,7 +530,7 @@ uint64_t query_bytes_sub(const tt_graph *g, const QueryCtx *q, uint32_t subset_n
     if (!subset_n) return 0;
     const uint64_t c = (uint64_t)subset_n;
     const uint64_t tmp = ((c * 4 + 7) & ~7ull) + (c + 1) * 4 + 8 + (c + 1) * 8 + WBINS * 8 + c;
-    return 2 * dev_round(flag_bytes(g)) + 4 * dev_round(sub_stream_cap(g, q) * 4) + dev_round(sub_list_cap(g, q) * 4) +
+    return 2 * dev_round(flag_bytes(g)) + 6 * dev_round(sub_stream_cap(g, q) * 4) + 3 * dev_round(sub_list_cap(g, q) * 4) +
            dev_round(tmp);
 }
 uint64_t query_bytes(const tt_graph *g, const QueryCtx *q, uint32_t k, uint32_t subset_n) {
@@ -504,7 +540,8 @@ uint64_t query_bytes(const tt_graph *g, const QueryCtx *q, uint32_t k, uint32_t 
 // Device bytes a context holds now.
 uint64_t ctx_bytes(const QueryCtx *q) {
     const void *ptrs[] = {q->buf0, q->buf1, q->cand, q->ccnt, q->spart, q->dcount, q->dout, q->vflag, q->vflag2,
-                          q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_vlist, q->heavy, q->nheavy,
+                          q->sub_src, q->sub_col, q->sub_wgt, q->sub_pos, q->sub_vlist, q->sp_c, q->sp_w,
+                          q->sp_start, q->sp_cnt, q->heavy, q->nheavy,
                           q->hpiece};
     uint64_t b = 0;
     for (const void *p : ptrs) b += dev_bytes(p);
@@ -820,6 +857,12 @@ int launch_enum(const tt_graph *g, QueryCtx *q, const Band &B, int filter, bool 
     A.emark = g->emark;
     A.vflag = q->vflag;
     A.vflag2 = q->vflag2;
+    if (q->sub_active) { // the compact subset stream carries the lists of heads in the subset
+        A.sp_c = q->sp_c;
+        A.sp_w = q->sp_w;
+        A.sp_start = q->sp_start;
+        A.sp_cnt = q->sp_cnt;
+    }
     A.out = q->buf0;
     A.count = q->dcount;
     A.cap = q->buf_cap;
@@ -1126,7 +1169,10 @@ int prepare_subset(tt_graph *g, QueryCtx *q, const uint32_t *subset, uint32_t cn
             (rc = dev_alloc(nullptr, (void **)&q->sub_col, scap * 4)) ||
             (rc = dev_alloc(nullptr, (void **)&q->sub_wgt, scap * 4)) ||
             (rc = dev_alloc(nullptr, (void **)&q->sub_pos, scap * 4)) ||
-            (rc = dev_alloc(nullptr, (void **)&q->sub_vlist, vcap * 4)))
+            (rc = dev_alloc(nullptr, (void **)&q->sub_vlist, vcap * 4)) ||
+            (rc = dev_alloc(nullptr, (void **)&q->sp_c, scap * 4)) || (rc = dev_alloc(nullptr, (void **)&q->sp_w, scap * 4)) ||
+            (rc = dev_alloc(nullptr, (void **)&q->sp_start, vcap * 4)) ||
+            (rc = dev_alloc(nullptr, (void **)&q->sp_cnt, vcap * 4)))
             return rc;
     }
     // per-query scratch: ids[cnt] | lens[cnt+1] | pre[cnt+1] (u64) | hist[WBINS] (u64) | own[cnt]
@@ -1144,7 +1190,7 @@ int prepare_subset(tt_graph *g, QueryCtx *q, const uint32_t *subset, uint32_t cn
     auto body = [&]() -> int {
         HIP_TRY(hipMemsetAsync(q->vflag, 0, flag_bytes(g), s));
         HIP_TRY(hipMemsetAsync(q->vflag2, 0, flag_bytes(g), s));
-        HIP_TRY(hipMemsetAsync(cnt8, 0, 3 * sizeof(unsigned long long), s));
+        HIP_TRY(hipMemsetAsync(cnt8, 0, 4 * sizeof(unsigned long long), s));
         HIP_TRY(hipMemsetAsync(hist, 0, WBINS * 8, s));
         HIP_TRY(hipMemcpyAsync(ids, subset, (uint64_t)cnt * 4, hipMemcpyHostToDevice, s));
         k_sub_mark<<<(cnt + 1 + 255) / 256, 256, 0, s>>>(ids, cnt, g->irstart, g->rlen, q->vflag, own, lens, cnt8);
@@ -1163,7 +1209,8 @@ int prepare_subset(tt_graph *g, QueryCtx *q, const uint32_t *subset, uint32_t cn
         if (nv > vcap || bound > SUB_SCAN_MUL * scap) return TT_OK;
         k_sub_rows<<<num_cus() * 8, 256, 0, s>>>(ids, own, cnt, q->sub_vlist, (uint32_t)nv, g->rstart, g->rlen,
                                                  g->col, g->wgt, q->vflag, q->vflag2, q->sub_src, q->sub_col,
-                                                 q->sub_wgt, q->sub_pos, scap, cnt8, hist);
+                                                 q->sub_wgt, q->sub_pos, scap, q->sp_c, q->sp_w, q->sp_start,
+                                                 q->sp_cnt, cnt8, hist);
         HIP_TRY(hipGetLastError());
         q->sub_hist.assign(WBINS, 0);
         HIP_TRY(hipMemcpyAsync(q->sub_hist.data(), hist, WBINS * 8, hipMemcpyDeviceToHost, s));
