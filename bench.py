@@ -101,6 +101,88 @@ def single_breakdown(reqs, ms, res):
                 **{"mean_" + f: g[f] / g["n"] for f in fields}} for k, g in sorted(groups.items())}
 
 
+def run_methods(args):
+    """The paper's other methods on the 1M-vertex workload (top-1000 at p = 1): edge sampling
+    (Alg. 3), wedge and path sampling (Algs. 4, 5) at growing budgets, static heavy-light (Alg. 1)
+    at growing heavy fractions, each timed on the GPU with the fraction of the exact top-k it
+    returns; DHL and Auto-HL (Alg. 2) on the host; and the clique extension (Sec. 4.5) on a
+    30K-vertex graph with planted 5-cliques, sampled against its exact top cliques."""
+    import torch
+    import graphgen
+    import paper_1910_00692_amd as tt
+    from paper_1910_00692_amd import dhl
+
+    torch.cuda.init()
+    k, p = 1000, 1.0
+    g = graphgen.medium()
+    G = tt.Graph(g.n, g.src, g.dst, g.w)
+
+    def timed(fn, reps=3):
+        fn()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        return (time.perf_counter() - t) * 1e3 / reps, r
+
+    def tri_set(r):
+        return set(zip(r["i"].tolist(), r["j"].tolist(), r["l"].tolist()))
+
+    ms_exact, exact = timed(lambda: G.topk(k, p))
+    ref = tri_set(exact)
+
+    def acc(r):
+        return len(tri_set(r) & ref) / len(ref)
+
+    out = {"metric": "paper's methods: time and fraction of the exact top-k found", "unit": "ms", "n_gpus": 1,
+           "data": "synthetic", "higher_is_better": False,
+           "config": {"workload": "chung-lu n=1M m~20M gamma2.1 zipf(1.8) +50 planted K4 x1000 seed0; top-1000 at p=1",
+                      "n": g.n, "m": g.m, "k": k, "p": p},
+           "exact_gpu_ms": ms_exact, "edge_sampling": [], "wedge_sampling": [], "path_sampling": [], "shl": []}
+    for budget in (100_000, 1_000_000, 10_000_000):
+        ms, r = timed(lambda: G.sample(k, p, budget, seed=5))
+        out["edge_sampling"].append({"budget": budget, "ms": ms, "accuracy": acc(r)})
+        for scheme in ("wedge", "path"):
+            ms, r = timed(lambda: G.sample_by(scheme, k, p, budget, seed=5))
+            out[scheme + "_sampling"].append({"budget": budget, "ms": ms, "accuracy": acc(r),
+                                              "distinct_triangles": r["distinct"]})
+        print(f"[bench] samplers at budget {budget} done", file=sys.stderr, flush=True)
+    wsorted = np.sort(g.w)[::-1]
+    for f in (0.001, 0.01, 0.1, 0.5):
+        tau = int(wsorted[max(int(f * len(wsorted)) - 1, 0)]) - 1
+        ms, r = timed(lambda: G.shl(k, p, tau))
+        out["shl"].append({"heavy_fraction": f, "tau": tau, "heavy_edges": r["heavy_edges"], "ms": ms,
+                           "accuracy": acc(r)})
+    G.close()
+    nthreads = min(16, os.cpu_count() or 1)
+    out["dhl_cpu"] = {}
+    for name, alpha in (("dhl_alpha_1.25", 1.25), ("auto_hl", 0.0)):
+        t = time.perf_counter()
+        r = dhl.topk(g.n, g.src, g.dst, g.w, k, p, alpha, threads=nthreads)
+        out["dhl_cpu"][name] = {"ms": (time.perf_counter() - t) * 1e3, "threads": nthreads,
+                                "equals_gpu_exact": bool(np.array_equal(r["i"], exact["i"]) and
+                                                         np.array_equal(r["j"], exact["j"]) and
+                                                         np.array_equal(r["l"], exact["l"]) and
+                                                         np.array_equal(r["score"], exact["score"]))}
+    print("[bench] dhl done", file=sys.stderr, flush=True)
+    h = graphgen.chung_lu(5000, 60000, 2.5, 1.8, seed=51, plant=6, plant_size=5, plant_mult=1000)
+    H = tt.Graph(h.n, h.src, h.dst, h.w)
+    out["cliques"] = {"graph": "chung-lu n=5K m~60K gamma2.5 zipf(1.8) +6 planted K5 x1000 seed51",
+                      "size": 5, "k": 20, "p": p, "runs": []}
+    try:
+        ms, ex = timed(lambda: H.cliques(5, 20, p, all_edges=True))
+        cref = set(map(tuple, ex["v"].tolist()))
+        out["cliques"]["exact_ms"] = ms
+        for budget in (1_000, 10_000, 100_000):
+            ms, r = timed(lambda: H.cliques(5, 20, p, budget=budget, seed=9))
+            got = set(map(tuple, r["v"].tolist()))
+            out["cliques"]["runs"].append({"budget": budget, "ms": ms,
+                                           "accuracy": len(got & cref) / max(len(cref), 1)})
+    except tt.TopKError as e:  # more common neighbours than the clique kernel holds
+        out["cliques"]["error"] = str(e)
+    H.close()
+    print(json.dumps(out), flush=True)
+
+
 def run_serve(args):
     """Served workload: a resident n=10M, ~200M-edge graph and a Poisson request stream (mean
     2,000 req/s; k log-uniform in [10, 1e4]; p from {-inf, -1, 0, 1, 2, +inf}; 20% restricted
@@ -298,7 +380,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS) + ["serve", "batch"])
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS) + ["serve", "batch", "methods"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sampling", action="store_true", help="exact queries only")
     ap.add_argument("--no-warm", action="store_true",
@@ -326,6 +408,8 @@ def main():
         return run_serve(args)
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "methods":
+        return run_methods(args)
 
     import graphgen
 
@@ -535,8 +619,9 @@ def cpu_baseline_timeboxed(g, gen, k, budget_s, nthreads):
     (the value is then an upper bound, as the paper reports a run that did not finish); beside it
     the oracle on vertex samples (every vertex kept with probability f, the graph's IDs being a
     random permutation: the vertices with ID < f n) at f = 0.1 and 0.15, extrapolated to f = 1
-    with t(f) = a f^2 + b f^3 (building the adjacency grows with the edges, f^2; enumeration with
-    the wedges and triangles, f^3), and the f = 0.1 sample on one thread."""
+    by the triangles it enumerates (it lists every triangle: the samples hold T(1) f^3 of them, so
+    T(1) is estimated from each sample, and the time per triangle is the larger sample's), and
+    the f = 0.1 sample on one thread."""
     import multiprocessing as mp
     import oracle
     ctx = mp.get_context("spawn")
@@ -578,11 +663,9 @@ def cpu_baseline_timeboxed(g, gen, k, budget_s, nthreads):
     oracle.topk(g.n, s, d, w, k, 1.0, nthreads=1)
     one_thread = time.perf_counter() - t
     (f1, (t1, m1, T1)), (f2, (t2, m2, T2)) = sorted(samples.items())
-    # t = a f^2 + b f^3 through both points
-    b = (t2 / f2 ** 2 - t1 / f1 ** 2) / (f2 - f1)
-    a = t1 / f1 ** 2 - b * f1
-    a, b = max(a, 0.0), max(b, 0.0)
-    extrap = a + b if a + b > 0 else max(t1 / f1 ** 3, t2 / f2 ** 3)
+    T_est = 0.5 * (T1 / f1 ** 3 + T2 / f2 ** 3)  # the two estimates agree within a few percent
+    ns_per_triangle = t2 / max(T2, 1) * 1e9
+    extrap = T_est * ns_per_triangle * 1e-9
     if whole:
         value, desc = 1.0 / whole[0], f"one exact top-{k} query at p=1 on the whole graph ({whole[1]} triangles), " \
                                       f"{whole[0]:.1f}s"
@@ -595,6 +678,8 @@ def cpu_baseline_timeboxed(g, gen, k, budget_s, nthreads):
             "vertex_samples": [{"f": f, "edges": m_, "triangles": T_, "s": t_}
                                for f, (t_, m_, T_) in sorted(samples.items())],
             "extrapolated_s_per_query": extrap, "extrapolated_queries_per_s": 1.0 / extrap,
+            "triangles_estimate": T_est, "triangles_estimates_per_sample": [T1 / f1 ** 3, T2 / f2 ** 3],
+            "ns_per_triangle": ns_per_triangle,
             "paper_method_on_sample": dhl_on_sample,
             "one_thread": {"f": 0.1, "s": one_thread, "threads_speedup": one_thread / samples[0.1][0]}}
 
