@@ -189,9 +189,10 @@ def run_serve(args):
     to triangles touching 1,000 random vertices), submitted at its arrival times to the
     continuous-batching server; compared with the same requests run one at a time."""
     import threading
-    # one hardware queue per server slot, so the slots' streams do not share queues (HIP reads
-    # this when the runtime starts, i.e. before torch touches the GPU; the default is 4)
-    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(4, args.slots)))
+    # two hardware queues per server slot, so the slots' streams share no queue with each other or
+    # with the runtime's own copies (HIP reads this when the runtime starts, i.e. before torch
+    # touches the GPU; the default is 4)
+    os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues or min(32, max(4, 2 * args.slots)))
     import torch
     import graphgen
     import paper_1910_00692_amd as tt
@@ -388,7 +389,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device 3 times (a kernel of known traffic for counter runs)")
     ap.add_argument("--requests", type=int, default=2000, help="served workload: number of requests")
-    ap.add_argument("--slots", type=int, default=8, help="served workload: server slots")
+    ap.add_argument("--slots", type=int, default=4, help="served workload: server slots")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="served workload: hardware queues of the process (default: two per slot, 4 to 32)")
     ap.add_argument("--budget-gb", type=int, default=16, help="served workload: scratch budget (GiB)")
     ap.add_argument("--serve-n", type=int, default=10_000_000)
     ap.add_argument("--serve-m", type=int, default=200_000_000)
