@@ -93,7 +93,7 @@ struct QueryCtx {
     // for each listed in-neighbour u (by its index in sub_vlist): its out-neighbours c in the
     // subset and the weights of u->c, as a run [sp_start, sp_start + sp_cnt) of sp_c / sp_w
     uint32_t *sp_c = nullptr, *sp_w = nullptr, *sp_start = nullptr, *sp_cnt = nullptr;
-    uint64_t sub_cap = 1ull << 22;         // capacity of the compact stream and of the list
+    uint64_t sub_cap = 1ull << 24;         // capacity of the compact stream and of the list
     uint64_t sub_len = 0;                  // entries in the compact stream
     bool sub_active = false;               // the passes stream the compact list
     std::vector<uint64_t> sub_hist;        // host: its entries per weight_bin(w)
