@@ -161,18 +161,40 @@ namespace {
 
 constexpr uint32_t F_RANGE = 1, F_LOOP = 2, F_ZERO = 4, F_DUP = 8;
 
+// Validation, and the histogram of the weights by weight_bin (the graph's weight bins: the
+// entries hold the same multiset of weights).  Four edges per thread in flight; an LDS
+// histogram per block, flushed with one global atomic per non-empty bin.
 __global__ __launch_bounds__(256) void k_validate(const uint32_t *src, const uint32_t *dst, const uint32_t *w,
-                                                  uint64_t m, uint32_t n, uint32_t *flags) {
+                                                  uint64_t m, uint32_t n, uint32_t *flags,
+                                                  unsigned long long *hist) {
+    __shared__ uint32_t h[WBINS];
+    for (int t = threadIdx.x; t < WBINS; t += blockDim.x) h[t] = 0;
+    __syncthreads();
     uint32_t f = 0;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t a = src[e], b = dst[e];
-        if (a >= n || b >= n) f |= F_RANGE;
-        else if (a == b) f |= F_LOOP;
-        if (w[e] == 0) f |= F_ZERO;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < m; e0 += 4 * stride) {
+        uint32_t a[4], b[4], x[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint64_t e = e0 + (uint64_t)i * stride;
+            a[i] = b[i] = x[i] = 0;
+            if (e < m) { a[i] = src[e]; b[i] = dst[e]; x[i] = w[e]; }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+            if (e0 + (uint64_t)i * stride < m) {
+                if (a[i] >= n || b[i] >= n) f |= F_RANGE;
+                else if (a[i] == b[i]) f |= F_LOOP;
+                if (x[i] == 0) f |= F_ZERO;
+                atomicAdd(&h[weight_bin(x[i])], 1u);
+            }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) f |= __shfl_xor(f, o, 64);
     if ((threadIdx.x & 63) == 0 && f) atomicOr(flags, f);
+    __syncthreads();
+    for (int t = threadIdx.x; t < WBINS; t += blockDim.x)
+        if (h[t]) atomicAdd(&hist[t], (unsigned long long)h[t]);
 }
 
 // Wave-level merging of atomics: in grid-stride loops the valid lanes are a prefix of the wave,
@@ -737,8 +759,9 @@ constexpr int RANK_ITEMS = 2;        // window of RANK_ITEMS * 64 entries per wa
 __device__ __forceinline__ void put_entry(uint64_t P, uint32_t r1, uint32_t r2, uint32_t t, uint32_t c, uint32_t w,
                                           uint32_t d, uint32_t hm, uint32_t *col, uint32_t *wgt, uint32_t *eid,
                                           uint32_t *osrc, uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
-                                          uint32_t *hmx) {
+                                          uint32_t *hmx, uint2 *cw) {
     col[P + r1] = c;
+    cw[P + r1] = make_uint2(c, w);
     if (hmx) hmx[P + r1] = hm;
     wgt[P + r1] = w;
     eid[P + r1] = d;
@@ -802,7 +825,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
                                                     const uint64_t *rstart, const uint32_t *rlen, uint32_t *col,
                                                     uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
                                                     uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos, uint32_t *flags,
-                                                    const uint32_t *hm0, uint32_t *hmx) {
+                                                    const uint32_t *hm0, uint32_t *hmx, uint2 *cw) {
     __shared__ uint32_t sc[4][RANK_ITEMS * 64], sw[4][RANK_ITEMS * 64];
     const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
     const uint64_t nw = (m + 63) / 64;
@@ -847,7 +870,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
                 r2 += wf > wt[k] || (wf == wt[k] && before_id);
                 dup |= cf == c[k] && f != me;
             }
-            put_entry(P[k], r1, r2, t[k], c[k], wt[k], d[k], hv[k], col, wgt, eid, osrc, wcol, wwgt, wpos, hmx);
+            put_entry(P[k], r1, r2, t[k], c[k], wt[k], d[k], hv[k], col, wgt, eid, osrc, wcol, wwgt, wpos, hmx, cw);
         }
         __syncthreads();
     }
@@ -907,7 +930,7 @@ __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P,
                                              uint32_t *sc, uint32_t *sw, uint32_t *sd, uint32_t *hc, uint32_t *hw,
                                              uint64_t *xch, uint32_t *col, uint32_t *wgt, uint32_t *eid,
                                              uint32_t *osrc, uint32_t *wcol, uint32_t *wwgt,
-                                             uint32_t *wpos, const uint32_t *hm0, uint32_t *hmx, bool &dup) {
+                                             uint32_t *wpos, const uint32_t *hm0, uint32_t *hmx, uint2 *cw, bool &dup) {
     const uint32_t t = threadIdx.x;
     uint64_t k[R];
 #pragma unroll
@@ -931,6 +954,7 @@ __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P,
             const uint32_t i = (uint32_t)k[r], c = sc[i], w = sw[i], d = sd[i];
             col[P + s] = c;
             wgt[P + s] = w;
+            cw[P + s] = make_uint2(c, w);
             eid[P + s] = d;
             osrc[P + s] = u;
             if (hmx) hmx[P + s] = hm0[b + i];
@@ -963,7 +987,7 @@ __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t 
                                                   const uint64_t *rowp0, const uint64_t *rstart, const uint32_t *rlen,
                                                   uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
                                                   uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
-                                                  uint32_t *flags, const uint32_t *hm0, uint32_t *hmx) {
+                                                  uint32_t *flags, const uint32_t *hm0, uint32_t *hmx, uint2 *cw) {
     static_assert(MID_MAX == 1024, "rows are sorted as up to 4 keys per thread");
     __shared__ uint32_t sc[MID_MAX], sw[MID_MAX], sd[MID_MAX], hc[MID_MAX], hw[MID_MAX];
     __shared__ uint64_t xch[MID_MAX];
@@ -972,11 +996,14 @@ __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t 
         const uint32_t u = mid[bi], len = rlen[u];
         const uint64_t b = rowp0[u], P = rstart[u];
         if (len <= 256)
-            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
+            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, cw,
+                            dup);
         else if (len <= 512)
-            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
+            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, cw,
+                            dup);
         else
-            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
+            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, cw,
+                            dup);
     }
     if (__ballot(dup) && (threadIdx.x & 63) == 0) atomicOr(flags, F_DUP);
 }
@@ -1003,15 +1030,16 @@ __global__ __launch_bounds__(256) void k_move_big(const uint32_t *big, uint32_t 
 __global__ __launch_bounds__(256) void k_post_big(const uint32_t *big, uint32_t nbig, const uint64_t *rstart,
                                                   const uint32_t *rlen, const uint32_t *col, const uint32_t *wgt,
                                                   uint64_t *wkey, uint32_t *wpos, uint32_t *flags,
-                                                  const uint32_t *maxw, uint32_t *hmx) {
+                                                  const uint32_t *maxw, uint32_t *hmx, uint2 *cw) {
     bool dup = false;
     for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
         const uint32_t u = big[bi];
         const uint64_t b = rstart[u];
         for (uint32_t t = threadIdx.x; t < rlen[u]; t += blockDim.x) {
-            const uint32_t c = col[b + t];
+            const uint32_t c = col[b + t], w = wgt[b + t];
             if (t > 0 && col[b + t - 1] == c) dup = true;
-            wkey[b + t] = ((uint64_t)(~wgt[b + t]) << 32) | c; // ascending = weight desc, then ID
+            cw[b + t] = make_uint2(c, w);
+            wkey[b + t] = ((uint64_t)(~w) << 32) | c; // ascending = weight desc, then ID
             wpos[b + t] = (uint32_t)(b + t);
             if (hmx) hmx[b + t] = maxw[c];
         }
@@ -1075,29 +1103,6 @@ __global__ __launch_bounds__(256) void k_place_entries(const uint32_t *osrc, con
             if (hmx) ws_hmx[d] = hmx[e];
         }
     }
-}
-
-// Four weights per thread in flight (a few blocks per CU run this, so that each bin's global
-// counter takes few atomics; their loads would otherwise wait one at a time).
-__global__ __launch_bounds__(256) void k_weight_hist(const uint32_t *wgt, uint64_t m, unsigned long long *hist) {
-    __shared__ uint32_t h[WBINS];
-    for (int t = threadIdx.x; t < WBINS; t += blockDim.x) h[t] = 0;
-    __syncthreads();
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < m; e0 += 4 * stride) {
-        uint32_t w[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const uint64_t e = e0 + (uint64_t)i * stride;
-            w[i] = e < m ? wgt[e] : 0u;
-        }
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-            if (e0 + (uint64_t)i * stride < m) atomicAdd(&h[weight_bin(w[i])], 1u);
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < WBINS; t += blockDim.x)
-        if (h[t]) atomicAdd(&hist[t], (unsigned long long)h[t]);
 }
 
 unsigned grid_for(uint64_t items, unsigned per_block = 256) {
@@ -1211,10 +1216,6 @@ __global__ __launch_bounds__(256) void k_pack_vinfo(const uint64_t *rstart, cons
         vi[v] = VInfo{rstart[v], rlen[v], maxw[v]};
 }
 
-__global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint32_t *wgt, uint64_t m, uint2 *cw) {
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
-        cw[e] = make_uint2(col[e], wgt[e]);
-}
 
 } // namespace
 
@@ -1266,9 +1267,11 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     Scratch S;
     S.stream = s;
     uint32_t *flags = nullptr;
-    if ((rc = S.get((void **)&flags, 16))) return rc;
+    unsigned long long *hist = nullptr; // entries per weight_bin, made by the validation pass
+    if ((rc = S.get((void **)&flags, 16)) || (rc = S.get((void **)&hist, WBINS * 8))) return rc;
     HIP_TRY(hipMemsetAsync(flags, 0, 16, s));
-    if (m) k_validate<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, n, flags);
+    HIP_TRY(hipMemsetAsync(hist, 0, WBINS * 8, s));
+    if (m) k_validate<<<std::min<unsigned>(grid_for(m), (unsigned)num_cus() * 4), 256, 0, s>>>(src, dst, w, m, n, flags, hist);
     uint32_t hf[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1362,6 +1365,8 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     // The per-entry head maxima pay only where the row maxima no longer stay in the caches
     // (then the filter's gather of maxw[v] misses to HBM for nearly every streamed entry).  They
     // are gathered once, in record order, and placed by the row ranking with their entries.
+    // (head, weight) pairs of the head-sorted rows, written by the row ranking with the entries
+    if ((rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8))) return rc;
     uint32_t *hm0 = nullptr;
     if (n >= HMX_MIN_N &&
         ((rc = dev_alloc(g, (void **)&g->hmx, (m + 1) * 4)) || (rc = S.get((void **)&hm0, (m + 1) * 4))))
@@ -1391,7 +1396,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     }
     // both row orders: counted ranks for rows up to MID_MAX entries, sorts for longer ones
     if (m) k_rank_small<<<grid_for(m), 256, 0, s>>>(rec0, rowp0, m, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                                    g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
+                                                    g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx, g->cw);
     HIP_TRY(hipMemsetAsync(flags + 1, 0, 8, s));
     if (n) k_list_long<<<grid_for(n, 4096), 256, 0, s>>>(g->rlen, n, mid, flags + 2, big, flags + 1);
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
@@ -1400,7 +1405,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     if (nmid) {
         const unsigned gm = nmid < 8192u ? nmid : 8192u;
         k_rank_mid<<<gm, 256, 0, s>>>(mid, nmid, rec0, rowp0, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                      g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
+                                      g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx, g->cw);
     }
     if (nbig) {
         const unsigned gb = nbig < 4096u ? nbig : 4096u;
@@ -1409,17 +1414,13 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         uint64_t *wkey = nullptr;
         if ((rc = S.get((void **)&wkey, (m + 1) * 8))) return rc;
         k_post_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, g->col, g->wgt, wkey, g->wpos, flags, g->maxw,
-                                      g->hmx);
+                                      g->hmx, g->cw);
         if ((rc = sort_big<uint64_t>(g, S, g->rstart, g->rlen, big, nbig, wkey, g->wpos, nullptr))) return rc;
         k_split_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, wkey, g->wcol, g->wwgt);
         S.drop(wkey);
     }
     HIP_TRY(hipStreamSynchronize(s));
     S.drop(rec0);
-    unsigned long long *hist = nullptr;
-    if ((rc = S.get((void **)&hist, WBINS * 8))) return rc;
-    HIP_TRY(hipMemsetAsync(hist, 0, WBINS * 8, s));
-    if (m) k_weight_hist<<<std::min<unsigned>(grid_for(m), (unsigned)num_cus() * 4), 256, 0, s>>>(g->wgt, m, hist);
     g->whist.assign(WBINS, 0);
     HIP_TRY(hipMemcpyAsync(g->whist.data(), hist, WBINS * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
@@ -1443,10 +1444,8 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         for (int b = WBINS - 1; b >= 0; b--) { g->wbase[b] = run; run += g->whist[b]; }
     }
     // (the stream itself is placed by the first query that streams it: ensure_weight_stream)
-    if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo))) || (rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8)))
-        return rc;
+    if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo)))) return rc;
     k_pack_vinfo<<<grid_for(nn), 256, 0, s>>>(g->rstart, g->rlen, g->maxw, nn, g->vinfo);
-    if (m) k_pack_cw<<<grid_for(m), 256, 0, s>>>(g->col, g->wgt, m, g->cw);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
     return TT_OK;
