@@ -759,9 +759,8 @@ constexpr int RANK_ITEMS = 2;        // window of RANK_ITEMS * 64 entries per wa
 __device__ __forceinline__ void put_entry(uint64_t P, uint32_t r1, uint32_t r2, uint32_t t, uint32_t c, uint32_t w,
                                           uint32_t d, uint32_t hm, uint32_t *col, uint32_t *wgt, uint32_t *eid,
                                           uint32_t *osrc, uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
-                                          uint32_t *hmx, uint2 *cw) {
+                                          uint32_t *hmx) {
     col[P + r1] = c;
-    cw[P + r1] = make_uint2(c, w);
     if (hmx) hmx[P + r1] = hm;
     wgt[P + r1] = w;
     eid[P + r1] = d;
@@ -825,7 +824,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
                                                     const uint64_t *rstart, const uint32_t *rlen, uint32_t *col,
                                                     uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
                                                     uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos, uint32_t *flags,
-                                                    const uint32_t *hm0, uint32_t *hmx, uint2 *cw) {
+                                                    const uint32_t *hm0, uint32_t *hmx) {
     __shared__ uint32_t sc[4][RANK_ITEMS * 64], sw[4][RANK_ITEMS * 64];
     const int lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
     const uint64_t nw = (m + 63) / 64;
@@ -870,7 +869,7 @@ __global__ __launch_bounds__(256) void k_rank_small(const uint4 *rec0, const uin
                 r2 += wf > wt[k] || (wf == wt[k] && before_id);
                 dup |= cf == c[k] && f != me;
             }
-            put_entry(P[k], r1, r2, t[k], c[k], wt[k], d[k], hv[k], col, wgt, eid, osrc, wcol, wwgt, wpos, hmx, cw);
+            put_entry(P[k], r1, r2, t[k], c[k], wt[k], d[k], hv[k], col, wgt, eid, osrc, wcol, wwgt, wpos, hmx);
         }
         __syncthreads();
     }
@@ -930,7 +929,7 @@ __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P,
                                              uint32_t *sc, uint32_t *sw, uint32_t *sd, uint32_t *hc, uint32_t *hw,
                                              uint64_t *xch, uint32_t *col, uint32_t *wgt, uint32_t *eid,
                                              uint32_t *osrc, uint32_t *wcol, uint32_t *wwgt,
-                                             uint32_t *wpos, const uint32_t *hm0, uint32_t *hmx, uint2 *cw, bool &dup) {
+                                             uint32_t *wpos, const uint32_t *hm0, uint32_t *hmx, bool &dup) {
     const uint32_t t = threadIdx.x;
     uint64_t k[R];
 #pragma unroll
@@ -954,7 +953,6 @@ __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P,
             const uint32_t i = (uint32_t)k[r], c = sc[i], w = sw[i], d = sd[i];
             col[P + s] = c;
             wgt[P + s] = w;
-            cw[P + s] = make_uint2(c, w);
             eid[P + s] = d;
             osrc[P + s] = u;
             if (hmx) hmx[P + s] = hm0[b + i];
@@ -987,7 +985,7 @@ __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t 
                                                   const uint64_t *rowp0, const uint64_t *rstart, const uint32_t *rlen,
                                                   uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
                                                   uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
-                                                  uint32_t *flags, const uint32_t *hm0, uint32_t *hmx, uint2 *cw) {
+                                                  uint32_t *flags, const uint32_t *hm0, uint32_t *hmx) {
     static_assert(MID_MAX == 1024, "rows are sorted as up to 4 keys per thread");
     __shared__ uint32_t sc[MID_MAX], sw[MID_MAX], sd[MID_MAX], hc[MID_MAX], hw[MID_MAX];
     __shared__ uint64_t xch[MID_MAX];
@@ -996,14 +994,11 @@ __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t 
         const uint32_t u = mid[bi], len = rlen[u];
         const uint64_t b = rowp0[u], P = rstart[u];
         if (len <= 256)
-            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, cw,
-                            dup);
+            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
         else if (len <= 512)
-            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, cw,
-                            dup);
+            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
         else
-            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, cw,
-                            dup);
+            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
     }
     if (__ballot(dup) && (threadIdx.x & 63) == 0) atomicOr(flags, F_DUP);
 }
@@ -1030,16 +1025,15 @@ __global__ __launch_bounds__(256) void k_move_big(const uint32_t *big, uint32_t 
 __global__ __launch_bounds__(256) void k_post_big(const uint32_t *big, uint32_t nbig, const uint64_t *rstart,
                                                   const uint32_t *rlen, const uint32_t *col, const uint32_t *wgt,
                                                   uint64_t *wkey, uint32_t *wpos, uint32_t *flags,
-                                                  const uint32_t *maxw, uint32_t *hmx, uint2 *cw) {
+                                                  const uint32_t *maxw, uint32_t *hmx) {
     bool dup = false;
     for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
         const uint32_t u = big[bi];
         const uint64_t b = rstart[u];
         for (uint32_t t = threadIdx.x; t < rlen[u]; t += blockDim.x) {
-            const uint32_t c = col[b + t], w = wgt[b + t];
+            const uint32_t c = col[b + t];
             if (t > 0 && col[b + t - 1] == c) dup = true;
-            cw[b + t] = make_uint2(c, w);
-            wkey[b + t] = ((uint64_t)(~w) << 32) | c; // ascending = weight desc, then ID
+            wkey[b + t] = ((uint64_t)(~wgt[b + t]) << 32) | c; // ascending = weight desc, then ID
             wpos[b + t] = (uint32_t)(b + t);
             if (hmx) hmx[b + t] = maxw[c];
         }
@@ -1103,6 +1097,11 @@ __global__ __launch_bounds__(256) void k_place_entries(const uint32_t *osrc, con
             if (hmx) ws_hmx[d] = hmx[e];
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint32_t *wgt, uint64_t m, uint2 *cw) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        cw[e] = make_uint2(col[e], wgt[e]);
 }
 
 unsigned grid_for(uint64_t items, unsigned per_block = 256) {
@@ -1365,8 +1364,6 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     // The per-entry head maxima pay only where the row maxima no longer stay in the caches
     // (then the filter's gather of maxw[v] misses to HBM for nearly every streamed entry).  They
     // are gathered once, in record order, and placed by the row ranking with their entries.
-    // (head, weight) pairs of the head-sorted rows, written by the row ranking with the entries
-    if ((rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8))) return rc;
     uint32_t *hm0 = nullptr;
     if (n >= HMX_MIN_N &&
         ((rc = dev_alloc(g, (void **)&g->hmx, (m + 1) * 4)) || (rc = S.get((void **)&hm0, (m + 1) * 4))))
@@ -1396,7 +1393,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     }
     // both row orders: counted ranks for rows up to MID_MAX entries, sorts for longer ones
     if (m) k_rank_small<<<grid_for(m), 256, 0, s>>>(rec0, rowp0, m, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                                    g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx, g->cw);
+                                                    g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
     HIP_TRY(hipMemsetAsync(flags + 1, 0, 8, s));
     if (n) k_list_long<<<grid_for(n, 4096), 256, 0, s>>>(g->rlen, n, mid, flags + 2, big, flags + 1);
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
@@ -1405,7 +1402,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     if (nmid) {
         const unsigned gm = nmid < 8192u ? nmid : 8192u;
         k_rank_mid<<<gm, 256, 0, s>>>(mid, nmid, rec0, rowp0, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                      g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx, g->cw);
+                                      g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
     }
     if (nbig) {
         const unsigned gb = nbig < 4096u ? nbig : 4096u;
@@ -1414,7 +1411,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         uint64_t *wkey = nullptr;
         if ((rc = S.get((void **)&wkey, (m + 1) * 8))) return rc;
         k_post_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, g->col, g->wgt, wkey, g->wpos, flags, g->maxw,
-                                      g->hmx, g->cw);
+                                      g->hmx);
         if ((rc = sort_big<uint64_t>(g, S, g->rstart, g->rlen, big, nbig, wkey, g->wpos, nullptr))) return rc;
         k_split_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, wkey, g->wcol, g->wwgt);
         S.drop(wkey);
@@ -1444,8 +1441,13 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         for (int b = WBINS - 1; b >= 0; b--) { g->wbase[b] = run; run += g->whist[b]; }
     }
     // (the stream itself is placed by the first query that streams it: ensure_weight_stream)
-    if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo)))) return rc;
+    // the (head, weight) pairs are packed after the ranking, once its scratch is returned (made
+    // inside the ranking, their 16 GB on the 2B-edge graph raised the build's peak and the
+    // allocator then had to return cached blocks to the driver in later queries)
+    if ((rc = dev_alloc(g, (void **)&g->vinfo, nn * sizeof(VInfo))) || (rc = dev_alloc(g, (void **)&g->cw, (m + 1) * 8)))
+        return rc;
     k_pack_vinfo<<<grid_for(nn), 256, 0, s>>>(g->rstart, g->rlen, g->maxw, nn, g->vinfo);
+    if (m) k_pack_cw<<<grid_for(m), 256, 0, s>>>(g->col, g->wgt, m, g->cw);
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
     return TT_OK;
