@@ -75,7 +75,7 @@ def recorded_traffic(workload):
     except OSError:
         return None
     h = hashlib.sha256()
-    for f in ("enum.h", "query.hip"):
+    for f in ("enum.h", "query.hip", "common.h"):
         with open(os.path.join(ROOT, "paper_1910_00692_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if fields.get("workload") != workload or fields.get("sources_sha256_16") != h.hexdigest()[:16]:

@@ -73,7 +73,7 @@ struct QueryCtx {
     uint64_t buf_cap = 0;
     struct cand *cand = nullptr;           // candidate entries of the current piece of a pass
     uint64_t cand_cap = 0;
-    uint64_t max_cand = 1ull << 25;        // a pass streams its entries in pieces of this size
+    uint64_t max_cand = 1ull << 27;        // a pass streams its entries in pieces of this size
     uint64_t min_buf = 1ull << 22;         // smallest triangle buffer (records)
     uint32_t *ccnt = nullptr;              // candidates per filter block
     struct Heavy *heavy = nullptr;         // [HEAVY_CAP] heavy candidates of the current piece
