@@ -1064,32 +1064,40 @@ __global__ __launch_bounds__(256) void k_place_entries(const uint32_t *osrc, con
                                                        unsigned long long *bincur, const uint32_t *hmx, uint32_t *ws_src,
                                                        uint32_t *ws_col, uint32_t *ws_wgt, uint32_t *ws_pos,
                                                        uint32_t *ws_hmx) {
+    // counters only for the bins placed by this call, [blo, bhi): a call usually places a few
+    // high bins, and clearing and scanning all 2,048 per block cost more than the block's items
     __shared__ uint32_t lc[WBINS];
     __shared__ unsigned long long lb[WBINS];
-    for (int t = threadIdx.x; t < WBINS; t += blockDim.x) lc[t] = 0;
+    const uint32_t nb = bhi - blo;
+    for (uint32_t t = threadIdx.x; t < nb; t += blockDim.x) lc[t] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * PLACE_ITEMS;
-    uint32_t off[PLACE_ITEMS];
+    uint32_t off[PLACE_ITEMS], bin[PLACE_ITEMS], wv[PLACE_ITEMS]; // bin ~0u: not placed here
 #pragma unroll
     for (int it = 0; it < PLACE_ITEMS; it++) {
         const uint64_t e = base + (uint64_t)it * blockDim.x + threadIdx.x;
         off[it] = 0;
+        bin[it] = ~0u;
+        wv[it] = 0;
         if (e < m) {
-            const uint32_t b = weight_bin(wgt[e]);
-            if (b >= blo && b < bhi) off[it] = atomicAdd(&lc[b], 1u);
+            wv[it] = wgt[e];
+            const uint32_t b = weight_bin(wv[it]);
+            if (b >= blo && b < bhi) {
+                bin[it] = b - blo;
+                off[it] = atomicAdd(&lc[b - blo], 1u);
+            }
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < WBINS; t += blockDim.x)
-        if (lc[t]) lb[t] = binbase[t] + atomicAdd(&bincur[t], (unsigned long long)lc[t]);
+    for (uint32_t t = threadIdx.x; t < nb; t += blockDim.x)
+        if (lc[t]) lb[t] = binbase[blo + t] + atomicAdd(&bincur[blo + t], (unsigned long long)lc[t]);
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < PLACE_ITEMS; it++) {
         const uint64_t e = base + (uint64_t)it * blockDim.x + threadIdx.x;
-        const uint32_t w = e < m ? wgt[e] : 0u;
-        const uint32_t b = weight_bin(w);
-        if (e < m && b >= blo && b < bhi) {
-            const uint64_t d = lb[b] + off[it];
+        const uint32_t w = wv[it];
+        if (bin[it] != ~0u) {
+            const uint64_t d = lb[bin[it]] + off[it];
             ws_src[d] = osrc[e];
             ws_col[d] = col[e];
             ws_wgt[d] = w;
