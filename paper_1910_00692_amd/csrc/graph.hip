@@ -161,12 +161,13 @@ namespace {
 
 constexpr uint32_t F_RANGE = 1, F_LOOP = 2, F_ZERO = 4, F_DUP = 8;
 
-// Validation, and the histogram of the weights by weight_bin (the graph's weight bins: the
-// entries hold the same multiset of weights).  Four edges per thread in flight; an LDS
-// histogram per block, flushed with one global atomic per non-empty bin.
+// Validation, the histogram of the weights by weight_bin (the graph's weight bins: the
+// entries hold the same multiset of weights) and the graph's copy of the weights in input
+// order.  Four edges per thread in flight; an LDS histogram per block, flushed with one global
+// atomic per non-empty bin.
 __global__ __launch_bounds__(256) void k_validate(const uint32_t *src, const uint32_t *dst, const uint32_t *w,
                                                   uint64_t m, uint32_t n, uint32_t *flags,
-                                                  unsigned long long *hist) {
+                                                  unsigned long long *hist, uint32_t *w_copy) {
     __shared__ uint32_t h[WBINS];
     for (int t = threadIdx.x; t < WBINS; t += blockDim.x) h[t] = 0;
     __syncthreads();
@@ -187,6 +188,7 @@ __global__ __launch_bounds__(256) void k_validate(const uint32_t *src, const uin
                 else if (a[i] == b[i]) f |= F_LOOP;
                 if (x[i] == 0) f |= F_ZERO;
                 atomicAdd(&h[weight_bin(x[i])], 1u);
+                w_copy[e0 + (uint64_t)i * stride] = x[i];
             }
     }
 #pragma unroll
@@ -299,7 +301,11 @@ struct PartGeom {
     uint64_t per;           // edges per partition block
 };
 
-constexpr int PART_THREADS = 256;
+// Partition blocks of 512 threads: their LDS (one counter per bucket) allows 4-5 blocks per
+// CU, and the grid has at most 1,024 blocks, so the block size sets the waves in flight.
+constexpr int PART_THREADS = 512;
+// Bucket blocks (one per bucket, 64 KB of LDS per array of per-vertex counters) of 1,024 threads.
+constexpr int BUCKET_THREADS = 1024;
 // Items per thread and loop trip in the partition passes: their loads are issued together
 // (one at a time, each trip waited on its load before the LDS atomic could start).
 constexpr int PART_UNROLL = 4;
@@ -354,7 +360,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_part_ends(const uint32_t *src,
 }
 
 // Degrees of bucket b's vertices from its endpoints ep[off(b, 0) .. off(b + 1, 0)).
-__global__ __launch_bounds__(256) void k_bucket_degree(const uint32_t *ep, const uint64_t *off, uint64_t total,
+__global__ __launch_bounds__(BUCKET_THREADS) void k_bucket_degree(const uint32_t *ep, const uint64_t *off, uint64_t total,
                                                        PartGeom G, uint32_t n, uint32_t *deg) {
     __shared__ uint32_t c[PART_MAX_R];
     const uint32_t b = blockIdx.x, R = 1u << G.rb;
@@ -511,31 +517,42 @@ __global__ __launch_bounds__(PART_THREADS) void k_seg_scatter(const uint32_t *in
     }
 }
 
-// Rows of bucket b: records per tail (row lengths), their exclusive scan from the bucket's
-// first record (row starts, vertex order), then every record at its row's next slot.
-__global__ __launch_bounds__(256) void k_bucket_rows(const uint4 *part, const uint64_t *off, uint64_t m, PartGeom G,
-                                                     uint32_t n, uint32_t *rlen, uint64_t *rowp, uint4 *rec) {
-    __shared__ uint32_t c[PART_MAX_R];
-    __shared__ uint32_t wsum[4];
+// Rows of bucket b: records per tail (row lengths) and the largest weight per tail (row
+// maxima), the lengths' exclusive scan from the bucket's first record (row starts, vertex
+// order), then every record at its row's next slot.
+__global__ __launch_bounds__(BUCKET_THREADS) void k_bucket_rows(const uint4 *part, const uint64_t *off, uint64_t m, PartGeom G,
+                                                     uint32_t n, uint32_t *rlen, uint32_t *maxw, uint64_t *rowp,
+                                                     uint4 *rec) {
+    __shared__ uint32_t c[PART_MAX_R], mx[PART_MAX_R];
+    __shared__ uint32_t wsum[BUCKET_THREADS / 64];
     const uint32_t b = blockIdx.x, R = 1u << G.rb, lane = threadIdx.x & 63, wib = threadIdx.x >> 6;
     const uint64_t base = (uint64_t)b << G.rb;
-    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) c[i] = 0;
+    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) c[i] = mx[i] = 0;
     __syncthreads();
     const uint64_t lo = off[(uint64_t)b * G.nblk], hi = b + 1 < G.nbk ? off[(uint64_t)(b + 1) * G.nblk] : m;
     for (uint64_t j0 = lo + threadIdx.x; j0 < hi; j0 += PART_UNROLL * blockDim.x) {
-        uint32_t x[PART_UNROLL];
+        uint2 x[PART_UNROLL]; // (tail, weight)
 #pragma unroll
         for (int i = 0; i < PART_UNROLL; i++) {
             const uint64_t j = j0 + (uint64_t)i * blockDim.x;
-            if (j < hi) x[i] = part[j].w;
+            if (j < hi) {
+                const uint4 r = part[j];
+                x[i] = make_uint2(r.w, r.y);
+            }
         }
 #pragma unroll
         for (int i = 0; i < PART_UNROLL; i++)
-            if (j0 + (uint64_t)i * blockDim.x < hi) atomicAdd(&c[(uint32_t)(x[i] - base)], 1u);
+            if (j0 + (uint64_t)i * blockDim.x < hi) {
+                const uint32_t t = (uint32_t)(x[i].x - base);
+                atomicAdd(&c[t], 1u);
+                atomicMax(&mx[t], x[i].y);
+            }
     }
     __syncthreads();
+    for (uint32_t i = threadIdx.x; i < R; i += blockDim.x)
+        if (base + i < n) maxw[base + i] = mx[i];
     // thread t owns counters [t*per, t*per + per)
-    const uint32_t per = (R + 255) / 256;
+    const uint32_t per = (R + BUCKET_THREADS - 1) / BUCKET_THREADS;
     uint32_t sum = 0;
     for (uint32_t k = 0; k < per; k++) {
         const uint32_t i = threadIdx.x * per + k;
@@ -816,6 +833,37 @@ template <int R> __device__ __forceinline__ void block_bitonic(uint64_t (&k)[R],
     }
 }
 
+// Ascending bitonic sort of a wave's 64*R keys, lane l holding the keys at positions l + 64 r
+// (r < R <= N): strides of 64 and more pair two registers of one lane, shorter ones two lanes.
+template <int R, int N> __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[N]) {
+    static_assert(R <= N, "keys beyond the array");
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (uint32_t size = 2; size <= 64u * R; size <<= 1) {
+#pragma unroll
+        for (uint32_t s = size >> 1; s > 0; s >>= 1) {
+            if (s >= 64) {
+                const uint32_t rs = s >> 6;
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (r & rs) continue;
+                    const bool asc = ((lane + 64u * r) & size) == 0;
+                    const uint64_t x = k[r], y = k[r | rs];
+                    if ((x > y) == asc) { k[r] = y; k[r | rs] = x; }
+                }
+                continue;
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                const uint64_t o = shfl_xor_u64(k[r], (int)s);
+                const uint32_t i = lane + 64u * r;
+                const bool keep_min = ((i & s) == 0) == ((i & size) == 0);
+                k[r] = keep_min ? min(k[r], o) : max(k[r], o);
+            }
+        }
+    }
+}
+
 // Rows of at most SMALL_MAX entries.  Window w holds the rows that START in entries
 // [64w, 64w+64) of the scatter layout; they end before 64w+128.  A wave stages that 128-entry
 // window (heads and weights) in LDS and every lane counts its entries' ranks (by head ID; by
@@ -981,6 +1029,77 @@ __device__ __forceinline__ void rank_mid_row(uint32_t u, uint64_t b, uint64_t P,
     __syncthreads(); // LDS is reused by the block's next row
 }
 
+// Rows of SMALL_MAX+1 .. WAVE_MID_MAX entries, one per wave: the same two orders as
+// rank_mid_row, sorted in registers (up to four keys per lane) with the row staged in the
+// wave's quarter of the block's LDS arrays.  Every thread of the block calls it (`have` false
+// where the wave has no such row), so that its barriers are uniform.
+constexpr uint32_t WAVE_MID_MAX = 256;
+
+__device__ __forceinline__ void rank_mid_wave(bool have, uint32_t u, uint64_t b, uint64_t P, uint32_t len,
+                                              const uint4 *rec0, uint32_t *sc, uint32_t *sw, uint32_t *sd,
+                                              uint32_t *hc, uint32_t *hw, uint32_t *col, uint32_t *wgt, uint32_t *eid,
+                                              uint32_t *osrc, uint32_t *wcol, uint32_t *wwgt, uint32_t *wpos,
+                                              const uint32_t *hm0, uint32_t *hmx, bool &dup) {
+    const uint32_t lane = threadIdx.x & 63, q = (threadIdx.x >> 6) * WAVE_MID_MAX;
+    uint64_t k[4];
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const uint32_t i = lane + 64u * r;
+        k[r] = ~0ull;
+        if (have && i < len) {
+            const uint4 x = rec0[b + i];
+            sc[q + i] = x.x;
+            sw[q + i] = x.y;
+            sd[q + i] = x.z;
+            k[r] = ((uint64_t)x.x << 32) | i;
+        }
+    }
+    if (have) {
+        if (len <= 128) wave_bitonic<2>(k);
+        else wave_bitonic<4>(k);
+    }
+    __syncthreads(); // the wave's staged row is complete
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const uint32_t s = lane + 64u * r;
+        if (have && s < len) {
+            const uint32_t i = (uint32_t)k[r], c = sc[q + i], w = sw[q + i], d = sd[q + i];
+            col[P + s] = c;
+            wgt[P + s] = w;
+            eid[P + s] = d;
+            osrc[P + s] = u;
+            if (hmx) hmx[P + s] = hm0[b + i];
+            hc[q + s] = c;
+            hw[q + s] = w;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const uint32_t s = lane + 64u * r;
+        const bool in = have && s < len;
+        dup |= in && s + 1 < len && hc[q + s + 1] == hc[q + s];
+        k[r] = in ? (((uint64_t)~hw[q + s] << 32) | s) : ~0ull;
+    }
+    if (have) {
+        if (len <= 128) wave_bitonic<2>(k);
+        else wave_bitonic<4>(k);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const uint32_t s = lane + 64u * r;
+        if (have && s < len) {
+            const uint32_t h = (uint32_t)k[r];
+            wcol[P + s] = hc[q + h];
+            wwgt[P + s] = hw[q + h];
+            wpos[P + s] = (uint32_t)(P + h);
+        }
+    }
+    __syncthreads(); // LDS is reused by the block's next rows
+}
+
+// A block takes the mid rows in groups of four: each row of at most WAVE_MID_MAX entries goes
+// to one wave, then the group's longer rows are ranked by the whole block, one at a time.
 __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t nmid, const uint4 *rec0,
                                                   const uint64_t *rowp0, const uint64_t *rstart, const uint32_t *rlen,
                                                   uint32_t *col, uint32_t *wgt, uint32_t *eid, uint32_t *osrc,
@@ -989,16 +1108,32 @@ __global__ __launch_bounds__(256) void k_rank_mid(const uint32_t *mid, uint32_t 
     static_assert(MID_MAX == 1024, "rows are sorted as up to 4 keys per thread");
     __shared__ uint32_t sc[MID_MAX], sw[MID_MAX], sd[MID_MAX], hc[MID_MAX], hw[MID_MAX];
     __shared__ uint64_t xch[MID_MAX];
+    static_assert(4 * WAVE_MID_MAX <= MID_MAX, "a wave's rows fit its quarter of the arrays");
     bool dup = false;
-    for (uint32_t bi = blockIdx.x; bi < nmid; bi += gridDim.x) {
-        const uint32_t u = mid[bi], len = rlen[u];
-        const uint64_t b = rowp0[u], P = rstart[u];
-        if (len <= 256)
-            rank_mid_row<1>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
-        else if (len <= 512)
-            rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
-        else
-            rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
+    const uint32_t ngrp = (nmid + 3) / 4, wi = threadIdx.x >> 6;
+    for (uint32_t g = blockIdx.x; g < ngrp; g += gridDim.x) {
+        {
+            const uint32_t bi = 4 * g + wi;
+            uint32_t u = 0, len = 0;
+            uint64_t b = 0, P = 0;
+            if (bi < nmid) {
+                u = mid[bi];
+                len = rlen[u];
+                b = rowp0[u];
+                P = rstart[u];
+            }
+            rank_mid_wave(bi < nmid && len <= WAVE_MID_MAX, u, b, P, len, rec0, sc, sw, sd, hc, hw, col, wgt, eid,
+                          osrc, wcol, wwgt, wpos, hm0, hmx, dup);
+        }
+        for (uint32_t j = 0; j < 4 && 4 * g + j < nmid; j++) { // block-uniform
+            const uint32_t u = mid[4 * g + j], len = rlen[u];
+            if (len <= WAVE_MID_MAX) continue;
+            const uint64_t b = rowp0[u], P = rstart[u];
+            if (len <= 512)
+                rank_mid_row<2>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
+            else
+                rank_mid_row<4>(u, b, P, len, rec0, sc, sw, sd, hc, hw, xch, col, wgt, eid, osrc, wcol, wwgt, wpos, hm0, hmx, dup);
+        }
     }
     if (__ballot(dup) && (threadIdx.x & 63) == 0) atomicOr(flags, F_DUP);
 }
@@ -1275,10 +1410,14 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     S.stream = s;
     uint32_t *flags = nullptr;
     unsigned long long *hist = nullptr; // entries per weight_bin, made by the validation pass
-    if ((rc = S.get((void **)&flags, 16)) || (rc = S.get((void **)&hist, WBINS * 8))) return rc;
+    if ((rc = S.get((void **)&flags, 16)) || (rc = S.get((void **)&hist, WBINS * 8)) ||
+        (rc = dev_alloc(g, (void **)&g->in_w, (m + 1) * 4)))
+        return rc;
     HIP_TRY(hipMemsetAsync(flags, 0, 16, s));
     HIP_TRY(hipMemsetAsync(hist, 0, WBINS * 8, s));
-    if (m) k_validate<<<std::min<unsigned>(grid_for(m), (unsigned)num_cus() * 4), 256, 0, s>>>(src, dst, w, m, n, flags, hist);
+    if (m)
+        k_validate<<<std::min<unsigned>(grid_for(m), (unsigned)num_cus() * 4), 256, 0, s>>>(src, dst, w, m, n, flags,
+                                                                                            hist, g->in_w);
     uint32_t hf[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1296,7 +1435,7 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         (rc = dev_alloc(g, (void **)&g->wgt, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->osrc, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->eid, (m + 1) * 4)) ||
         (rc = dev_alloc(g, (void **)&g->wcol, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->wwgt, (m + 1) * 4)) ||
-        (rc = dev_alloc(g, (void **)&g->wpos, (m + 1) * 4)) || (rc = dev_alloc(g, (void **)&g->in_w, (m + 1) * 4)) ||
+        (rc = dev_alloc(g, (void **)&g->wpos, (m + 1) * 4)) ||
         (rc = S.get((void **)&big, nn * 4)) ||
         (rc = S.get((void **)&mid, nn * 4)) || (rc = S.get((void **)&rowp0, (nn + 1) * 8)) ||
         (rc = S.get((void **)&rec0, (m + 1) * 16)))
@@ -1304,7 +1443,6 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     HIP_TRY(hipMemsetAsync(g->deg, 0, nn * 4, s));
     HIP_TRY(hipMemsetAsync(g->rlen, 0, nn * 4, s));
     HIP_TRY(hipMemsetAsync(g->maxw, 0, nn * 4, s));
-    if (m) HIP_TRY(hipMemcpyAsync(g->in_w, w, m * 4, hipMemcpyDeviceToDevice, s));
     // rows in vertex order first (unsorted), rowp0[n] = m
     const PartGeom PG = part_geometry(n, m);
     if (m && PG.nbk <= PART_MAX_BUCKETS && (1u << PG.rb) <= PART_MAX_R) {
@@ -1345,14 +1483,15 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
             if (ends32) k_seg_scatter<uint32_t><<<E2.nblk, PART_THREADS, 0, s>>>(ep1, 2 * m, E2, off, (uint32_t *)grouped);
             else k_seg_scatter<unsigned long long><<<E2.nblk, PART_THREADS, 0, s>>>(ep1, 2 * m, E2, off, (uint32_t *)grouped);
         }
-        k_bucket_degree<<<PE.nbk, 256, 0, s>>>((const uint32_t *)grouped, off, 2 * m, PE, n, g->deg);
+        k_bucket_degree<<<PE.nbk, BUCKET_THREADS, 0, s>>>((const uint32_t *)grouped, off, 2 * m, PE, n, g->deg);
         // records in one level (a second level measured no faster for the 16-byte records).
         // The weight-sorted head array holds each edge's tail until the row ranking fills it.
         k_part_count_tails<<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, g->deg, g->wcol, M);
         if ((rc = exclusive_scan_u32_to_u64(M, off, (uint64_t)PG.nbk * PG.nblk, s, nullptr, scan_tmp))) return rc;
         if (m < (1ull << 32)) k_part_edges<uint32_t><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
         else k_part_edges<unsigned long long><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
-        k_bucket_rows<<<PG.nbk, 256, 0, s>>>((const uint4 *)grouped, off, m, PG, n, g->rlen, rowp0, rec0);
+        k_bucket_rows<<<PG.nbk, BUCKET_THREADS, 0, s>>>((const uint4 *)grouped, off, m, PG, n, g->rlen, g->maxw, rowp0,
+                                                         rec0);
         HIP_TRY(hipGetLastError());
     } else {
         if (m) {
@@ -1366,8 +1505,8 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
             (rc = exclusive_scan_u32_to_u64(g->rlen, rowp0, nn, s, nullptr, scan_tmp)))
             return rc;
         if (m) k_scatter<<<grid_for(m), 256, 0, s>>>(src, dst, w, m, g->wcol, g->wwgt, rowp0, rec0);
+        if (m) k_row_max<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw); // (the bucket pass makes them above)
     }
-    if (m) k_row_max<<<grid_for(m), 256, 0, s>>>(rec0, m, g->maxw);
     HIP_TRY(hipMemcpyAsync(g->hb, g->maxw, nn * 4, hipMemcpyDeviceToDevice, s));
     // The per-entry head maxima pay only where the row maxima no longer stay in the caches
     // (then the filter's gather of maxw[v] misses to HBM for nearly every streamed entry).  They
@@ -1408,7 +1547,8 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
     HIP_TRY(hipStreamSynchronize(s));
     const uint32_t nbig = hf[1], nmid = hf[2];
     if (nmid) {
-        const unsigned gm = nmid < 8192u ? nmid : 8192u;
+        const uint32_t ngrp = (nmid + 3) / 4; // groups of four rows
+        const unsigned gm = ngrp < 8192u ? ngrp : 8192u;
         k_rank_mid<<<gm, 256, 0, s>>>(mid, nmid, rec0, rowp0, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
                                       g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
     }

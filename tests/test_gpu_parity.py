@@ -293,21 +293,24 @@ def test_validation_errors(tt):
         assert e.value.code == want, (s, d, w, e.value.code, want)
 
 
-def test_repeated_pair_in_long_rows(tt):
-    """A repeated pair is found in rows of every length class: vertex 0 has 300 neighbours S,
-    each of which also reaches 301 further vertices T, so 0 (lowest degree) is the tail of a
-    301-entry row and every T vertex of a 300-entry row; the repeat is put in one such row
-    (0 -> S[0], or T[0] -> S[7]), and in a 2-entry row (an extra edge 602 - 603) for contrast."""
-    S = np.arange(1, 301, dtype=np.uint32)
-    T = np.arange(301, 602, dtype=np.uint32)
-    s0, d0 = np.zeros(300, np.uint32), S
+@pytest.mark.parametrize("L", [100, 200, 300])
+def test_repeated_pair_in_long_rows(tt, L):
+    """A repeated pair is found in rows of every length class: vertex 0 has L neighbours S,
+    each of which also reaches L + 1 further vertices T, so 0 (lowest degree) is the tail of an
+    (L + 1)-entry row and every T vertex of an L-entry row; the repeat is put in one such row
+    (0 -> S[0], or T[0] -> S[7]), and in a 2-entry row (an extra edge between the last two
+    vertices) for contrast.  L = 100 and 200 give rows that one wave ranks (at most 128 and
+    256 entries), L = 300 rows that a whole block ranks."""
+    S = np.arange(1, L + 1, dtype=np.uint32)
+    T = np.arange(L + 1, 2 * L + 2, dtype=np.uint32)
+    s0, d0 = np.zeros(L, np.uint32), S
     s1, d1 = np.repeat(S, len(T)), np.tile(T, len(S))
-    base_s = np.concatenate([s0, s1, [602]]).astype(np.uint32)
-    base_d = np.concatenate([d0, d1, [603]]).astype(np.uint32)
-    n = 604
+    n = 2 * L + 4
+    base_s = np.concatenate([s0, s1, [n - 2]]).astype(np.uint32)
+    base_d = np.concatenate([d0, d1, [n - 1]]).astype(np.uint32)
     with tt.Graph(n, base_s, base_d, np.ones(len(base_s), np.uint32)) as G:
         assert G.m == len(base_s)
-    for a, b in ((0, 1), (301, 8), (603, 602)):
+    for a, b in ((0, 1), (L + 1, 8), (n - 1, n - 2)):
         s = np.concatenate([base_s, [b]]).astype(np.uint32)
         d = np.concatenate([base_d, [a]]).astype(np.uint32)
         w = np.ones(len(s), np.uint32)
