@@ -1242,6 +1242,70 @@ __global__ __launch_bounds__(256) void k_place_entries(const uint32_t *osrc, con
     }
 }
 
+// The same placement by rows, for calls that place some bins only: a row's entries of bins
+// [blo, bhi) are a run of its weight-sorted copy (weights descend along it), and a row whose
+// maximum is below bin blo has none, so only the rows that hold such entries are read (the
+// entry-order placement reads every weight and, as the placed entries are spread over the
+// whole layout, nearly every line of the other arrays).  Each thread takes PLACE_ROWS rows.
+constexpr int PLACE_ROWS = 4;
+
+__global__ __launch_bounds__(256) void k_place_row_runs(const uint64_t *rstart, const uint32_t *rlen,
+                                                        const uint32_t *maxw, uint32_t n, const uint32_t *wcol,
+                                                        const uint32_t *wwgt, const uint32_t *wpos, uint32_t blo,
+                                                        uint32_t bhi, const unsigned long long *binbase,
+                                                        unsigned long long *bincur, const uint32_t *hmx,
+                                                        uint32_t *ws_src, uint32_t *ws_col, uint32_t *ws_wgt,
+                                                        uint32_t *ws_pos, uint32_t *ws_hmx) {
+    __shared__ uint32_t lc[WBINS];
+    __shared__ unsigned long long lb[WBINS];
+    const uint32_t nb = bhi - blo;
+    for (uint32_t t = threadIdx.x; t < nb; t += blockDim.x) lc[t] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * PLACE_ROWS;
+    uint64_t P[PLACE_ROWS];
+    uint32_t j0[PLACE_ROWS], j1[PLACE_ROWS]; // the run [j0, j1) of the row's weight-sorted copy
+#pragma unroll
+    for (int it = 0; it < PLACE_ROWS; it++) {
+        const uint64_t u = base + (uint64_t)it * blockDim.x + threadIdx.x;
+        P[it] = 0;
+        j0[it] = j1[it] = 0;
+        if (u < n && weight_bin(maxw[u]) >= blo) {
+            const uint64_t b = rstart[u];
+            const uint32_t len = rlen[u];
+            uint32_t j = 0, bj = 0;
+            while (j < len && (bj = weight_bin(wwgt[b + j])) >= bhi) j++; // placed by earlier calls
+            j0[it] = j;
+            while (j < len && bj >= blo) {
+                atomicAdd(&lc[bj - blo], 1u);
+                if (++j < len) bj = weight_bin(wwgt[b + j]);
+            }
+            P[it] = b;
+            j1[it] = j;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < nb; t += blockDim.x)
+        if (lc[t]) {
+            lb[t] = binbase[blo + t] + atomicAdd(&bincur[blo + t], (unsigned long long)lc[t]);
+            lc[t] = 0;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < PLACE_ROWS; it++) {
+        const uint32_t u = (uint32_t)(base + (uint64_t)it * blockDim.x + threadIdx.x);
+        for (uint32_t j = j0[it]; j < j1[it]; j++) {
+            const uint64_t e = P[it] + j;
+            const uint32_t w = wwgt[e], bi = weight_bin(w) - blo, h = wpos[e];
+            const uint64_t d = lb[bi] + atomicAdd(&lc[bi], 1u);
+            ws_src[d] = u;
+            ws_col[d] = wcol[e];
+            ws_wgt[d] = w;
+            ws_pos[d] = h;
+            if (hmx) ws_hmx[d] = hmx[h];
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_pack_cw(const uint32_t *col, const uint32_t *wgt, uint64_t m, uint2 *cw) {
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
         cw[e] = make_uint2(col[e], wgt[e]);
@@ -1302,12 +1366,11 @@ struct Scratch {
     }
 };
 
-// Sorts the listed long rows by key K (ascending), carrying up to two u32 payloads.
+// Sorts the listed long rows by key K (ascending), carrying up to two u32 payloads, on stream s.
 template <typename K>
-int sort_big(tt_graph *g, Scratch &S, const uint64_t *rstart, const uint32_t *rlen, const uint32_t *big, uint32_t nbig,
-             K *key, uint32_t *p1, uint32_t *p2) {
+int sort_big(tt_graph *g, Scratch &S, hipStream_t s, const uint64_t *rstart, const uint32_t *rlen, const uint32_t *big,
+             uint32_t nbig, K *key, uint32_t *p1, uint32_t *p2) {
     if (!nbig) return TT_OK;
-    hipStream_t s = g->stream;
     const uint64_t m = g->m;
     K *tk = nullptr;
     uint32_t *t12 = nullptr;
@@ -1321,6 +1384,64 @@ int sort_big(tt_graph *g, Scratch &S, const uint64_t *rstart, const uint32_t *rl
     S.drop(t12);
     return TT_OK;
 }
+
+// Two more streams (default priority), for the ranking of the mid and of the long rows beside
+// that of the small rows: the three classes write disjoint rows.  The streams are made once per
+// device and kept for the process (making them for every build cost ~0.1 ms); builds that run
+// at once share them, which orders their work but keeps each build's own order.  Both wait
+// for what the build's stream has queued, and join() makes it wait for them; the destructor
+// waits for them too, so that no scratch they use is freed under them (declare it after the
+// Scratch).
+static int device_side_streams(hipStream_t &a, hipStream_t &b) {
+    static std::mutex mu;
+    static std::map<int, std::pair<hipStream_t, hipStream_t>> made;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = made.find(dev);
+    if (it == made.end()) {
+        hipStream_t x = nullptr, y = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        if (hipStreamCreateWithFlags(&y, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipStreamDestroy(x);
+            return fail(TT_E_DEVICE, "hipStreamCreateWithFlags failed");
+        }
+        it = made.emplace(dev, std::make_pair(x, y)).first;
+    }
+    a = it->second.first;
+    b = it->second.second;
+    return TT_OK;
+}
+
+struct SideStreams {
+    hipStream_t mid = nullptr, big = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    int open(hipStream_t s) {
+        int rc;
+        if ((rc = device_side_streams(mid, big))) return rc;
+        for (hipEvent_t &e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(ev[0], s));
+        HIP_TRY(hipStreamWaitEvent(mid, ev[0], 0));
+        HIP_TRY(hipStreamWaitEvent(big, ev[0], 0));
+        return TT_OK;
+    }
+    int join(hipStream_t s) {
+        HIP_TRY(hipEventRecord(ev[1], mid));
+        HIP_TRY(hipEventRecord(ev[2], big));
+        HIP_TRY(hipStreamWaitEvent(s, ev[1], 0));
+        HIP_TRY(hipStreamWaitEvent(s, ev[2], 0));
+        return TT_OK;
+    }
+    ~SideStreams() {
+        for (hipStream_t x : {mid, big})
+            if (x) (void)hipStreamSynchronize(x);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+// Graphs with at least this many edges rank the three row classes concurrently (below it the
+// streams' set-up is not repaid).
+constexpr uint64_t SIDE_STREAMS_MIN_M = 1ull << 22;
 
 // In-degrees of the oriented CSR (heads of all entries), runs merged per wave.
 __global__ __launch_bounds__(256) void k_indeg(const uint32_t *col, uint64_t m, uint32_t *indeg) {
@@ -1538,32 +1659,42 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         const uint64_t per = 256ull * PLACE_ITEMS;
         k_place_rows<<<(unsigned)(((uint64_t)n + per - 1) / per), 256, 0, s>>>(g->hb, g->rlen, n, binbase, bincur, g->rstart);
     }
-    // both row orders: counted ranks for rows up to MID_MAX entries, sorts for longer ones
-    if (m) k_rank_small<<<grid_for(m), 256, 0, s>>>(rec0, rowp0, m, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                                    g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
+    // both row orders: counted ranks for rows up to SMALL_MAX entries, LDS sorts up to MID_MAX,
+    // sorts in memory for longer ones; the three classes on three streams on large graphs
     HIP_TRY(hipMemsetAsync(flags + 1, 0, 8, s));
     if (n) k_list_long<<<grid_for(n, 4096), 256, 0, s>>>(g->rlen, n, mid, flags + 2, big, flags + 1);
     HIP_TRY(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const uint32_t nbig = hf[1], nmid = hf[2];
+    SideStreams side;
+    hipStream_t s_mid = s, s_big = s;
+    if (m >= SIDE_STREAMS_MIN_M && (nmid || nbig)) {
+        if ((rc = side.open(s))) return rc;
+        s_mid = side.mid;
+        s_big = side.big;
+    }
+    if (m) k_rank_small<<<grid_for(m), 256, 0, s>>>(rec0, rowp0, m, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
+                                                    g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
     if (nmid) {
         const uint32_t ngrp = (nmid + 3) / 4; // groups of four rows
         const unsigned gm = ngrp < 8192u ? ngrp : 8192u;
-        k_rank_mid<<<gm, 256, 0, s>>>(mid, nmid, rec0, rowp0, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
-                                      g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
+        k_rank_mid<<<gm, 256, 0, s_mid>>>(mid, nmid, rec0, rowp0, g->rstart, g->rlen, g->col, g->wgt, g->eid, g->osrc,
+                                          g->wcol, g->wwgt, g->wpos, flags, hm0, g->hmx);
     }
     if (nbig) {
         const unsigned gb = nbig < 4096u ? nbig : 4096u;
-        k_move_big<<<gb, 256, 0, s>>>(big, nbig, rowp0, g->rstart, g->rlen, rec0, g->col, g->wgt, g->eid, g->osrc);
-        if ((rc = sort_big<uint32_t>(g, S, g->rstart, g->rlen, big, nbig, g->col, g->wgt, g->eid))) return rc;
+        k_move_big<<<gb, 256, 0, s_big>>>(big, nbig, rowp0, g->rstart, g->rlen, rec0, g->col, g->wgt, g->eid, g->osrc);
+        if ((rc = sort_big<uint32_t>(g, S, s_big, g->rstart, g->rlen, big, nbig, g->col, g->wgt, g->eid))) return rc;
         uint64_t *wkey = nullptr;
         if ((rc = S.get((void **)&wkey, (m + 1) * 8))) return rc;
-        k_post_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, g->col, g->wgt, wkey, g->wpos, flags, g->maxw,
-                                      g->hmx);
-        if ((rc = sort_big<uint64_t>(g, S, g->rstart, g->rlen, big, nbig, wkey, g->wpos, nullptr))) return rc;
-        k_split_big<<<gb, 256, 0, s>>>(big, nbig, g->rstart, g->rlen, wkey, g->wcol, g->wwgt);
+        k_post_big<<<gb, 256, 0, s_big>>>(big, nbig, g->rstart, g->rlen, g->col, g->wgt, wkey, g->wpos, flags, g->maxw,
+                                          g->hmx);
+        if ((rc = sort_big<uint64_t>(g, S, s_big, g->rstart, g->rlen, big, nbig, wkey, g->wpos, nullptr))) return rc;
+        k_split_big<<<gb, 256, 0, s_big>>>(big, nbig, g->rstart, g->rlen, wkey, g->wcol, g->wwgt);
+        HIP_TRY(hipStreamSynchronize(s_big)); // wkey is dropped below
         S.drop(wkey);
     }
+    if (side.mid && (rc = side.join(s))) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     S.drop(rec0);
     g->whist.assign(WBINS, 0);
@@ -1667,11 +1798,16 @@ int ensure_weight_stream(tt_graph *g, hipStream_t s, uint32_t bin) {
     unsigned long long *bincur = nullptr;
     if ((rc = S.get((void **)&bincur, WBINS * 8))) return rc;
     HIP_TRY(hipMemsetAsync(bincur, 0, WBINS * 8, s));
-    if (m) {
+    if (m && m <= ws_all_at_once()) {
         const uint64_t per = 256ull * PLACE_ITEMS;
         k_place_entries<<<(unsigned)((m + per - 1) / per), 256, 0, s>>>(g->osrc, g->col, g->wgt, m, lo, have, g->ws_base,
                                                                         bincur, g->hmx, g->ws_src, g->ws_col,
                                                                         g->ws_wgt, g->ws_pos, g->ws_hmx);
+    } else if (m) {
+        const uint64_t per = 256ull * PLACE_ROWS;
+        k_place_row_runs<<<(unsigned)(((uint64_t)g->n + per - 1) / per), 256, 0, s>>>(
+            g->rstart, g->rlen, g->maxw, g->n, g->wcol, g->wwgt, g->wpos, lo, have, g->ws_base, bincur, g->hmx,
+            g->ws_src, g->ws_col, g->ws_wgt, g->ws_pos, g->ws_hmx);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s)); // complete before other streams may see it
