@@ -304,6 +304,11 @@ struct PartGeom {
 // Partition blocks of 512 threads: their LDS (one counter per bucket) allows 4-5 blocks per
 // CU, and the grid has at most 1,024 blocks, so the block size sets the waves in flight.
 constexpr int PART_THREADS = 512;
+// The scatter of the 16-byte records takes blocks twice as long, of twice the threads: half as
+// many (bucket, block) ranges are written at once, so more of their partly written lines are
+// combined before they leave the caches (49 -> 41 ms on the 2B-edge graph; the counting and
+// endpoint passes are slower with the longer blocks, so they keep theirs).
+constexpr int REC_THREADS = 1024;
 // Bucket blocks (one per bucket, 64 KB of LDS per array of per-vertex counters) of 1,024 threads.
 constexpr int BUCKET_THREADS = 1024;
 // Items per thread and loop trip in the partition passes: their loads are issued together
@@ -414,9 +419,22 @@ __global__ __launch_bounds__(PART_THREADS) void k_part_count_tails(const uint32_
     for (uint32_t b = threadIdx.x; b < G.nbk; b += blockDim.x) M[(uint64_t)b * G.nblk + blockIdx.x] = h[b];
 }
 
+// Counts per (bucket, record-scatter block) from those per (bucket, orientation block): scatter
+// block k covers orientation blocks 2k and 2k + 1.
+__global__ __launch_bounds__(256) void k_pair_blocks(const uint32_t *Mf, uint32_t nbk, uint32_t nf, uint32_t nc,
+                                                     uint32_t *Mc) {
+    const uint64_t total = (uint64_t)nbk * nc;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = i / nc;
+        const uint32_t k = (uint32_t)(i - b * nc);
+        const uint64_t f = b * nf + 2ull * k;
+        Mc[i] = Mf[f] + (2 * k + 1 < nf ? Mf[f + 1] : 0u);
+    }
+}
+
 // Every edge as a 16-byte record (head, weight, edge, tail) into tail-bucket order.
 template <typename C>
-__global__ __launch_bounds__(PART_THREADS) void k_part_edges(const uint32_t *src, const uint32_t *dst, const uint32_t *w,
+__global__ __launch_bounds__(REC_THREADS) void k_part_edges(const uint32_t *src, const uint32_t *dst, const uint32_t *w,
                                                              uint64_t m, PartGeom G, const uint32_t *etail,
                                                              const uint64_t *off, uint4 *part) {
     __shared__ C cur[PART_MAX_BUCKETS];
@@ -1607,11 +1625,18 @@ static int build_csr(tt_graph *g, const uint32_t *src, const uint32_t *dst, cons
         k_bucket_degree<<<PE.nbk, BUCKET_THREADS, 0, s>>>((const uint32_t *)grouped, off, 2 * m, PE, n, g->deg);
         // records in one level (a second level measured no faster for the 16-byte records).
         // The weight-sorted head array holds each edge's tail until the row ranking fills it.
+        // The scatter's blocks (PR) are pairs of the orientation pass's (PG).
+        PartGeom PR = PG;
+        PR.per = 2 * PG.per;
+        PR.nblk = (uint32_t)((m + PR.per - 1) / PR.per);
+        uint32_t *Mr = nullptr;
+        if ((rc = S.get((void **)&Mr, (uint64_t)PR.nbk * PR.nblk * 4))) return rc;
         k_part_count_tails<<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, m, PG, g->deg, g->wcol, M);
-        if ((rc = exclusive_scan_u32_to_u64(M, off, (uint64_t)PG.nbk * PG.nblk, s, nullptr, scan_tmp))) return rc;
-        if (m < (1ull << 32)) k_part_edges<uint32_t><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
-        else k_part_edges<unsigned long long><<<PG.nblk, PART_THREADS, 0, s>>>(src, dst, w, m, PG, g->wcol, off, (uint4 *)grouped);
-        k_bucket_rows<<<PG.nbk, BUCKET_THREADS, 0, s>>>((const uint4 *)grouped, off, m, PG, n, g->rlen, g->maxw, rowp0,
+        k_pair_blocks<<<grid_for((uint64_t)PR.nbk * PR.nblk), 256, 0, s>>>(M, PG.nbk, PG.nblk, PR.nblk, Mr);
+        if ((rc = exclusive_scan_u32_to_u64(Mr, off, (uint64_t)PR.nbk * PR.nblk, s, nullptr, scan_tmp))) return rc;
+        if (m < (1ull << 32)) k_part_edges<uint32_t><<<PR.nblk, REC_THREADS, 0, s>>>(src, dst, w, m, PR, g->wcol, off, (uint4 *)grouped);
+        else k_part_edges<unsigned long long><<<PR.nblk, REC_THREADS, 0, s>>>(src, dst, w, m, PR, g->wcol, off, (uint4 *)grouped);
+        k_bucket_rows<<<PR.nbk, BUCKET_THREADS, 0, s>>>((const uint4 *)grouped, off, m, PR, n, g->rlen, g->maxw, rowp0,
                                                          rec0);
         HIP_TRY(hipGetLastError());
     } else {
