@@ -1776,8 +1776,8 @@ int ensure_opos(tt_graph *g, hipStream_t s) {
 // entries each call places the bins from the requested one up to those already placed,
 // extended down until the placed prefix holds WS_GROW times the requested one and at least
 // m / WS_MIN_FRAC entries, so that a descending sequence of bands costs a few calls).  Each
-// call reads every entry's weight once and writes only the new bins.
-constexpr uint64_t WS_GROW = 16, WS_MIN_FRAC = 64;
+// call writes only the new bins; it reads every row maximum and the rows that hold new bins.
+constexpr uint64_t WS_GROW = 4, WS_MIN_FRAC = 1024;
 // Up to this many entries one call places every bin: a call costs about a pass over all the
 // weights whatever it writes (the 20M-entry graph: 0.22 ms for a partial placement, 0.37 ms for
 // all of it), while on larger graphs the writes dominate (2B entries: all bins ~54 ms).  The
