@@ -1503,7 +1503,8 @@ __global__ __launch_bounds__(256) void k_pack_vinfo(const uint64_t *rstart, cons
 // ----------------------------------------------------------------------------- build
 // Buckets of 2^rb vertices, rb in [6, 14], at least ~2,048 buckets where n allows (bucket
 // blocks fill the device); partition blocks of >= 8,192 edges, at most 1,024 of them (fewer,
-// larger blocks measured slower: the passes are bound by latency, not by the run lengths).
+// larger blocks measured slower for the counting and endpoint passes; the record scatter takes
+// them in pairs, see REC_THREADS).
 PartGeom part_geometry(uint32_t n, uint64_t m) {
     PartGeom G;
     uint32_t rb = 6;
